@@ -1,0 +1,216 @@
+/*
+ * lrbg.h -- batched low-rank GEMM on AMD Instinct MI355X (gfx950), C ABI.
+ *
+ * The products are those of a low-rank matrix multiplication (Deshmukh,
+ * Yokota, Bosilca, arXiv 2311.07602): a low-rank block is a tuple
+ * (U, S, V) with A ~ U S V^T (Sec. 2, dense-to-low-rank equation), and the
+ * low-rank product of Alg. 1 starts with the rank-sized inner product of two
+ * skinny bases; the batched form takes per-instance arrays of operands
+ * (Alg. 2, Alg. 3).  Three product kinds are exposed:
+ *
+ *   LRBG_OP_DENSE_TS  C = A * U          A m x k, U k x n, C m x n
+ *                     (dense block times a tall-skinny basis: m = k = b,
+ *                      n = r; the skinny products of Sec. 3 and the BLR
+ *                      matrix times multiple right-hand sides of Sec. 7)
+ *   LRBG_OP_INNER     T = V1^T * U2      V1 k x m, U2 k x n, T m x n
+ *                     (Alg. 1 step 1, C_temp = A_{V^T} B_U; the loop-4
+ *                      accumulation C_MN of Alg. 2; k = b, m, n = ranks)
+ *   LRBG_OP_RECOMP    W = U1 * (S * V2^T) U1 m x k, S k x k, V2 n x k, W m x n
+ *                     (rebuild a block from the rank x rank core of a
+ *                      low-rank product, the small-core-times-skinny role of
+ *                      Alg. 1 steps 2-3; k = r, m = n = b)
+ *
+ * Conventions for every entry point:
+ *   - All matrices are column-major: element (i, j) of X is at
+ *     X[i + j * ldX], with ldX >= max(1, rows).  V matrices are stored
+ *     b x r, so V^T is implied by the operation, never materialised.
+ *   - The output is overwritten (beta = 0): Alg. 2 accumulates G with "+="
+ *     but G is defined as the result of the product (Alg. 1).  k = 0 yields
+ *     a zero-filled output; m = 0 or n = 0 makes an instance a no-op.
+ *   - Precisions: LRBG_FP64 takes and returns IEEE binary64.  LRBG_BF16X3
+ *     (DENSE_TS and INNER only) takes FP32 operands (A/U or V1/U2 are
+ *     float *), splits each value into three bfloat16 terms, multiplies the
+ *     six term pairs of order <= 2 on the bf16 matrix cores with FP32
+ *     accumulation and returns the output in FP64 (double *).  RECOMP is
+ *     FP64 only (LRBG_EUNSUPPORTED otherwise).
+ *   - Limits: rank-type dimensions (DENSE_TS n; INNER m, n; RECOMP k) at
+ *     most 128; block-type dimensions at most 65536; violating either is
+ *     LRBG_EUNSUPPORTED.
+ *   - Pointers named "device" are device (HBM) addresses on the current HIP
+ *     device, naturally aligned (8 bytes for FP64, 4 for FP32).  Host arrays
+ *     (sizes, leading dimensions, pointer arrays, descriptor arrays) are read
+ *     during the call only.  The caller owns every buffer; the library never
+ *     frees caller memory.  A buffer may be NULL only if it has no elements.
+ *   - Outputs must not overlap each other or any input of the same call,
+ *     except through a dependency that a plan or grouped call orders (an
+ *     input that is exactly another product's output, see lrbg_grouped).
+ *   - Calls are asynchronous on `stream` (a hipStream_t; NULL is the null
+ *     stream).  Every argument is validated before anything is launched; an
+ *     invalid call launches nothing and returns a status code.  Launch
+ *     failures return LRBG_EDEVICE; faults inside kernels surface at the
+ *     caller's next synchronisation.  lrbg_last_error() gives a thread-local
+ *     text for the last failure.
+ *   - Results are deterministic: the same inputs and tile configuration give
+ *     the same bits, whatever else runs in the same launch.
+ */
+#ifndef LRBG_H
+#define LRBG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lrbg_status {
+    LRBG_OK = 0,
+    LRBG_EINVAL = 1,        /* malformed argument (null, negative, ld, alias) */
+    LRBG_EUNSUPPORTED = 2,  /* outside the supported op / precision / size set */
+    LRBG_ENOMEM = 3,        /* a host or device allocation failed */
+    LRBG_EDEVICE = 4,       /* a HIP call or kernel launch failed */
+    LRBG_EBUDGET = 5        /* a request does not fit the memory budget */
+} lrbg_status;
+
+typedef enum lrbg_op {
+    LRBG_OP_DENSE_TS = 0,
+    LRBG_OP_INNER = 1,
+    LRBG_OP_RECOMP = 2
+} lrbg_op;
+
+typedef enum lrbg_prec {
+    LRBG_FP64 = 0,
+    LRBG_BF16X3 = 1
+} lrbg_prec;
+
+/* One product of a grouped call.  a/b/c are device pointers whose element
+ * type follows `prec` (see above); s is the RECOMP core (device, FP64,
+ * k x k, lds >= k), NULL for the other ops.  `flags` is reserved (0). */
+typedef struct lrbg_desc {
+    int32_t op, prec;
+    int32_t m, n, k;
+    int32_t lda, ldb, lds, ldc;
+    int32_t flags;
+    const void *a;
+    const void *b;
+    const double *s;
+    void *c;
+} lrbg_desc;
+
+/*
+ * lr_batched_gemm -- `count` independent products of one kind and precision.
+ *   op, prec      : lrbg_op, lrbg_prec.
+ *   m, n, k       : host arrays [count] of sizes, meaning per op above.
+ *   A, lda        : host arrays [count]: device pointer of the first operand
+ *                   (A | V1 | U1) and its leading dimension.
+ *   B, ldb        : second operand (U | U2 | V2).
+ *   S, lds        : RECOMP core pointers and leading dimensions; NULL for the
+ *                   other ops.
+ *   C, ldc        : output (C | T | W).
+ *   stream        : hipStream_t.
+ * The batched problem statement is Alg. 2's per-instance operand arrays.
+ */
+lrbg_status lr_batched_gemm(int32_t op, int32_t prec, int64_t count,
+                            const int32_t *m, const int32_t *n, const int32_t *k,
+                            const void *const *A, const int32_t *lda,
+                            const void *const *B, const int32_t *ldb,
+                            const double *const *S, const int32_t *lds,
+                            void *const *C, const int32_t *ldc,
+                            void *stream);
+
+/*
+ * lrbg_grouped -- one launch sequence over `count` heterogeneous products
+ * (any mix of ops, precisions, sizes).  Products whose input is exactly the
+ * output buffer of another product of the same call (e.g. a RECOMP whose
+ * core S is an INNER's T: the low-rank x low-rank chain) run after it; all
+ * others run together in one grouped launch.  Same semantics as
+ * lr_batched_gemm otherwise.
+ */
+lrbg_status lrbg_grouped(const lrbg_desc *descs, int64_t count, void *stream);
+
+/* ------------------------------------------------------------ plans ---- */
+
+typedef struct lrbg_plan lrbg_plan;
+
+/* Plan flags. */
+#define LRBG_PLAN_PERSISTENT 0x1u  /* persistent workgroups pulling tiles from
+                                      per-XCD queues (default: one workgroup
+                                      per tile, hardware-dispatched) */
+#define LRBG_PLAN_NO_GRAPH   0x2u  /* replay by direct launches instead of a
+                                      captured hipGraph */
+#define LRBG_PLAN_SCHED_MIX  0x4u  /* interleave compute-bound and memory-bound
+                                      tiles instead of longest-first order */
+
+typedef struct lrbg_plan_stats {
+    int64_t products;     /* descriptors in the plan */
+    int64_t tiles;        /* workgroup tiles over all levels */
+    int32_t levels;       /* dependent launch levels (1 unless chained) */
+    int32_t grid;         /* workgroups of the largest level's launch */
+    double useful_flops;  /* 2 flops per multiply-add, no padding */
+    double hbm_bytes;     /* compulsory: each operand read once, output written once */
+} lrbg_plan_stats;
+
+/*
+ * lrbg_plan_create -- validate `count` descriptors, pick a tile variant per
+ * (op, prec, b, r) bucket (from `tune_cache`, a file written by
+ * lrbg_autotune, or built-in defaults when NULL or absent), build the
+ * XCD-aware tile schedule, upload it to the device and capture the launch
+ * sequence in a hipGraph.  The plan keeps the device pointers; the caller's
+ * buffers must stay valid while the plan is executed.  On success *out owns
+ * device memory until lrbg_plan_destroy.
+ */
+lrbg_status lrbg_plan_create(lrbg_plan **out, const lrbg_desc *descs, int64_t count,
+                             const char *tune_cache, uint32_t flags);
+
+/* Replay the plan on `stream` (hipGraphLaunch; no host work per tile). */
+lrbg_status lrbg_plan_execute(lrbg_plan *plan, void *stream);
+
+/* Free the plan's device memory and graph.  Waits for the plan's work to
+ * finish first.  NULL is a no-op. */
+lrbg_status lrbg_plan_destroy(lrbg_plan *plan);
+
+lrbg_status lrbg_plan_get_stats(const lrbg_plan *plan, lrbg_plan_stats *out);
+
+/*
+ * lrbg_plan_last_kernel_ms -- device time of the plan's most recent
+ * execution, measured with HIP events recorded on the execution stream
+ * around the grouped kernel(s) (only when the plan was created with
+ * LRBG_PLAN_NO_GRAPH; otherwise around the graph launch).  Returns a
+ * negative value if no execution has completed.
+ */
+double lrbg_plan_last_ms(lrbg_plan *plan);
+
+/*
+ * lrbg_schedule_stats -- validate `count` descriptors and build the tile
+ * schedule exactly as lrbg_plan_create would, on the host only (no device
+ * memory, no launch), and report its statistics.  Lets callers (and tests)
+ * check sizes, levels and the work accounting without a GPU.
+ */
+lrbg_status lrbg_schedule_stats(const lrbg_desc *descs, int64_t count, const char *tune_cache,
+                                uint32_t flags, lrbg_plan_stats *out);
+
+/* ---------------------------------------------------------- tuning ---- */
+
+/*
+ * lrbg_autotune -- for every (op, prec, b, r) bucket present in `sample`,
+ * time each candidate tile variant on the sample's own buffers (outputs are
+ * overwritten) and write the fastest to `cache_out` (text, one bucket per
+ * line).  `reps` timed repetitions per candidate (>= 1).  Synchronous.
+ */
+lrbg_status lrbg_autotune(const lrbg_desc *sample, int64_t count,
+                          const char *cache_out, int32_t reps);
+
+/* Number of tile variants compiled in, and the name of one (for tooling). */
+int32_t lrbg_variant_count(void);
+const char *lrbg_variant_name(int32_t v);
+
+/* ----------------------------------------------------------- misc ---- */
+
+const char *lrbg_status_string(lrbg_status s);
+const char *lrbg_last_error(void);   /* thread-local detail of the last failure */
+int32_t lrbg_version(void);           /* major*10000 + minor*100 + patch */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LRBG_H */

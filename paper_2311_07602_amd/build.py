@@ -1,0 +1,55 @@
+"""Build ``liblrbg.so`` (the C-ABI library) with hipcc for gfx950.
+
+Always recompiles.  Packed-FP32 instructions are disabled in the device code
+generator.  The library depends on the HIP runtime by its SONAME
+(libamdhip64.so.7), so in a process that has already loaded PyTorch's bundled
+copy of the runtime (same SONAME) it binds to that one; standalone it
+resolves through its RUNPATH to ROCm's runtime.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "liblrbg.so")
+BUILD = os.path.join(ROOT, "_build")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+HIPCC = os.environ.get("HIPCC", os.path.join(ROCM, "bin", "hipcc"))
+
+COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-I", os.path.join(ROOT, "include")]
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    msgs = [ln for ln in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in ln and ln.strip()]
+    if r.returncode != 0:
+        raise RuntimeError("build step failed:\n" + " ".join(cmd) + "\n" + "\n".join(msgs))
+    if verbose and msgs:
+        print("\n".join(msgs))
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    objs = []
+    for src in ("lrbg_kernels.hip", "lrbg_host.cpp"):
+        obj = os.path.join(BUILD, src.rsplit(".", 1)[0] + ".o")
+        lang = ["-x", "hip"] if src.endswith(".hip") else []
+        _run([HIPCC, *COMMON, *lang, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        objs.append(obj)
+    tmp = LIB + ".tmp"
+    link_rt = ["-L", os.path.join(ROCM, "lib"), "-lamdhip64"]
+    clang = os.path.join(ROCM, "llvm", "bin", "clang++")
+    _run([clang, "-shared", "-fPIC", *objs, "-o", tmp, *link_rt,
+          "-Wl,-rpath," + os.path.join(ROCM, "lib"), "-Wl,--no-undefined", "-lstdc++", "-lm"], verbose)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)

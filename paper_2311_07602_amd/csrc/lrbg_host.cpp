@@ -1,0 +1,942 @@
+// Host side of the lrbg C ABI (include/lrbg.h): argument validation,
+// per-bucket tile-variant choice, the XCD-aware tile schedule, dependency
+// levels for chained products, plans captured in hipGraphs, and the
+// autotuner.  Every step of the products themselves runs in the HIP kernels
+// of lrbg_kernels.hip; nothing here computes on matrix data.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/lrbg.h"
+#include "lrbg_internal.h"
+
+namespace lrbg {
+
+// ------------------------------------------------------------- errors
+
+static thread_local std::string g_last_error;
+
+static lrbg_status fail(lrbg_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                               \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess) return fail(LRBG_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+// ------------------------------------------------------------- variants
+
+static const VariantInfo kVariants[kNumVariants] = {
+    {K_NOP, 0, 0, 0, 0},
+#define LRBG_INFO(id, kind, p1, p2, p3, p4) {kind, p1, p2, p3, p4},
+    LRBG_VARIANTS(LRBG_INFO)
+#undef LRBG_INFO
+};
+
+static std::string variant_name(int v)
+{
+    if (v <= 0 || v >= kNumVariants) return "nop";
+    const VariantInfo &vi = kVariants[v];
+    char buf[64];
+    switch (vi.kind) {
+    case K_DTS64: snprintf(buf, sizeof buf, "dts64_rm%d_rn%d_kg%d", vi.p1, vi.p2, vi.p3); break;
+    case K_INN64: snprintf(buf, sizeof buf, "inn64_ri%d_rj%d_ks%d_kg%d", vi.p1, vi.p2, vi.p3, vi.p4); break;
+    case K_REC64: snprintf(buf, sizeof buf, "rec64_rm%d_bn%d_kg%d", vi.p1, vi.p2, vi.p3); break;
+    case K_DTS3: snprintf(buf, sizeof buf, "dts3_rm%d_rn%d", vi.p1, vi.p2); break;
+    case K_INN3: snprintf(buf, sizeof buf, "inn3_ri%d_rj%d_ks%d", vi.p1, vi.p2, vi.p3); break;
+    default: snprintf(buf, sizeof buf, "v%d", v);
+    }
+    return buf;
+}
+
+static int kind_of(int op, int prec)
+{
+    if (prec == LRBG_FP64) {
+        if (op == LRBG_OP_DENSE_TS) return K_DTS64;
+        if (op == LRBG_OP_INNER) return K_INN64;
+        if (op == LRBG_OP_RECOMP) return K_REC64;
+    } else if (prec == LRBG_BF16X3) {
+        if (op == LRBG_OP_DENSE_TS) return K_DTS3;
+        if (op == LRBG_OP_INNER) return K_INN3;
+    }
+    return K_NOP;
+}
+
+// Can variant v compute this product?  (Rank-type limits of the tile.)
+static bool variant_fits(int v, const lrbg_desc &d)
+{
+    if (v <= 0 || v >= kNumVariants) return false;
+    const VariantInfo &vi = kVariants[v];
+    if (vi.kind != kind_of(d.op, d.prec)) return false;
+    switch (vi.kind) {
+    case K_DTS64: return d.n <= 16 * vi.p2;
+    case K_DTS3: return d.n <= 16 * vi.p2;
+    case K_INN64: return d.n <= 16 * vi.p2;
+    case K_INN3: return d.n <= 16 * vi.p2;
+    case K_REC64: {
+        const int kp = (d.k + 15) / 16 * 16;
+        return (size_t)kp * 16 * vi.p2 * 8 <= (size_t)kLdsBytes;
+    }
+    }
+    return false;
+}
+
+// Tiles of product d under variant v; p0 of each tile appended to out.
+static void tiles_of(int v, const lrbg_desc &d, std::vector<int32_t> &p0s)
+{
+    const VariantInfo &vi = kVariants[v];
+    int step = 0, extent = 0;
+    switch (vi.kind) {
+    case K_DTS64: case K_DTS3: step = 64 * vi.p1; extent = d.m; break;
+    case K_INN64: case K_INN3: step = 16 * vi.p1 * (4 / vi.p3); extent = d.m; break;
+    case K_REC64: step = 16 * vi.p2; extent = d.n; break;
+    default: return;
+    }
+    for (int p = 0; p < extent; p += step) p0s.push_back(p);
+}
+
+// (b, r) of a product: block-type and rank-type dimension.
+static void bucket_dims(const lrbg_desc &d, int &b, int &r)
+{
+    switch (d.op) {
+    case LRBG_OP_DENSE_TS: b = std::max(d.m, d.k); r = d.n; break;
+    case LRBG_OP_INNER: b = d.k; r = std::max(d.m, d.n); break;
+    default: b = std::max(d.m, d.n); r = d.k; break;
+    }
+}
+
+static int round_bucket(int x, int lo)
+{
+    int v = lo;
+    while (v < x) v *= 2;
+    return v;
+}
+
+typedef std::tuple<int, int, int, int> BucketKey;   // op, prec, b, r (rounded)
+
+static BucketKey bucket_of(const lrbg_desc &d)
+{
+    int b, r;
+    bucket_dims(d, b, r);
+    return BucketKey(d.op, d.prec, round_bucket(b, 64), round_bucket(r, 8));
+}
+
+// Built-in choice per bucket (overridden by a tuning cache).
+static int default_variant(const lrbg_desc &d)
+{
+    int b, r;
+    bucket_dims(d, b, r);
+    const int kind = kind_of(d.op, d.prec);
+    auto pick = [&](std::initializer_list<int> cands) {
+        for (int v : cands)
+            if (variant_fits(v, d)) return v;
+        return 0;
+    };
+    if (kind == K_DTS64) {
+        if (d.n <= 16) return pick({d.m >= 256 ? 3 : (d.m >= 128 ? 2 : 1)});
+        if (d.n <= 32) return pick({d.m >= 128 ? 5 : 4});
+        if (d.n <= 64) return pick({d.m >= 128 ? 7 : 6});
+        return pick({d.m >= 128 ? 9 : 8});
+    }
+    if (kind == K_INN64) {
+        const int rr = std::max(d.m, d.n);
+        if (rr <= 16) return pick({10});
+        if (rr <= 32) return pick({11});
+        if (rr <= 64) return pick({13});
+        return pick({15, 16});
+    }
+    if (kind == K_REC64) {
+        if (d.k <= 16) return pick({17});
+        if (d.k <= 32) return pick({18});
+        if (d.k <= 64) return pick({18, 20});
+        return pick({20});
+    }
+    (void)b;
+    (void)r;
+    return 0;
+}
+
+// ------------------------------------------------------------- validation
+
+static size_t elem_size(int prec) { return prec == LRBG_BF16X3 ? 4 : 8; }
+
+struct Range {
+    uintptr_t lo, hi;   // [lo, hi) in bytes
+    int64_t idx;
+};
+
+static Range span(const void *p, int rows, int cols, int ld, size_t es, int64_t idx)
+{
+    if (!p || rows <= 0 || cols <= 0) return Range{0, 0, idx};
+    uintptr_t lo = (uintptr_t)p;
+    uintptr_t hi = lo + ((size_t)(cols - 1) * (size_t)ld + (size_t)rows) * es;
+    return Range{lo, hi, idx};
+}
+
+static bool overlaps(const Range &a, const Range &b) { return a.lo < b.hi && b.lo < a.hi && a.hi > a.lo && b.hi > b.lo; }
+
+// Operand shapes (rows, cols) of a product: a, b, s, c.
+static void shapes(const lrbg_desc &d, int sh[4][2])
+{
+    switch (d.op) {
+    case LRBG_OP_DENSE_TS:
+        sh[0][0] = d.m; sh[0][1] = d.k; sh[1][0] = d.k; sh[1][1] = d.n; sh[2][0] = 0; sh[2][1] = 0;
+        break;
+    case LRBG_OP_INNER:
+        sh[0][0] = d.k; sh[0][1] = d.m; sh[1][0] = d.k; sh[1][1] = d.n; sh[2][0] = 0; sh[2][1] = 0;
+        break;
+    default:
+        sh[0][0] = d.m; sh[0][1] = d.k; sh[1][0] = d.n; sh[1][1] = d.k; sh[2][0] = d.k; sh[2][1] = d.k;
+        break;
+    }
+    sh[3][0] = d.m;
+    sh[3][1] = d.n;
+}
+
+static lrbg_status validate_one(const lrbg_desc &d, int64_t i)
+{
+    if (d.op < 0 || d.op > 2) return fail(LRBG_EINVAL, "product %lld: bad op %d", (long long)i, d.op);
+    if (d.prec != LRBG_FP64 && d.prec != LRBG_BF16X3)
+        return fail(LRBG_EINVAL, "product %lld: bad precision %d", (long long)i, d.prec);
+    if (d.m < 0 || d.n < 0 || d.k < 0)
+        return fail(LRBG_EINVAL, "product %lld: negative size (m=%d n=%d k=%d)", (long long)i, d.m, d.n, d.k);
+    if (d.flags != 0) return fail(LRBG_EINVAL, "product %lld: flags must be 0", (long long)i);
+    if (kind_of(d.op, d.prec) == K_NOP)
+        return fail(LRBG_EUNSUPPORTED, "product %lld: op %d has no bf16x3 form (recompression stays FP64)",
+                    (long long)i, d.op);
+    if (d.prec == LRBG_BF16X3) return fail(LRBG_EUNSUPPORTED, "product %lld: bf16x3 kernels not built", (long long)i);
+    int b, r;
+    bucket_dims(d, b, r);
+    const int rankdims[3][2] = {{d.n, 0}, {d.m, d.n}, {d.k, 0}};
+    for (int t = 0; t < 2; ++t)
+        if (rankdims[d.op][t] > kMaxRank)
+            return fail(LRBG_EUNSUPPORTED, "product %lld: rank dimension %d exceeds %d", (long long)i,
+                        rankdims[d.op][t], kMaxRank);
+    if (b > kMaxBlock)
+        return fail(LRBG_EUNSUPPORTED, "product %lld: block dimension %d exceeds %d", (long long)i, b, kMaxBlock);
+    int sh[4][2];
+    shapes(d, sh);
+    const void *ptr[4] = {d.a, d.b, d.s, d.c};
+    const int ld[4] = {d.lda, d.ldb, d.lds, d.ldc};
+    const char *nm[4] = {"a", "b", "s", "c"};
+    const size_t es[4] = {elem_size(d.prec), elem_size(d.prec), 8, 8};
+    for (int t = 0; t < 4; ++t) {
+        if (t == 2 && d.op != LRBG_OP_RECOMP) continue;
+        const int rows = sh[t][0], cols = sh[t][1];
+        if (ld[t] < std::max(1, rows))
+            return fail(LRBG_EINVAL, "product %lld: ld%s=%d < rows=%d", (long long)i, nm[t], ld[t], rows);
+        if (rows > 0 && cols > 0) {
+            if (!ptr[t]) return fail(LRBG_EINVAL, "product %lld: %s is NULL", (long long)i, nm[t]);
+            if ((uintptr_t)ptr[t] % es[t])
+                return fail(LRBG_EINVAL, "product %lld: %s not %zu-byte aligned", (long long)i, nm[t], es[t]);
+        }
+    }
+    const Range out = span(d.c, sh[3][0], sh[3][1], d.ldc, 8, i);
+    for (int t = 0; t < 3; ++t) {
+        if (t == 2 && d.op != LRBG_OP_RECOMP) continue;
+        if (overlaps(out, span(ptr[t], sh[t][0], sh[t][1], ld[t], es[t], i)))
+            return fail(LRBG_EINVAL, "product %lld: output overlaps input %s", (long long)i, nm[t]);
+    }
+    return LRBG_OK;
+}
+
+// ------------------------------------------------------------- tuning cache
+
+struct TuneTable {
+    std::map<BucketKey, int> choice;
+};
+
+static int variant_by_name(const std::string &nm)
+{
+    for (int v = 1; v < kNumVariants; ++v)
+        if (variant_name(v) == nm) return v;
+    return 0;
+}
+
+static void load_tune_cache(const char *path, TuneTable &tt)
+{
+    if (!path || !*path) return;
+    std::ifstream f(path);
+    if (!f) return;
+    std::string line;
+    while (std::getline(f, line)) {
+        if (line.empty() || line[0] == '#') continue;
+        std::istringstream is(line);
+        int op, prec, b, r;
+        std::string nm;
+        if (!(is >> op >> prec >> b >> r >> nm)) continue;
+        const int v = variant_by_name(nm);
+        if (v) tt.choice[BucketKey(op, prec, b, r)] = v;
+    }
+}
+
+// ------------------------------------------------------------- cost model
+
+// Useful flops and compulsory bytes of one product (2 flops per multiply-add;
+// each operand read once, the output written once).
+static void work_of(const lrbg_desc &d, double &flops, double &bytes)
+{
+    const double m = d.m, n = d.n, k = d.k, es = (double)elem_size(d.prec);
+    switch (d.op) {
+    case LRBG_OP_DENSE_TS:
+        flops = 2.0 * m * n * k;
+        bytes = es * (m * k + k * n) + 8.0 * m * n;
+        break;
+    case LRBG_OP_INNER:
+        flops = 2.0 * m * n * k;
+        bytes = es * (k * m + k * n) + 8.0 * m * n;
+        break;
+    default:
+        flops = 2.0 * m * n * k + 2.0 * k * k * n;
+        bytes = 8.0 * (m * k + n * k + k * k + m * n);
+        break;
+    }
+    if (d.m == 0 || d.n == 0) flops = bytes = 0.0;
+}
+
+// Relative time estimate of a product on the whole chip (seconds).
+static double est_time(const lrbg_desc &d)
+{
+    double f, b;
+    work_of(d, f, b);
+    return std::max(f / 70e12, b / 5.5e12) + 2e-9;
+}
+
+static bool compute_bound(const lrbg_desc &d)
+{
+    double f, b;
+    work_of(d, f, b);
+    return f / 70e12 > b / 5.5e12;
+}
+
+// ------------------------------------------------------------- plans
+
+struct Level {
+    int64_t tile_off = 0;   // into the plan's tile array
+    int32_t ntiles = 0;     // grid of the one-workgroup-per-tile launch
+    int32_t qinfo_off = 0;  // 9 queue offsets (persistent mode)
+    int32_t grid = 0;
+};
+
+}  // namespace lrbg
+
+struct lrbg_plan {
+    uint32_t flags = 0;
+    int device = 0;
+    lrbg::DevDesc *d_descs = nullptr;
+    lrbg::Tile *d_tiles = nullptr;
+    int32_t *d_qinfo = nullptr;
+    int32_t *d_counters = nullptr;
+    std::vector<lrbg::Level> levels;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+    lrbg_plan_stats stats{};
+};
+
+namespace lrbg {
+
+struct Schedule {
+    std::vector<DevDesc> descs;
+    std::vector<Tile> tiles;      // all levels, each laid out for its launch
+    std::vector<int32_t> qinfo;   // 9 per level
+    std::vector<Level> levels;
+    lrbg_plan_stats stats{};
+};
+
+// Dependency level of every product: a product reading (a, b or s) memory
+// written by another product runs one level after it.
+static lrbg_status compute_levels(const lrbg_desc *ds, int64_t n, std::vector<int> &level)
+{
+    level.assign((size_t)n, 0);
+    std::vector<Range> outs;
+    outs.reserve((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        int sh[4][2];
+        shapes(ds[i], sh);
+        Range r = span(ds[i].c, sh[3][0], sh[3][1], ds[i].ldc, 8, i);
+        if (r.hi > r.lo) outs.push_back(r);
+    }
+    std::sort(outs.begin(), outs.end(), [](const Range &x, const Range &y) { return x.lo < y.lo; });
+    for (size_t t = 1; t < outs.size(); ++t)
+        if (outs[t].lo < outs[t - 1].hi)
+            return fail(LRBG_EINVAL, "outputs of products %lld and %lld overlap", (long long)outs[t - 1].idx,
+                        (long long)outs[t].idx);
+    // deps[i]: products whose output product i reads
+    std::vector<std::vector<int64_t>> deps((size_t)n);
+    bool any = false;
+    for (int64_t i = 0; i < n; ++i) {
+        const lrbg_desc &d = ds[i];
+        int sh[4][2];
+        shapes(d, sh);
+        const void *ptr[3] = {d.a, d.b, d.s};
+        const int ld[3] = {d.lda, d.ldb, d.lds};
+        const size_t es[3] = {elem_size(d.prec), elem_size(d.prec), 8};
+        for (int t = 0; t < 3; ++t) {
+            if (t == 2 && d.op != LRBG_OP_RECOMP) continue;
+            Range in = span(ptr[t], sh[t][0], sh[t][1], ld[t], es[t], i);
+            if (in.hi <= in.lo) continue;
+            // outputs starting before in.hi; walk back while they may overlap
+            auto it = std::lower_bound(outs.begin(), outs.end(), in.hi,
+                                       [](const Range &x, uintptr_t v) { return x.lo < v; });
+            while (it != outs.begin()) {
+                --it;
+                if (it->hi <= in.lo) break;   // outputs are disjoint and sorted
+                if (it->idx != i) {
+                    deps[(size_t)i].push_back(it->idx);
+                    any = true;
+                }
+            }
+        }
+    }
+    if (!any) return LRBG_OK;
+    // longest-path levels; more passes than products means a cycle
+    for (int pass = 0;; ++pass) {
+        bool changed = false;
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j : deps[(size_t)i])
+                if (level[(size_t)i] < level[(size_t)j] + 1) {
+                    level[(size_t)i] = level[(size_t)j] + 1;
+                    changed = true;
+                }
+        if (!changed) break;
+        if (pass > 64) return fail(LRBG_EINVAL, "product dependencies form a cycle or a chain deeper than 64");
+    }
+    return LRBG_OK;
+}
+
+// Lay out one level's tiles: products are assigned to the 8 XCD bins by
+// longest-processing-time on the cost model (a product's tiles stay in one
+// bin, so tiles sharing its operands share an L2); within a bin products run
+// longest first (or interleaved compute-/memory-bound with SCHED_MIX); the
+// bins are interleaved so that tile t is dispatched to XCD t % 8.
+static void layout_level(const std::vector<int64_t> &prods, const lrbg_desc *ds, const std::vector<int> &variant,
+                         uint32_t flags, Schedule &sch, Level &lv)
+{
+    struct P {
+        int64_t i;
+        double t;
+    };
+    std::vector<P> ps;
+    ps.reserve(prods.size());
+    for (int64_t i : prods) ps.push_back(P{i, est_time(ds[i])});
+    std::stable_sort(ps.begin(), ps.end(), [](const P &x, const P &y) { return x.t > y.t; });
+    std::vector<std::vector<int64_t>> bins(kXcds);
+    std::vector<double> load(kXcds, 0.0);
+    for (const P &p : ps) {
+        int bmin = 0;
+        for (int b = 1; b < kXcds; ++b)
+            if (load[b] < load[bmin]) bmin = b;
+        bins[bmin].push_back(p.i);
+        load[bmin] += p.t;
+    }
+    if (flags & LRBG_PLAN_SCHED_MIX) {
+        for (auto &bin : bins) {
+            std::vector<int64_t> cb, mb;
+            double tc = 0, tm = 0;
+            for (int64_t i : bin) (compute_bound(ds[i]) ? cb : mb).push_back(i);
+            for (int64_t i : cb) tc += est_time(ds[i]);
+            for (int64_t i : mb) tm += est_time(ds[i]);
+            std::vector<int64_t> merged;
+            size_t a = 0, b = 0;
+            double sc = 0, sm = 0;
+            while (a < cb.size() || b < mb.size()) {
+                const bool takec = b >= mb.size() || (a < cb.size() && sc / std::max(tc, 1e-30) <= sm / std::max(tm, 1e-30));
+                if (takec) {
+                    sc += est_time(ds[cb[a]]);
+                    merged.push_back(cb[a++]);
+                } else {
+                    sm += est_time(ds[mb[b]]);
+                    merged.push_back(mb[b++]);
+                }
+            }
+            bin.swap(merged);
+        }
+    }
+    std::vector<std::vector<Tile>> bt(kXcds);
+    std::vector<int32_t> p0s;
+    for (int b = 0; b < kXcds; ++b)
+        for (int64_t i : bins[b]) {
+            p0s.clear();
+            tiles_of(variant[(size_t)i], ds[i], p0s);
+            for (int32_t p0 : p0s) bt[b].push_back(Tile{(int32_t)i, variant[(size_t)i], p0, 0});
+        }
+    size_t maxlen = 0, total = 0;
+    for (auto &v : bt) {
+        maxlen = std::max(maxlen, v.size());
+        total += v.size();
+    }
+    lv.tile_off = (int64_t)sch.tiles.size();
+    lv.qinfo_off = (int32_t)sch.qinfo.size();
+    if (flags & LRBG_PLAN_PERSISTENT) {
+        // queue q = bins[q], contiguous
+        int32_t off = 0;
+        for (int b = 0; b < kXcds; ++b) {
+            sch.qinfo.push_back(off);
+            for (const Tile &t : bt[b]) sch.tiles.push_back(t);
+            off += (int32_t)bt[b].size();
+        }
+        sch.qinfo.push_back(off);
+        lv.ntiles = off;
+    } else {
+        for (size_t slot = 0; slot < maxlen; ++slot)
+            for (int b = 0; b < kXcds; ++b)
+                sch.tiles.push_back(slot < bt[b].size() ? bt[b][slot] : Tile{0, 0, 0, 0});
+        lv.ntiles = (int32_t)(maxlen * kXcds);
+        for (int b = 0; b <= kXcds; ++b) sch.qinfo.push_back(0);
+    }
+    (void)total;
+}
+
+static lrbg_status build_schedule(const lrbg_desc *ds, int64_t n, const TuneTable &tt, uint32_t flags,
+                                  const int *force_variant, Schedule &sch)
+{
+    if (n < 0) return fail(LRBG_EINVAL, "negative count");
+    if (n > (int64_t)INT32_MAX / 2) return fail(LRBG_EUNSUPPORTED, "too many products");
+    if (n > 0 && !ds) return fail(LRBG_EINVAL, "descriptor array is NULL");
+    for (int64_t i = 0; i < n; ++i) {
+        lrbg_status st = validate_one(ds[i], i);
+        if (st != LRBG_OK) return st;
+    }
+    std::vector<int> level;
+    lrbg_status st = compute_levels(ds, n, level);
+    if (st != LRBG_OK) return st;
+    std::vector<int> variant((size_t)n, 0);
+    sch.descs.resize((size_t)n);
+    double flops = 0, bytes = 0;
+    int nlev = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const lrbg_desc &d = ds[i];
+        int v = 0;
+        if (force_variant && variant_fits(*force_variant, d)) v = *force_variant;
+        if (!v) {
+            auto it = tt.choice.find(bucket_of(d));
+            if (it != tt.choice.end() && variant_fits(it->second, d)) v = it->second;
+        }
+        if (!v) v = default_variant(d);
+        if (!v) return fail(LRBG_EUNSUPPORTED, "product %lld: no tile variant fits", (long long)i);
+        if (d.m == 0 || d.n == 0) v = 0;   // no-op
+        variant[(size_t)i] = v;
+        DevDesc &dd = sch.descs[(size_t)i];
+        dd.a = d.a;
+        dd.b = d.b;
+        dd.s = d.s;
+        dd.c = d.c;
+        dd.m = d.m;
+        dd.n = d.n;
+        dd.k = d.k;
+        dd.lda = d.lda;
+        dd.ldb = d.ldb;
+        dd.lds = d.lds;
+        dd.ldc = d.ldc;
+        dd.pad = 0;
+        double f, b;
+        work_of(d, f, b);
+        flops += f;
+        bytes += b;
+        nlev = std::max(nlev, level[(size_t)i] + 1);
+    }
+    std::vector<std::vector<int64_t>> bylevel((size_t)std::max(nlev, 1));
+    for (int64_t i = 0; i < n; ++i)
+        if (variant[(size_t)i]) bylevel[(size_t)level[(size_t)i]].push_back(i);
+    for (auto &prods : bylevel) {
+        Level lv;
+        layout_level(prods, ds, variant, flags, sch, lv);
+        sch.levels.push_back(lv);
+    }
+    if (sch.tiles.empty()) sch.tiles.push_back(Tile{0, 0, 0, 0});
+    if (sch.descs.empty()) sch.descs.push_back(DevDesc{});
+    int64_t ntiles = 0;
+    int32_t grid = 0;
+    for (auto &lv : sch.levels) {
+        ntiles += lv.ntiles;
+        grid = std::max(grid, lv.ntiles);
+    }
+    sch.stats.products = n;
+    sch.stats.tiles = ntiles;
+    sch.stats.levels = (int32_t)sch.levels.size();
+    sch.stats.grid = grid;
+    sch.stats.useful_flops = flops;
+    sch.stats.hbm_bytes = bytes;
+    return LRBG_OK;
+}
+
+static int g_persist_grid = 0;
+
+static int persistent_grid()
+{
+    if (!g_persist_grid) {
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            hipDeviceProp_t p;
+            if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+        }
+        g_persist_grid = cus * persistent_blocks_per_cu();
+        g_persist_grid = (g_persist_grid + kXcds - 1) / kXcds * kXcds;
+    }
+    return g_persist_grid;
+}
+
+// Enqueue every level of a plan on `stream`.
+static lrbg_status enqueue_levels(lrbg_plan *p, hipStream_t stream)
+{
+    for (auto &lv : p->levels) {
+        if (lv.ntiles <= 0) continue;
+        int rc;
+        if (p->flags & LRBG_PLAN_PERSISTENT) {
+            rc = launch_reset(p->d_counters + lv.qinfo_off, kXcds, stream);
+            if (rc) return fail(LRBG_EDEVICE, "reset launch failed: %s", hipGetErrorString((hipError_t)rc));
+            rc = launch_persistent(p->d_descs, p->d_tiles + lv.tile_off, p->d_qinfo + lv.qinfo_off,
+                                   p->d_counters + lv.qinfo_off, std::min(lv.grid, lv.ntiles), stream);
+        } else {
+            rc = launch_grouped(p->d_descs, p->d_tiles + lv.tile_off, lv.ntiles, stream);
+        }
+        if (rc) return fail(LRBG_EDEVICE, "grouped launch failed: %s", hipGetErrorString((hipError_t)rc));
+    }
+    return LRBG_OK;
+}
+
+static lrbg_status plan_from_schedule(Schedule &sch, uint32_t flags, lrbg_plan **out)
+{
+    lrbg_plan *p = new (std::nothrow) lrbg_plan();
+    if (!p) return fail(LRBG_ENOMEM, "plan allocation failed");
+    p->flags = flags;
+    p->levels = sch.levels;
+    p->stats = sch.stats;
+    hipGetDevice(&p->device);
+    auto cleanup = [&](lrbg_status st) {
+        lrbg_plan_destroy(p);
+        return st;
+    };
+    const size_t nd = sch.descs.size() * sizeof(DevDesc), nt = sch.tiles.size() * sizeof(Tile);
+    const size_t nq = std::max<size_t>(sch.qinfo.size(), 1) * sizeof(int32_t);
+    if (hipMalloc(&p->d_descs, nd) != hipSuccess || hipMalloc(&p->d_tiles, nt) != hipSuccess ||
+        hipMalloc(&p->d_qinfo, nq) != hipSuccess || hipMalloc(&p->d_counters, nq) != hipSuccess)
+        return cleanup(fail(LRBG_ENOMEM, "device allocation for the plan failed"));
+    if (hipMemcpy(p->d_descs, sch.descs.data(), nd, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_tiles, sch.tiles.data(), nt, hipMemcpyHostToDevice) != hipSuccess ||
+        (sch.qinfo.size() &&
+         hipMemcpy(p->d_qinfo, sch.qinfo.data(), sch.qinfo.size() * 4, hipMemcpyHostToDevice) != hipSuccess))
+        return cleanup(fail(LRBG_EDEVICE, "plan upload failed"));
+    if (flags & LRBG_PLAN_PERSISTENT) {
+        const int grid = persistent_grid();
+        for (auto &lv : p->levels) lv.grid = grid;
+    }
+    if (hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess)
+        return cleanup(fail(LRBG_EDEVICE, "event creation failed"));
+    if (!(flags & LRBG_PLAN_NO_GRAPH)) {
+        hipStream_t cs;
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+            return cleanup(fail(LRBG_EDEVICE, "capture stream creation failed"));
+        lrbg_status st = LRBG_OK;
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            st = fail(LRBG_EDEVICE, "hipStreamBeginCapture failed");
+        if (st == LRBG_OK) {
+            st = enqueue_levels(p, cs);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(cs, &g);
+            if (st == LRBG_OK && e != hipSuccess) st = fail(LRBG_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+            p->graph = g;
+        }
+        if (st == LRBG_OK && hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
+            st = fail(LRBG_EDEVICE, "hipGraphInstantiate failed");
+        hipStreamDestroy(cs);
+        if (st != LRBG_OK) return cleanup(st);
+    }
+    *out = p;
+    return LRBG_OK;
+}
+
+// ------------------------------------------------------------- one-shot calls
+
+// One-shot calls upload their schedule into pooled device buffers and
+// release them once an event recorded after the launch has completed, so
+// they never block the host on earlier work.
+struct Pending {
+    hipEvent_t ev;
+    lrbg_plan *plan;
+};
+static std::mutex g_mu;
+static std::vector<Pending> g_pending;
+
+static void reap(bool wait)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    std::vector<Pending> keep;
+    for (auto &pd : g_pending) {
+        if (wait) hipEventSynchronize(pd.ev);
+        if (hipEventQuery(pd.ev) == hipSuccess) {
+            hipEventDestroy(pd.ev);
+            lrbg_plan_destroy(pd.plan);
+        } else {
+            keep.push_back(pd);
+        }
+    }
+    g_pending.swap(keep);
+}
+
+static lrbg_status run_once(const lrbg_desc *ds, int64_t n, hipStream_t stream)
+{
+    reap(false);
+    if (n == 0) return LRBG_OK;
+    Schedule sch;
+    TuneTable tt;
+    load_tune_cache(getenv("LRBG_TUNE_CACHE"), tt);
+    lrbg_status st = build_schedule(ds, n, tt, 0, nullptr, sch);
+    if (st != LRBG_OK) return st;
+    lrbg_plan *p = nullptr;
+    st = plan_from_schedule(sch, LRBG_PLAN_NO_GRAPH, &p);
+    if (st != LRBG_OK) return st;
+    st = enqueue_levels(p, stream);
+    hipEvent_t ev;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        hipStreamSynchronize(stream);
+        lrbg_plan_destroy(p);
+        return st != LRBG_OK ? st : fail(LRBG_EDEVICE, "event creation failed");
+    }
+    hipEventRecord(ev, stream);
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_pending.push_back(Pending{ev, p});
+    return st;
+}
+
+}  // namespace lrbg
+
+// =================================================================== C ABI
+
+using namespace lrbg;
+
+extern "C" {
+
+lrbg_status lr_batched_gemm(int32_t op, int32_t prec, int64_t count, const int32_t *m, const int32_t *n,
+                            const int32_t *k, const void *const *A, const int32_t *lda, const void *const *B,
+                            const int32_t *ldb, const double *const *S, const int32_t *lds, void *const *C,
+                            const int32_t *ldc, void *stream)
+{
+    if (count < 0) return fail(LRBG_EINVAL, "negative count");
+    if (count == 0) return LRBG_OK;
+    if (!m || !n || !k || !A || !lda || !B || !ldb || !C || !ldc)
+        return fail(LRBG_EINVAL, "a required host array is NULL");
+    if (op == LRBG_OP_RECOMP && (!S || !lds)) return fail(LRBG_EINVAL, "RECOMP needs S and lds arrays");
+    std::vector<lrbg_desc> ds((size_t)count);
+    for (int64_t i = 0; i < count; ++i) {
+        lrbg_desc &d = ds[(size_t)i];
+        d.op = op;
+        d.prec = prec;
+        d.m = m[i];
+        d.n = n[i];
+        d.k = k[i];
+        d.a = A[i];
+        d.lda = lda[i];
+        d.b = B[i];
+        d.ldb = ldb[i];
+        d.s = (op == LRBG_OP_RECOMP) ? S[i] : nullptr;
+        d.lds = (op == LRBG_OP_RECOMP) ? lds[i] : 1;
+        d.c = C[i];
+        d.ldc = ldc[i];
+        d.flags = 0;
+    }
+    return run_once(ds.data(), count, (hipStream_t)stream);
+}
+
+lrbg_status lrbg_grouped(const lrbg_desc *descs, int64_t count, void *stream)
+{
+    if (count < 0) return fail(LRBG_EINVAL, "negative count");
+    return run_once(descs, count, (hipStream_t)stream);
+}
+
+lrbg_status lrbg_plan_create(lrbg_plan **out, const lrbg_desc *descs, int64_t count, const char *tune_cache,
+                             uint32_t flags)
+{
+    if (!out) return fail(LRBG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (flags & ~(uint32_t)(LRBG_PLAN_PERSISTENT | LRBG_PLAN_NO_GRAPH | LRBG_PLAN_SCHED_MIX))
+        return fail(LRBG_EINVAL, "unknown plan flags 0x%x", flags);
+    reap(false);
+    TuneTable tt;
+    load_tune_cache(tune_cache ? tune_cache : getenv("LRBG_TUNE_CACHE"), tt);
+    Schedule sch;
+    lrbg_status st = build_schedule(descs, count, tt, flags, nullptr, sch);
+    if (st != LRBG_OK) return st;
+    return plan_from_schedule(sch, flags, out);
+}
+
+lrbg_status lrbg_schedule_stats(const lrbg_desc *descs, int64_t count, const char *tune_cache, uint32_t flags,
+                                lrbg_plan_stats *out)
+{
+    if (!out) return fail(LRBG_EINVAL, "out is NULL");
+    if (flags & ~(uint32_t)(LRBG_PLAN_PERSISTENT | LRBG_PLAN_NO_GRAPH | LRBG_PLAN_SCHED_MIX))
+        return fail(LRBG_EINVAL, "unknown plan flags 0x%x", flags);
+    TuneTable tt;
+    load_tune_cache(tune_cache, tt);
+    Schedule sch;
+    lrbg_status st = build_schedule(descs, count, tt, flags, nullptr, sch);
+    if (st != LRBG_OK) return st;
+    *out = sch.stats;
+    return LRBG_OK;
+}
+
+lrbg_status lrbg_plan_execute(lrbg_plan *p, void *stream)
+{
+    if (!p) return fail(LRBG_EINVAL, "plan is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (hipEventRecord(p->ev0, s) != hipSuccess) return fail(LRBG_EDEVICE, "event record failed");
+    lrbg_status st = LRBG_OK;
+    if (p->exec) {
+        hipError_t e = hipGraphLaunch(p->exec, s);
+        if (e != hipSuccess) st = fail(LRBG_EDEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
+    } else {
+        st = enqueue_levels(p, s);
+    }
+    if (hipEventRecord(p->ev1, s) != hipSuccess) return fail(LRBG_EDEVICE, "event record failed");
+    p->timed = st == LRBG_OK;
+    return st;
+}
+
+double lrbg_plan_last_ms(lrbg_plan *p)
+{
+    if (!p || !p->timed) return -1.0;
+    if (hipEventSynchronize(p->ev1) != hipSuccess) return -1.0;
+    float ms = -1.0f;
+    if (hipEventElapsedTime(&ms, p->ev0, p->ev1) != hipSuccess) return -1.0;
+    return ms;
+}
+
+lrbg_status lrbg_plan_destroy(lrbg_plan *p)
+{
+    if (!p) return LRBG_OK;
+    if (p->timed && p->ev1) hipEventSynchronize(p->ev1);
+    if (p->exec) hipGraphExecDestroy(p->exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    if (p->ev0) hipEventDestroy(p->ev0);
+    if (p->ev1) hipEventDestroy(p->ev1);
+    if (p->d_descs) hipFree(p->d_descs);
+    if (p->d_tiles) hipFree(p->d_tiles);
+    if (p->d_qinfo) hipFree(p->d_qinfo);
+    if (p->d_counters) hipFree(p->d_counters);
+    delete p;
+    return LRBG_OK;
+}
+
+lrbg_status lrbg_plan_get_stats(const lrbg_plan *p, lrbg_plan_stats *out)
+{
+    if (!p || !out) return fail(LRBG_EINVAL, "NULL argument");
+    *out = p->stats;
+    return LRBG_OK;
+}
+
+lrbg_status lrbg_autotune(const lrbg_desc *sample, int64_t count, const char *cache_out, int32_t reps)
+{
+    if (count <= 0 || !sample) return fail(LRBG_EINVAL, "empty sample");
+    if (reps < 1) return fail(LRBG_EINVAL, "reps must be >= 1");
+    for (int64_t i = 0; i < count; ++i) {
+        lrbg_status st = validate_one(sample[i], i);
+        if (st != LRBG_OK) return st;
+    }
+    std::map<BucketKey, std::vector<lrbg_desc>> buckets;
+    for (int64_t i = 0; i < count; ++i) buckets[bucket_of(sample[i])].push_back(sample[i]);
+    hipStream_t s;
+    HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    std::ostringstream os;
+    os << "# lrbg tuning cache: op prec b r variant ms\n";
+    lrbg_status result = LRBG_OK;
+    for (auto &kv : buckets) {
+        auto &vec = kv.second;
+        int best = 0;
+        double best_ms = 1e300;
+        for (int v = 1; v < kNumVariants && result == LRBG_OK; ++v) {
+            bool ok = true;
+            for (auto &d : vec) ok = ok && variant_fits(v, d);
+            if (!ok) continue;
+            Schedule sch;
+            TuneTable none;
+            if (build_schedule(vec.data(), (int64_t)vec.size(), none, 0, &v, sch) != LRBG_OK) continue;
+            lrbg_plan *p = nullptr;
+            if (plan_from_schedule(sch, LRBG_PLAN_NO_GRAPH, &p) != LRBG_OK) continue;
+            double ms = 1e300;
+            for (int r = 0; r <= reps; ++r) {   // first run warms up
+                hipEventRecord(e0, s);
+                lrbg_status st = enqueue_levels(p, s);
+                hipEventRecord(e1, s);
+                if (st != LRBG_OK || hipEventSynchronize(e1) != hipSuccess) {
+                    result = st != LRBG_OK ? st : fail(LRBG_EDEVICE, "autotune run failed");
+                    break;
+                }
+                float t = 0;
+                hipEventElapsedTime(&t, e0, e1);
+                if (r > 0) ms = std::min(ms, (double)t);
+            }
+            lrbg_plan_destroy(p);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = v;
+            }
+        }
+        if (best)
+            os << std::get<0>(kv.first) << " " << std::get<1>(kv.first) << " " << std::get<2>(kv.first) << " "
+               << std::get<3>(kv.first) << " " << variant_name(best) << " " << best_ms << "\n";
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipStreamDestroy(s);
+    if (result != LRBG_OK) return result;
+    if (cache_out) {
+        std::ofstream f(cache_out);
+        if (!f) return fail(LRBG_EINVAL, "cannot write %s", cache_out);
+        f << os.str();
+    }
+    return LRBG_OK;
+}
+
+int32_t lrbg_variant_count(void) { return kNumVariants; }
+
+const char *lrbg_variant_name(int32_t v)
+{
+    static thread_local std::string s;
+    s = variant_name(v);
+    return s.c_str();
+}
+
+const char *lrbg_status_string(lrbg_status s)
+{
+    switch (s) {
+    case LRBG_OK: return "ok";
+    case LRBG_EINVAL: return "invalid argument";
+    case LRBG_EUNSUPPORTED: return "unsupported";
+    case LRBG_ENOMEM: return "out of memory";
+    case LRBG_EDEVICE: return "device error";
+    case LRBG_EBUDGET: return "over budget";
+    }
+    return "unknown status";
+}
+
+const char *lrbg_last_error(void) { return g_last_error.c_str(); }
+
+int32_t lrbg_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+// Internal definitions shared by the HIP kernels and the host side of the
+// library: the device descriptor of one product, the tile record of the
+// grouped schedule, and the table of compiled tile variants.
+#pragma once
+#include <stdint.h>
+
+namespace lrbg {
+
+// One product as the kernels see it (64 bytes).  Element types follow the
+// variant: FP64 variants read double a/b, BF16X3 variants read float a/b;
+// every output c is double.
+struct DevDesc {
+    const void *a;
+    const void *b;
+    const double *s;
+    void *c;
+    int32_t m, n, k;
+    int32_t lda, ldb, lds, ldc;
+    int32_t pad;
+};
+static_assert(sizeof(DevDesc) == 64, "DevDesc layout");
+
+// One workgroup's unit of work: product `desc`, computed by `variant`,
+// starting at row (DENSE_TS, INNER) or column (RECOMP) `p0`.
+struct Tile {
+    int32_t desc;
+    int32_t variant;
+    int32_t p0;
+    int32_t pad;
+};
+static_assert(sizeof(Tile) == 16, "Tile layout");
+
+enum Kind : int32_t {
+    K_NOP = 0,
+    K_DTS64 = 1,   // DENSE_TS, FP64 MFMA          params: RM, RN, KG
+    K_INN64 = 2,   // INNER, FP64 MFMA             params: RI, RJ, KS, KG
+    K_REC64 = 3,   // RECOMP, FP64 MFMA            params: RM, BNB, KG
+    K_DTS3 = 4,    // DENSE_TS, bf16x3 split MFMA  params: RM, RN
+    K_INN3 = 5,    // INNER, bf16x3 split MFMA     params: RI, RJ, KS
+};
+
+constexpr int kThreads = 256;       // 4 wavefronts of 64
+constexpr int kWaves = 4;
+constexpr int kLdsBytes = 32768;    // static LDS per workgroup
+constexpr int kMaxRank = 128;
+constexpr int kMaxBlock = 65536;
+constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies
+
+// X(id, kind, p1, p2, p3, p4): the compiled tile variants.  Ids are dense
+// and stable within a build; tuning caches refer to variants by name.
+#define LRBG_VARIANTS(X)              \
+    X(1, K_DTS64, 1, 1, 8, 0)         \
+    X(2, K_DTS64, 2, 1, 8, 0)         \
+    X(3, K_DTS64, 4, 1, 8, 0)         \
+    X(4, K_DTS64, 1, 2, 8, 0)         \
+    X(5, K_DTS64, 2, 2, 8, 0)         \
+    X(6, K_DTS64, 1, 4, 4, 0)         \
+    X(7, K_DTS64, 2, 4, 4, 0)         \
+    X(8, K_DTS64, 1, 8, 4, 0)         \
+    X(9, K_DTS64, 2, 8, 2, 0)         \
+    X(10, K_INN64, 1, 1, 4, 8)        \
+    X(11, K_INN64, 2, 2, 4, 8)        \
+    X(12, K_INN64, 2, 2, 2, 8)        \
+    X(13, K_INN64, 2, 4, 2, 4)        \
+    X(14, K_INN64, 1, 4, 4, 4)        \
+    X(15, K_INN64, 2, 8, 1, 2)        \
+    X(16, K_INN64, 1, 8, 1, 4)        \
+    X(17, K_REC64, 2, 4, 2, 0)        \
+    X(18, K_REC64, 2, 4, 8, 0)        \
+    X(19, K_REC64, 1, 4, 8, 0)        \
+    X(20, K_REC64, 2, 2, 8, 0)        \
+    X(21, K_REC64, 2, 8, 8, 0)        \
+    X(22, K_REC64, 4, 4, 8, 0)
+
+constexpr int kNumVariants = 23;   // ids 0..22 (0 = no-op tile)
+
+struct VariantInfo {
+    int32_t kind, p1, p2, p3, p4;
+};
+
+// Kernel launch helpers (defined in lrbg_kernels.hip).
+int launch_grouped(const DevDesc *descs, const Tile *tiles, int ntiles, void *stream);
+int launch_persistent(const DevDesc *descs, const Tile *tiles, const int32_t *qinfo,
+                      int32_t *counters, int grid, void *stream);
+int launch_reset(int32_t *counters, int n, void *stream);
+int persistent_blocks_per_cu();
+
+}  // namespace lrbg

@@ -1,0 +1,266 @@
+"""Thin ctypes binding of the lrbg C ABI (include/lrbg.h).
+
+Argument marshalling only: every product is computed by the HIP kernels of
+``liblrbg.so``.  The entry points keep the C names (``lr_batched_gemm``,
+``lrbg_grouped``, ``lrbg_plan_create`` ...); they take raw device pointers and
+host sequences and return the C status code, raising :class:`LrbgError` on a
+non-zero status.  :func:`desc` and :class:`Plan` are conveniences over them
+for column-major torch tensors (``x.stride(0) == 1``, leading dimension
+``x.stride(1)``).
+
+The library is loaded on first use; if it has not been built this raises
+instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, List, Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblrbg.so")
+
+LRBG_OK, LRBG_EINVAL, LRBG_EUNSUPPORTED, LRBG_ENOMEM, LRBG_EDEVICE, LRBG_EBUDGET = range(6)
+LRBG_OP_DENSE_TS, LRBG_OP_INNER, LRBG_OP_RECOMP = 0, 1, 2
+LRBG_FP64, LRBG_BF16X3 = 0, 1
+LRBG_PLAN_PERSISTENT, LRBG_PLAN_NO_GRAPH, LRBG_PLAN_SCHED_MIX = 0x1, 0x2, 0x4
+
+OPS = {"dense_ts": LRBG_OP_DENSE_TS, "inner": LRBG_OP_INNER, "recomp": LRBG_OP_RECOMP}
+PRECS = {"fp64": LRBG_FP64, "bf16x3": LRBG_BF16X3}
+
+
+class LrbgError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status} ({detail})")
+        self.status = status
+
+
+class lrbg_desc(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("m", ctypes.c_int32), ("n", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("lda", ctypes.c_int32), ("ldb", ctypes.c_int32), ("lds", ctypes.c_int32),
+                ("ldc", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("a", ctypes.c_void_p), ("b", ctypes.c_void_p), ("s", ctypes.c_void_p),
+                ("c", ctypes.c_void_p)]
+
+
+class lrbg_plan_stats(ctypes.Structure):
+    _fields_ = [("products", ctypes.c_int64), ("tiles", ctypes.c_int64),
+                ("levels", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("useful_flops", ctypes.c_double), ("hbm_bytes", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load(path: Optional[str] = None):
+    """Load liblrbg.so; raise if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or os.environ.get("LRBG_LIB") or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"liblrbg.so not built ({p}); run `python -c 'import __graft_entry__ as g; g.build()'`")
+    try:
+        # Bind to the HIP runtime PyTorch ships (same SONAME) rather than
+        # loading a second copy of the runtime into the process.
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(p)
+    i32, i64, vp, u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_uint32
+    P = ctypes.POINTER
+    lib.lr_batched_gemm.argtypes = [i32, i32, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.lr_batched_gemm.restype = ctypes.c_int
+    lib.lrbg_grouped.argtypes = [P(lrbg_desc), i64, vp]
+    lib.lrbg_grouped.restype = ctypes.c_int
+    lib.lrbg_plan_create.argtypes = [P(vp), P(lrbg_desc), i64, ctypes.c_char_p, u32]
+    lib.lrbg_plan_create.restype = ctypes.c_int
+    lib.lrbg_plan_execute.argtypes = [vp, vp]
+    lib.lrbg_plan_execute.restype = ctypes.c_int
+    lib.lrbg_plan_destroy.argtypes = [vp]
+    lib.lrbg_plan_destroy.restype = ctypes.c_int
+    lib.lrbg_plan_get_stats.argtypes = [vp, P(lrbg_plan_stats)]
+    lib.lrbg_plan_get_stats.restype = ctypes.c_int
+    lib.lrbg_schedule_stats.argtypes = [P(lrbg_desc), i64, ctypes.c_char_p, u32, P(lrbg_plan_stats)]
+    lib.lrbg_schedule_stats.restype = ctypes.c_int
+    lib.lrbg_plan_last_ms.argtypes = [vp]
+    lib.lrbg_plan_last_ms.restype = ctypes.c_double
+    lib.lrbg_autotune.argtypes = [P(lrbg_desc), i64, ctypes.c_char_p, i32]
+    lib.lrbg_autotune.restype = ctypes.c_int
+    lib.lrbg_variant_count.argtypes = []
+    lib.lrbg_variant_count.restype = i32
+    lib.lrbg_variant_name.argtypes = [i32]
+    lib.lrbg_variant_name.restype = ctypes.c_char_p
+    lib.lrbg_status_string.argtypes = [ctypes.c_int]
+    lib.lrbg_status_string.restype = ctypes.c_char_p
+    lib.lrbg_last_error.argtypes = []
+    lib.lrbg_last_error.restype = ctypes.c_char_p
+    lib.lrbg_version.argtypes = []
+    lib.lrbg_version.restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(st: int, where: str) -> int:
+    if st != LRBG_OK:
+        raise LrbgError(st, where, load().lrbg_last_error().decode(errors="replace"))
+    return st
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)   # torch.cuda.Stream
+
+
+def _arr(ctype, vals):
+    vals = list(vals)
+    return (ctype * max(len(vals), 1))(*vals)
+
+
+# ------------------------------------------------------------ raw entry points
+
+def lr_batched_gemm(op: int, prec: int, m: Sequence[int], n: Sequence[int], k: Sequence[int],
+                    A: Sequence[int], lda: Sequence[int], B: Sequence[int], ldb: Sequence[int],
+                    S: Optional[Sequence[int]], lds: Optional[Sequence[int]],
+                    C: Sequence[int], ldc: Sequence[int], stream=None) -> int:
+    count = len(m)
+    i32, vp = ctypes.c_int32, ctypes.c_void_p
+    args = [_arr(i32, m), _arr(i32, n), _arr(i32, k), _arr(vp, A), _arr(i32, lda), _arr(vp, B), _arr(i32, ldb),
+            _arr(vp, S) if S is not None else None, _arr(i32, lds) if lds is not None else None,
+            _arr(vp, C), _arr(i32, ldc)]
+    ptrs = [ctypes.cast(a, vp) if a is not None else None for a in args]
+    st = load().lr_batched_gemm(op, prec, count, *ptrs, _stream_ptr(stream))
+    return _check(st, "lr_batched_gemm")
+
+
+def lrbg_grouped(descs: Sequence[lrbg_desc], stream=None) -> int:
+    arr = (lrbg_desc * max(len(descs), 1))(*descs)
+    return _check(load().lrbg_grouped(arr, len(descs), _stream_ptr(stream)), "lrbg_grouped")
+
+
+def lrbg_plan_create(descs: Sequence[lrbg_desc], tune_cache: Optional[str] = None, flags: int = 0) -> int:
+    arr = (lrbg_desc * max(len(descs), 1))(*descs)
+    h = ctypes.c_void_p()
+    cache = tune_cache.encode() if tune_cache else None
+    _check(load().lrbg_plan_create(ctypes.byref(h), arr, len(descs), cache, flags), "lrbg_plan_create")
+    return h.value
+
+
+def lrbg_plan_execute(plan: int, stream=None) -> int:
+    return _check(load().lrbg_plan_execute(plan, _stream_ptr(stream)), "lrbg_plan_execute")
+
+
+def lrbg_plan_destroy(plan: int) -> int:
+    return _check(load().lrbg_plan_destroy(plan), "lrbg_plan_destroy")
+
+
+def lrbg_plan_get_stats(plan: int) -> dict:
+    s = lrbg_plan_stats()
+    _check(load().lrbg_plan_get_stats(plan, ctypes.byref(s)), "lrbg_plan_get_stats")
+    return {f: getattr(s, f) for f, _ in lrbg_plan_stats._fields_}
+
+
+def lrbg_schedule_stats(descs: Sequence[lrbg_desc], tune_cache: Optional[str] = None, flags: int = 0) -> dict:
+    arr = (lrbg_desc * max(len(descs), 1))(*descs)
+    s = lrbg_plan_stats()
+    cache = tune_cache.encode() if tune_cache else None
+    _check(load().lrbg_schedule_stats(arr, len(descs), cache, flags, ctypes.byref(s)), "lrbg_schedule_stats")
+    return {f: getattr(s, f) for f, _ in lrbg_plan_stats._fields_}
+
+
+def lrbg_plan_last_ms(plan: int) -> float:
+    return float(load().lrbg_plan_last_ms(plan))
+
+
+def lrbg_autotune(descs: Sequence[lrbg_desc], cache_out: str, reps: int = 3) -> int:
+    arr = (lrbg_desc * max(len(descs), 1))(*descs)
+    return _check(load().lrbg_autotune(arr, len(descs), cache_out.encode(), reps), "lrbg_autotune")
+
+
+def lrbg_variant_names() -> List[str]:
+    lib = load()
+    return [lib.lrbg_variant_name(v).decode() for v in range(lib.lrbg_variant_count())]
+
+
+def lrbg_last_error() -> str:
+    return load().lrbg_last_error().decode(errors="replace")
+
+
+def lrbg_version() -> int:
+    return int(load().lrbg_version())
+
+
+# ------------------------------------------------------------ conveniences
+
+def _mat(x):
+    """(pointer, rows, cols, ld) of a column-major 2-D tensor (or None)."""
+    if x is None:
+        return 0, 0, 0, 1
+    if x.dim() != 2:
+        raise ValueError("operands are 2-D")
+    rows, cols = x.shape
+    if rows > 1 and x.stride(0) != 1:
+        raise ValueError("operands must be column-major (stride(0) == 1)")
+    ld = x.stride(1) if cols > 1 else max(rows, 1)
+    return x.data_ptr(), rows, cols, max(ld, 1)
+
+
+def desc(op: str, a, b, c, s=None, prec: str = "fp64") -> lrbg_desc:
+    """Descriptor of one product from column-major tensors.
+
+    dense_ts: a = A (m x k), b = U (k x n), c = C (m x n)
+    inner:    a = V1 (k x m), b = U2 (k x n), c = T (m x n)
+    recomp:   a = U1 (m x k), b = V2 (n x k), s = S (k x k), c = W (m x n)
+    """
+    pa, ra, ca, la = _mat(a)
+    pb, rb, cb, lb = _mat(b)
+    pc, rc, cc, lc = _mat(c)
+    ps, rs, cs, ls = _mat(s)
+    o = OPS[op]
+    if o == LRBG_OP_DENSE_TS:
+        m, k, n = ra, ca, cb
+    elif o == LRBG_OP_INNER:
+        k, m, n = ra, ca, cb
+    else:
+        m, k, n = ra, ca, rb
+    return lrbg_desc(op=o, prec=PRECS[prec], m=m, n=n, k=k, lda=la, ldb=lb, lds=ls if s is not None else 1,
+                     ldc=lc, flags=0, a=pa or None, b=pb or None, s=ps or None, c=pc or None)
+
+
+class Plan:
+    """Owning wrapper of an lrbg plan (a captured, replayable grouped launch)."""
+
+    def __init__(self, descs: Sequence[lrbg_desc], tune_cache: Optional[str] = None, flags: int = 0,
+                 keepalive: Iterable = ()):
+        self._keep = list(keepalive)      # tensors whose memory the plan points at
+        self.handle = lrbg_plan_create(descs, tune_cache, flags)
+
+    def execute(self, stream=None):
+        lrbg_plan_execute(self.handle, stream)
+
+    def stats(self) -> dict:
+        return lrbg_plan_get_stats(self.handle)
+
+    def last_ms(self) -> float:
+        return lrbg_plan_last_ms(self.handle)
+
+    def close(self):
+        if self.handle:
+            lrbg_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,160 @@
+"""The C-ABI library loads, exports every declared entry point and rejects
+malformed arguments before launching anything (CPU only: validation runs on
+the host before any device call)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2311_07602_amd import lrbg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lrbg.h")
+
+# Fake, aligned, non-null device addresses: validation never dereferences them.
+BASE = 1 << 40
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(l[a-z_0-9]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for must in ("lr_batched_gemm", "lrbg_grouped", "lrbg_plan_create", "lrbg_plan_execute",
+                 "lrbg_plan_destroy", "lrbg_autotune", "lrbg_last_error", "lrbg_schedule_stats"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(lrbg.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version_and_status_strings():
+    assert lrbg.lrbg_version() >= 100
+    lib = lrbg.load()
+    assert lib.lrbg_status_string(0) == b"ok"
+    assert lib.lrbg_status_string(1) == b"invalid argument"
+    names = lrbg.lrbg_variant_names()
+    assert names[0] == "nop" and len(names) == lib.lrbg_variant_count()
+    assert len(set(names)) == len(names)
+
+
+def mk(op="dense_ts", prec=0, m=64, n=16, k=64, lda=None, ldb=None, lds=None, ldc=None, a=None, b=None, s=None,
+       c=None, base=BASE):
+    o = lrbg.OPS[op]
+    if lda is None:
+        lda = {0: m, 1: k, 2: m}[o]
+    if ldb is None:
+        ldb = {0: k, 1: k, 2: n}[o]
+    if ldc is None:
+        ldc = m
+    a = base if a is None else a
+    b = base + (1 << 30) if b is None else b
+    c = base + (2 << 30) if c is None else c
+    if o == 2 and s is None:
+        s = base + (3 << 30)
+    if lds is None:
+        lds = k if o == 2 else 1
+    return lrbg.lrbg_desc(op=o, prec=prec, m=m, n=n, k=k, lda=lda, ldb=ldb, lds=lds, ldc=ldc, flags=0,
+                          a=a, b=b, s=s, c=c)
+
+
+def status(descs):
+    try:
+        lrbg.lrbg_schedule_stats(descs)
+        return 0
+    except lrbg.LrbgError as e:
+        return e.status
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(m=-1), lrbg.LRBG_EINVAL),
+    (dict(lda=10), lrbg.LRBG_EINVAL),
+    (dict(ldc=3), lrbg.LRBG_EINVAL),
+    (dict(a=0), lrbg.LRBG_EINVAL),
+    (dict(c=0), lrbg.LRBG_EINVAL),
+    (dict(a=BASE + 4), lrbg.LRBG_EINVAL),          # misaligned FP64
+    (dict(n=129), lrbg.LRBG_EUNSUPPORTED),         # rank > 128
+    (dict(m=70000, lda=70000, ldc=70000), lrbg.LRBG_EUNSUPPORTED),
+    (dict(prec=7), lrbg.LRBG_EINVAL),
+    (dict(c=BASE + 8), lrbg.LRBG_EINVAL),          # output overlaps A
+])
+def test_dense_ts_validation(bad, code):
+    assert status([mk(**bad)]) == code
+
+
+def test_other_ops_validation():
+    assert status([mk("inner", m=16, n=16, k=512)]) == 0
+    assert status([mk("inner", m=130, n=16, k=512)]) == lrbg.LRBG_EUNSUPPORTED
+    assert status([mk("inner", m=16, n=16, k=512, lda=100)]) == lrbg.LRBG_EINVAL
+    assert status([mk("recomp", m=512, n=512, k=32)]) == 0
+    assert status([mk("recomp", m=512, n=512, k=32, lds=16)]) == lrbg.LRBG_EINVAL
+    assert status([mk("recomp", m=512, n=512, k=32, prec=1)]) == lrbg.LRBG_EUNSUPPORTED
+    assert status([mk("recomp", m=512, n=512, k=32, s=0)]) == lrbg.LRBG_EINVAL
+    d = mk(); d.op = 5
+    assert status([d]) == lrbg.LRBG_EINVAL
+    d = mk(); d.flags = 1
+    assert status([d]) == lrbg.LRBG_EINVAL
+
+
+def test_empty_and_zero_sizes():
+    assert lrbg.lrbg_schedule_stats([])["products"] == 0
+    st = lrbg.lrbg_schedule_stats([mk(m=0, lda=1, ldc=1, a=0, c=0), mk(n=0, b=0, c=0, base=BASE * 2)])
+    assert st["tiles"] == 0 and st["useful_flops"] == 0
+    st = lrbg.lrbg_schedule_stats([mk(k=0, lda=64, ldb=1, a=0, b=0)])   # k = 0: output zero-filled
+    assert st["tiles"] >= 1
+
+
+def test_output_overlap_between_products_rejected():
+    d1 = mk(); d2 = mk(base=BASE * 2, c=BASE + (2 << 30) + 8 * 64 * 16)
+    assert status([d1, d2]) == 0
+    d2 = mk(base=BASE * 2, c=BASE + (2 << 30) + 8 * (64 * 16 - 1))
+    assert status([d1, d2]) == lrbg.LRBG_EINVAL
+
+
+def test_chain_levels_and_accounting():
+    b, r = 512, 32
+    T = BASE + (10 << 30)
+    inner = mk("inner", m=r, n=r, k=b, c=T, ldc=r)
+    rec = mk("recomp", m=b, n=b, k=r, s=T, lds=r, base=BASE * 3)
+    st = lrbg.lrbg_schedule_stats([inner, rec])
+    assert st["levels"] == 2
+    f_inner = 2 * b * r * r
+    f_rec = 2 * b * b * r + 2 * r * r * b
+    assert st["useful_flops"] == pytest.approx(f_inner + f_rec)
+    by_inner = 8 * (2 * b * r + r * r)
+    by_rec = 8 * (2 * b * r + r * r + b * b)
+    assert st["hbm_bytes"] == pytest.approx(by_inner + by_rec)
+    st1 = lrbg.lrbg_schedule_stats([inner])
+    assert st1["levels"] == 1
+
+
+def test_cycle_rejected():
+    X = BASE + (20 << 30); Y = BASE + (21 << 30)
+    d1 = mk("inner", m=16, n=16, k=64, a=Y, b=BASE, c=X, ldc=16)
+    d2 = mk("inner", m=16, n=16, k=64, a=X, b=BASE + (1 << 32), c=Y, ldc=16, lda=64)
+    # d2 reads X (64 x 16 view over a 16 x 16 output: overlapping) and writes Y read by d1
+    assert status([d1, d2]) == lrbg.LRBG_EINVAL
+
+
+def test_tile_counts():
+    # DENSE_TS b=1024, r=16 default variant: 256 rows per tile -> 4 tiles
+    st = lrbg.lrbg_schedule_stats([mk(m=1024, n=16, k=1024)])
+    assert st["tiles"] % 8 == 0 and st["tiles"] >= 4
+    st = lrbg.lrbg_schedule_stats([mk(m=1024, n=16, k=1024)], flags=lrbg.LRBG_PLAN_PERSISTENT)
+    assert st["tiles"] == 4
+
+
+def test_null_host_arrays_rejected():
+    lib = lrbg.load()
+    st = lib.lr_batched_gemm(0, 0, 1, None, None, None, None, None, None, None, None, None, None, None, None)
+    assert st == lrbg.LRBG_EINVAL
+    assert lib.lr_batched_gemm(0, 0, 0, None, None, None, None, None, None, None, None, None, None, None, None) == 0
+    assert b"NULL" in lib.lrbg_last_error() or lib.lrbg_last_error() != b""
