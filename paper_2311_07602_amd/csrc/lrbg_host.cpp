@@ -65,6 +65,8 @@ static std::string variant_name(int v)
     case K_REC64: snprintf(buf, sizeof buf, "rec64_rm%d_bn%d_kg%d", vi.p1, vi.p2, vi.p3); break;
     case K_DTS3: snprintf(buf, sizeof buf, "dts3_rm%d_rn%d", vi.p1, vi.p2); break;
     case K_INN3: snprintf(buf, sizeof buf, "inn3_ri%d_rj%d_ks%d", vi.p1, vi.p2, vi.p3); break;
+    case K_DTSL: snprintf(buf, sizeof buf, "dtsl_rm%d_rn%d_kg%d", vi.p1, vi.p2, vi.p3); break;
+    case K_INNL: snprintf(buf, sizeof buf, "innl_ri%d_rj%d_wr%d_kg%d", vi.p1, vi.p2, vi.p3, vi.p4); break;
     default: snprintf(buf, sizeof buf, "v%d", v);
     }
     return buf;
@@ -83,14 +85,26 @@ static int kind_of(int op, int prec)
     return K_NOP;
 }
 
+// Variant kinds that compute op/prec (several tile designs per product kind).
+static bool kind_matches(int kind, int op, int prec)
+{
+    const int base = kind_of(op, prec);
+    if (kind == base) return base != K_NOP;
+    if (prec == LRBG_FP64 && op == LRBG_OP_DENSE_TS) return kind == K_DTSL;
+    if (prec == LRBG_FP64 && op == LRBG_OP_INNER) return kind == K_INNL;
+    return false;
+}
+
 // Can variant v compute this product?  (Rank-type limits of the tile.)
 static bool variant_fits(int v, const lrbg_desc &d)
 {
     if (v <= 0 || v >= kNumVariants) return false;
     const VariantInfo &vi = kVariants[v];
-    if (vi.kind != kind_of(d.op, d.prec)) return false;
+    if (!kind_matches(vi.kind, d.op, d.prec)) return false;
     switch (vi.kind) {
     case K_DTS64: return d.n <= 16 * vi.p2;
+    case K_DTSL: return d.n <= 16 * vi.p2;
+    case K_INNL: return d.n <= 16 * vi.p2 * (4 / vi.p3);
     case K_DTS3: return d.n <= 16 * vi.p2;
     case K_INN64: return d.n <= 16 * vi.p2;
     case K_INN3: return d.n <= 16 * vi.p2;
@@ -102,18 +116,38 @@ static bool variant_fits(int v, const lrbg_desc &d)
     return false;
 }
 
-// Tiles of product d under variant v; p0 of each tile appended to out.
-static void tiles_of(int v, const lrbg_desc &d, std::vector<int32_t> &p0s)
+// Tiles of product d under variant v: p0 of each tile and whether it needs
+// the guarded (ragged-edge) code path.
+static void tiles_of(int v, const lrbg_desc &d, std::vector<int32_t> &p0s, std::vector<int32_t> &edge)
 {
     const VariantInfo &vi = kVariants[v];
-    int step = 0, extent = 0;
+    int step = 0, extent = 0, kc = 1;
+    bool rows_full_needed = false;   // block-type rows must fill the tile
     switch (vi.kind) {
-    case K_DTS64: case K_DTS3: step = 64 * vi.p1; extent = d.m; break;
-    case K_INN64: case K_INN3: step = 16 * vi.p1 * (4 / vi.p3); extent = d.m; break;
-    case K_REC64: step = 16 * vi.p2; extent = d.n; break;
+    case K_DTS64: case K_DTSL:
+        step = 64 * vi.p1; extent = d.m; kc = 4 * vi.p3; rows_full_needed = true; break;
+    case K_DTS3:
+        step = 64 * vi.p1; extent = d.m; kc = 32; rows_full_needed = true; break;
+    case K_INN64:
+        step = 16 * vi.p1 * (4 / vi.p3); extent = d.m; kc = 4 * vi.p4; break;
+    case K_INN3:
+        step = 16 * vi.p1 * (4 / vi.p3); extent = d.m; kc = 32; break;
+    case K_INNL:
+        step = 16 * vi.p1 * vi.p3; extent = d.m; kc = 4 * vi.p4; break;
+    case K_REC64:
+        step = 16 * vi.p2; extent = d.n; kc = 4 * vi.p3; break;
     default: return;
     }
-    for (int p = 0; p < extent; p += step) p0s.push_back(p);
+    const bool ktail = d.k % kc != 0;
+    // RECOMP: every row group of 16 RM rows must be full, and so must the
+    // tile's columns (block-type W columns).
+    const bool rec_rows_ragged = vi.kind == K_REC64 && d.m % (16 * vi.p1) != 0;
+    for (int p = 0; p < extent; p += step) {
+        bool e = ktail || rec_rows_ragged;
+        if ((rows_full_needed || vi.kind == K_REC64) && p + step > extent) e = true;
+        p0s.push_back(p);
+        edge.push_back(e ? kTileEdge : 0);
+    }
 }
 
 // (b, r) of a product: block-type and rank-type dimension.
@@ -154,23 +188,23 @@ static int default_variant(const lrbg_desc &d)
         return 0;
     };
     if (kind == K_DTS64) {
-        if (d.n <= 16) return pick({d.m >= 256 ? 3 : (d.m >= 128 ? 2 : 1)});
-        if (d.n <= 32) return pick({d.m >= 128 ? 5 : 4});
-        if (d.n <= 64) return pick({d.m >= 128 ? 7 : 6});
-        return pick({d.m >= 128 ? 9 : 8});
+        if (d.n <= 16) return pick({1});
+        if (d.n <= 32) return pick({4});
+        if (d.n <= 64) return pick({d.m >= 512 ? 22 : 6});
+        return pick({d.m >= 256 ? 23 : 24});
     }
     if (kind == K_INN64) {
         const int rr = std::max(d.m, d.n);
-        if (rr <= 16) return pick({10});
-        if (rr <= 32) return pick({11});
-        if (rr <= 64) return pick({13});
-        return pick({15, 16});
+        if (rr <= 16) return pick({8});
+        if (rr <= 32) return pick({9});
+        if (rr <= 64) return pick({26, 11});
+        return pick({25, 28});
     }
     if (kind == K_REC64) {
-        if (d.k <= 16) return pick({17});
-        if (d.k <= 32) return pick({18});
-        if (d.k <= 64) return pick({18, 20});
-        return pick({20});
+        if (d.k <= 16) return pick({13});
+        if (d.k <= 32) return pick({14});
+        if (d.k <= 64) return pick({14, 16});
+        return pick({16});
     }
     (void)b;
     (void)r;
@@ -476,12 +510,14 @@ static void layout_level(const std::vector<int64_t> &prods, const lrbg_desc *ds,
         }
     }
     std::vector<std::vector<Tile>> bt(kXcds);
-    std::vector<int32_t> p0s;
+    std::vector<int32_t> p0s, edge;
     for (int b = 0; b < kXcds; ++b)
         for (int64_t i : bins[b]) {
             p0s.clear();
-            tiles_of(variant[(size_t)i], ds[i], p0s);
-            for (int32_t p0 : p0s) bt[b].push_back(Tile{(int32_t)i, variant[(size_t)i], p0, 0});
+            edge.clear();
+            tiles_of(variant[(size_t)i], ds[i], p0s, edge);
+            for (size_t t = 0; t < p0s.size(); ++t)
+                bt[b].push_back(Tile{(int32_t)i, variant[(size_t)i], p0s[t], edge[t]});
         }
     size_t maxlen = 0, total = 0;
     for (auto &v : bt) {
@@ -863,7 +899,7 @@ lrbg_status lrbg_autotune(const lrbg_desc *sample, int64_t count, const char *ca
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     std::ostringstream os;
-    os << "# lrbg tuning cache: op prec b r variant ms\n";
+    os << "# lrbg tuning cache: op prec b r variant ms (#cand lines: every candidate, with the bucket's product count)\n";
     lrbg_status result = LRBG_OK;
     for (auto &kv : buckets) {
         auto &vec = kv.second;
@@ -892,6 +928,8 @@ lrbg_status lrbg_autotune(const lrbg_desc *sample, int64_t count, const char *ca
                 if (r > 0) ms = std::min(ms, (double)t);
             }
             lrbg_plan_destroy(p);
+            os << "#cand " << std::get<0>(kv.first) << " " << std::get<1>(kv.first) << " " << std::get<2>(kv.first)
+               << " " << std::get<3>(kv.first) << " " << variant_name(v) << " " << ms << " " << vec.size() << "\n";
             if (ms < best_ms) {
                 best_ms = ms;
                 best = v;

@@ -21,13 +21,16 @@ struct DevDesc {
 static_assert(sizeof(DevDesc) == 64, "DevDesc layout");
 
 // One workgroup's unit of work: product `desc`, computed by `variant`,
-// starting at row (DENSE_TS, INNER) or column (RECOMP) `p0`.
+// starting at row (DENSE_TS, INNER) or column (RECOMP) `p0`.  flags bit 0
+// (kTileEdge) marks a tile that touches a ragged block-type edge or a
+// contraction tail and must run the guarded code path.
 struct Tile {
     int32_t desc;
     int32_t variant;
     int32_t p0;
-    int32_t pad;
+    int32_t flags;
 };
+constexpr int32_t kTileEdge = 1;
 static_assert(sizeof(Tile) == 16, "Tile layout");
 
 enum Kind : int32_t {
@@ -37,11 +40,13 @@ enum Kind : int32_t {
     K_REC64 = 3,   // RECOMP, FP64 MFMA            params: RM, BNB, KG
     K_DTS3 = 4,    // DENSE_TS, bf16x3 split MFMA  params: RM, RN
     K_INN3 = 5,    // INNER, bf16x3 split MFMA     params: RI, RJ, KS
+    K_DTSL = 6,    // DENSE_TS, FP64, U in LDS     params: RM, RN, KG
+    K_INNL = 7,    // INNER, FP64, LDS-staged      params: RI, RJ, WR, KG
 };
 
 constexpr int kThreads = 256;       // 4 wavefronts of 64
 constexpr int kWaves = 4;
-constexpr int kLdsBytes = 32768;    // static LDS per workgroup
+constexpr int kLdsBytes = 65536;    // static LDS per workgroup (2 workgroups per CU)
 constexpr int kMaxRank = 128;
 constexpr int kMaxBlock = 65536;
 constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies
@@ -56,23 +61,29 @@ constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies
     X(5, K_DTS64, 2, 2, 8, 0)         \
     X(6, K_DTS64, 1, 4, 4, 0)         \
     X(7, K_DTS64, 2, 4, 4, 0)         \
-    X(8, K_DTS64, 1, 8, 4, 0)         \
-    X(9, K_DTS64, 2, 8, 2, 0)         \
-    X(10, K_INN64, 1, 1, 4, 8)        \
-    X(11, K_INN64, 2, 2, 4, 8)        \
-    X(12, K_INN64, 2, 2, 2, 8)        \
-    X(13, K_INN64, 2, 4, 2, 4)        \
-    X(14, K_INN64, 1, 4, 4, 4)        \
-    X(15, K_INN64, 2, 8, 1, 2)        \
-    X(16, K_INN64, 1, 8, 1, 4)        \
-    X(17, K_REC64, 2, 4, 2, 0)        \
-    X(18, K_REC64, 2, 4, 8, 0)        \
-    X(19, K_REC64, 1, 4, 8, 0)        \
-    X(20, K_REC64, 2, 2, 8, 0)        \
-    X(21, K_REC64, 2, 8, 8, 0)        \
-    X(22, K_REC64, 4, 4, 8, 0)
+    X(8, K_INN64, 1, 1, 4, 8)         \
+    X(9, K_INN64, 2, 2, 4, 8)         \
+    X(10, K_INN64, 2, 2, 2, 8)        \
+    X(11, K_INN64, 2, 4, 2, 4)        \
+    X(12, K_INN64, 1, 4, 4, 4)        \
+    X(13, K_REC64, 2, 4, 2, 0)        \
+    X(14, K_REC64, 2, 4, 8, 0)        \
+    X(15, K_REC64, 1, 4, 8, 0)        \
+    X(16, K_REC64, 2, 2, 8, 0)        \
+    X(17, K_REC64, 2, 8, 8, 0)        \
+    X(18, K_REC64, 4, 4, 8, 0)        \
+    X(19, K_DTSL, 2, 2, 8, 0)         \
+    X(20, K_DTSL, 4, 2, 4, 0)         \
+    X(21, K_DTSL, 2, 4, 4, 0)         \
+    X(22, K_DTSL, 4, 4, 4, 0)         \
+    X(23, K_DTSL, 2, 8, 4, 0)         \
+    X(24, K_DTSL, 1, 8, 4, 0)         \
+    X(25, K_INNL, 4, 4, 2, 2)         \
+    X(26, K_INNL, 2, 2, 2, 4)         \
+    X(27, K_INNL, 2, 4, 4, 4)         \
+    X(28, K_INNL, 4, 4, 2, 3)
 
-constexpr int kNumVariants = 23;   // ids 0..22 (0 = no-op tile)
+constexpr int kNumVariants = 29;   // ids 0..28 (0 = no-op tile)
 
 struct VariantInfo {
     int32_t kind, p1, p2, p3, p4;

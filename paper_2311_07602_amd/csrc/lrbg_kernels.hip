@@ -6,17 +6,26 @@
 // (v_mfma_f64_16x16x4f64): per instruction a wavefront multiplies a 16x4 by
 // a 4x16 block; lane l = c + 16 g supplies A(row c, k g) and B(k g, col c),
 // and receives D(i, c) for the four rows i with i % 4 == g (item i / 4).
+// Accumulators stay in VGPRs: on gfx950 the FP64 MFMA reaches its full rate
+// from VGPR accumulators even at one wave per SIMD, not from AGPRs.
 //
-// Two index remappings keep HBM traffic coalesced without any LDS
-// transposition:
+// Two index remappings keep HBM traffic coalesced without any transposition:
 //  * k permutation: the contraction order inside a chunk is free, so lane
 //    group g consumes KG consecutive k (k0 + KG g + s at step s).  A lane then
 //    reads KG contiguous doubles of a column of a k-contiguous operand (U, V1,
 //    U2), i.e. whole 16-byte vectors.
-//  * row permutation: MFMA row c of row-block mm reads actual row
-//    RM * rho(c) + mm with rho(c) = 4 (c % 4) + c / 4.  A lane then loads RM
-//    contiguous rows of a row-contiguous operand (A, U1) per column, and its
-//    outputs are the 4 RM contiguous rows RM*4g .. RM*4g + 4RM - 1.
+//  * row permutation: with rho(c) = 4 (c % 4) + c / 4, MFMA row c of row
+//    block mm reads actual row rho(c) (RM = 1) or 32 h + 2 rho(c) + e with
+//    mm = 2 h + e (RM even).  A lane then loads whole 16-byte row pairs of a
+//    row-contiguous operand (A, U1), one load instruction covers 256
+//    contiguous bytes of a column per lane group, and a lane's outputs are
+//    runs of contiguous rows: 4g .. 4g+3 (RM = 1) or 32 h + 8g .. +7.
+//
+// Ragged edges: rank-type dimensions (< 16 or not a multiple of 16) are
+// masked branch-free (clamped address, then select).  Block-type dimensions
+// and contraction tails are handled by a GUARD instantiation of each tile
+// that the host selects per tile (Tile::flags bit 0); interior tiles run
+// straight-line vector loads.
 //
 // The products (column-major, see include/lrbg.h):
 //   DENSE_TS C = A U          (dense block x skinny basis)
@@ -30,6 +39,16 @@ namespace lrbg {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
 
+// Operand pointers come out of the descriptor table, so the compiler cannot
+// infer their address space; flat accesses would also count against the LDS
+// wait counter and serialise HBM prefetches with LDS traffic.  All operand
+// accesses therefore go through explicit global-space pointers.
+#define GLB __attribute__((address_space(1)))
+typedef const GLB double *gcp;
+typedef GLB double *gp;
+typedef const GLB d2u *gcp2;
+typedef GLB d2u *gp2;
+
 __device__ __forceinline__ d4 mfma64(double a, double b, d4 c)
 {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -37,15 +56,20 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c)
 
 __device__ __forceinline__ int rho(int c) { return 4 * (c & 3) + (c >> 2); }
 
-// n contiguous doubles from p into dst; elements at or beyond `valid` read 0.
-template <int NV>
-__device__ __forceinline__ void load_run(double (&dst)[NV], const double *p, int valid)
+__device__ __forceinline__ gcp gin(const void *p) { return (gcp)(p); }
+__device__ __forceinline__ gp gout(void *p) { return (gp)(p); }
+
+// NV contiguous doubles from p.  With GUARD, elements at or beyond `valid`
+// read 0 (ragged edges); otherwise all NV are in range and the load is
+// straight-line 16-byte vector loads.
+template <int NV, bool GUARD>
+__device__ __forceinline__ void load_run(double (&dst)[NV], gcp p, int valid)
 {
-    if (valid >= NV) {
+    if (!GUARD || valid >= NV) {
         if constexpr (NV % 2 == 0) {
 #pragma unroll
             for (int t = 0; t < NV; t += 2) {
-                d2u v = *reinterpret_cast<const d2u *>(p + t);
+                const d2u v = *reinterpret_cast<gcp2>(p + t);
                 dst[t] = v.x;
                 dst[t + 1] = v.y;
             }
@@ -59,10 +83,10 @@ __device__ __forceinline__ void load_run(double (&dst)[NV], const double *p, int
     }
 }
 
-template <int NV>
-__device__ __forceinline__ void store_run(double *p, const double (&src)[NV], int valid, bool nt)
+template <int NV, bool GUARD>
+__device__ __forceinline__ void store_run(gp p, const double (&src)[NV], int valid, bool nt)
 {
-    if (valid >= NV) {
+    if (!GUARD || valid >= NV) {
         if constexpr (NV % 2 == 0) {
 #pragma unroll
             for (int t = 0; t < NV; t += 2) {
@@ -70,9 +94,9 @@ __device__ __forceinline__ void store_run(double *p, const double (&src)[NV], in
                 v.x = src[t];
                 v.y = src[t + 1];
                 if (nt)
-                    __builtin_nontemporal_store(v, reinterpret_cast<d2u *>(p + t));
+                    __builtin_nontemporal_store(v, reinterpret_cast<gp2>(p + t));
                 else
-                    *reinterpret_cast<d2u *>(p + t) = v;
+                    *reinterpret_cast<gp2>(p + t) = v;
             }
         } else {
 #pragma unroll
@@ -85,35 +109,130 @@ __device__ __forceinline__ void store_run(double *p, const double (&src)[NV], in
     }
 }
 
+// The lane's RM rows of one column (col = row 0 of the wave's span); with
+// GUARD, rows at or beyond `valid` (relative to the span) read 0.
+template <int RM, bool GUARD>
+__device__ __forceinline__ void load_rows(double (&dst)[RM], gcp col, int c, int valid)
+{
+    if constexpr (RM == 1) {
+        double t[1];
+        load_run<1, GUARD>(t, col + rho(c), valid - rho(c));
+        dst[0] = t[0];
+    } else {
+#pragma unroll
+        for (int h = 0; h < RM / 2; ++h) {
+            const int r0 = 32 * h + 2 * rho(c);
+            double t[2];
+            load_run<2, GUARD>(t, col + r0, valid - r0);
+            dst[2 * h] = t[0];
+            dst[2 * h + 1] = t[1];
+        }
+    }
+}
+
+// Store the lane's outputs of one column: acc[mm] is row block mm, item v
+// holding MFMA row 4v + g.  col = row 0 of the wave's span.
+template <int RM, bool GUARD>
+__device__ __forceinline__ void store_rows(gp col, const d4 (&acc)[RM], int g, int valid, bool nt)
+{
+    if constexpr (RM == 1) {
+        double o[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o[v] = acc[0][v];
+        store_run<4, GUARD>(col + 4 * g, o, valid - 4 * g, nt);
+    } else {
+#pragma unroll
+        for (int h = 0; h < RM / 2; ++h) {
+            const int r0 = 32 * h + 8 * g;
+            double o[8];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                o[2 * v] = acc[2 * h][v];
+                o[2 * v + 1] = acc[2 * h + 1][v];
+            }
+            store_run<8, GUARD>(col + r0, o, valid - r0, nt);
+        }
+    }
+}
+
+// KG doubles of a k-contiguous column selected by a lane-dependent mask:
+// the column pointer is already clamped to a valid column; masked lanes get 0.
+template <int KG, bool GUARD>
+__device__ __forceinline__ void load_kcol(double (&dst)[KG], gcp colp, bool ok, int kvalid)
+{
+    load_run<KG, GUARD>(dst, colp, kvalid);
+#pragma unroll
+    for (int s = 0; s < KG; ++s) dst[s] = ok ? dst[s] : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Staging of a k-contiguous operand chunk (KC rows of NCOL columns of a
+// column-major matrix) into LDS as buf[kk * P + j]: threads read 16-byte row
+// pairs, consecutive threads walking down a column, and write them
+// transposed so that the matrix-core operand reads (16 consecutive j per
+// lane group) are conflict-free.  Columns at or beyond `nvalid` are stored
+// as 0; with GUARD, so are rows at or beyond `kvalid`.
+template <int NCOL, int KC, bool GUARD>
+struct StageK {
+    static_assert(KC % 2 == 0, "row pairs");
+    static constexpr int NPAIR = NCOL * (KC / 2);
+    static constexpr int PPT = (NPAIR + kThreads - 1) / kThreads;
+    double r[PPT][2];
+
+    __device__ __forceinline__ void fetch(gcp base, size_t ld, int kvalid, int nvalid)
+    {
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            const int idx = threadIdx.x + kThreads * p;
+            const int j = idx / (KC / 2), kk = 2 * (idx % (KC / 2));
+            const bool ok = idx < NPAIR && j < nvalid;
+            const int jc = ok ? j : 0;
+            double t[2];
+            load_run<2, GUARD>(t, base + kk + (size_t)jc * ld, kvalid - kk);
+            r[p][0] = ok ? t[0] : 0.0;
+            r[p][1] = ok ? t[1] : 0.0;
+        }
+    }
+    __device__ __forceinline__ void store(double *buf, int P) const
+    {
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            const int idx = threadIdx.x + kThreads * p;
+            if (idx < NPAIR) {
+                const int j = idx / (KC / 2), kk = 2 * (idx % (KC / 2));
+                buf[kk * P + j] = r[p][0];
+                buf[(kk + 1) * P + j] = r[p][1];
+            }
+        }
+    }
+};
+
 // ---------------------------------------------------------------------------
 // DENSE_TS, FP64.  Workgroup tile: rows [i0, i0 + 64 RM) x all n (<= 16 RN)
 // columns, full contraction.  Wave w owns rows i0 + 16 RM w + [0, 16 RM).
 // A streams from HBM exactly once (each element feeds RN MFMAs in registers);
-// U chunks are re-read from L2 by every wave.
-template <int RM, int RN, int KG>
+// U chunks are re-read from L2 by every wave.  No barriers.
+template <int RM, int RN, int KG, bool GUARD>
 __device__ __forceinline__ void dts64_tile(const DevDesc &d, int i0)
 {
     constexpr int KSTEP = 4 * KG;
+    static_assert(RM == 1 || RM % 2 == 0, "RM is 1 or even");
     const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
     const int M = d.m, N = d.n, K = d.k;
     const size_t lda = (size_t)d.lda, ldu = (size_t)d.ldb, ldc = (size_t)d.ldc;
-    const double *__restrict__ A = static_cast<const double *>(d.a);
-    const double *__restrict__ U = static_cast<const double *>(d.b);
-    double *__restrict__ C = static_cast<double *>(d.c);
 
     const int wrow = i0 + 16 * RM * w;
-    if (wrow >= M) return;                       // no barriers in this tile
-    const int lrow = wrow + RM * rho(c);         // first of the lane's RM load rows
-    const int rvalid = M - lrow;                 // rows left from lrow (may be <= 0)
+    if (GUARD && wrow >= M) return;
+    const int rvalid = M - wrow;
+    const gcp Ap = gin(d.a) + wrow;
 
-    const double *Ap = A + lrow;                 // + col * lda
-    const double *Up[RN];
+    gcp Up[RN];
     bool colok[RN];
 #pragma unroll
     for (int jb = 0; jb < RN; ++jb) {
         const int col = jb * 16 + c;
         colok[jb] = col < N;
-        Up[jb] = U + (size_t)(colok[jb] ? col : 0) * ldu;
+        Up[jb] = gin(d.b) + (size_t)(colok[jb] ? col : 0) * ldu;
     }
 
     d4 acc[RM][RN];
@@ -123,29 +242,22 @@ __device__ __forceinline__ void dts64_tile(const DevDesc &d, int i0)
         for (int jb = 0; jb < RN; ++jb) acc[mm][jb] = d4{0.0, 0.0, 0.0, 0.0};
 
     double a[KG][RM], u[RN][KG];
-
     auto load = [&](int k0, double (&aa)[KG][RM], double (&uu)[RN][KG]) {
-        const int kb = k0 + KG * g;              // this lane group's first k
+        const int kb = k0 + KG * g;
         const int kvalid = K - kb;
 #pragma unroll
         for (int s = 0; s < KG; ++s) {
-            if (s < kvalid)
-                load_run<RM>(aa[s], Ap + (size_t)(kb + s) * lda, rvalid);
+            if (!GUARD || s < kvalid)
+                load_rows<RM, GUARD>(aa[s], Ap + (size_t)(kb + s) * lda, c, rvalid);
             else
 #pragma unroll
                 for (int mm = 0; mm < RM; ++mm) aa[s][mm] = 0.0;
         }
 #pragma unroll
-        for (int jb = 0; jb < RN; ++jb) {
-            if (colok[jb])
-                load_run<KG>(uu[jb], Up[jb] + kb, kvalid);
-            else
-#pragma unroll
-                for (int s = 0; s < KG; ++s) uu[jb][s] = 0.0;
-        }
+        for (int jb = 0; jb < RN; ++jb) load_kcol<KG, GUARD>(uu[jb], Up[jb] + kb, colok[jb], kvalid);
     };
 
-    load(0, a, u);
+    if (K > 0) load(0, a, u);
     for (int k0 = 0; k0 < K; k0 += KSTEP) {
         double an[KG][RM], un[RN][KG];
         const bool more = k0 + KSTEP < K;
@@ -169,19 +281,107 @@ __device__ __forceinline__ void dts64_tile(const DevDesc &d, int i0)
         }
     }
 
-    // lane (c, g) holds rows wrow + 4 RM g + (RM v + mm) of column jb*16 + c
-    const int orow = wrow + 4 * RM * g;
-    const int ovalid = M - orow;
-    if (ovalid <= 0) return;
 #pragma unroll
     for (int jb = 0; jb < RN; ++jb) {
         if (!colok[jb]) continue;
-        double o[4 * RM];
+        d4 o[RM];
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
+        for (int mm = 0; mm < RM; ++mm) o[mm] = acc[mm][jb];
+        store_rows<RM, GUARD>(gout(d.c) + wrow + (size_t)(jb * 16 + c) * ldc, o, g, rvalid, false);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// DENSE_TS, FP64, U staged in LDS (for the matrix-core-bound buckets): the 4
+// waves share each U chunk from LDS instead of each re-reading it from L2;
+// A streams from HBM straight into registers.  Tile: rows [i0, i0 + 64 RM) x
+// all n (<= 16 RN) columns.  Two LDS buffers, one barrier per chunk.
+template <int RM, int RN, int KG, bool GUARD>
+__device__ __forceinline__ void dtsl_tile(const DevDesc &d, int i0, double *lds)
+{
+    constexpr int KC = 4 * KG;
+    constexpr int NC = 16 * RN;
+    constexpr int P = NC + 1;
+    constexpr int BUF = KC * P;
+    static_assert(2 * BUF * 8 <= kLdsBytes, "DENSE_TS U staging exceeds LDS");
+    static_assert(RM == 1 || RM % 2 == 0, "RM is 1 or even");
+    const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
+    const int M = d.m, N = d.n, K = d.k;
+    const size_t lda = (size_t)d.lda, ldu = (size_t)d.ldb, ldc = (size_t)d.ldc;
+
+    const int wrow = i0 + 16 * RM * w;
+    const bool active = !GUARD || wrow < M;     // inactive waves still stage and sync
+    const int rvalid = M - wrow;
+    const gcp Ap = gin(d.a) + (active ? wrow : 0);
+    const gcp U = gin(d.b);
+
+    d4 acc[RM][RN];
 #pragma unroll
-            for (int mm = 0; mm < RM; ++mm) o[RM * v + mm] = acc[mm][jb][v];
-        store_run<4 * RM>(C + orow + (size_t)(jb * 16 + c) * ldc, o, ovalid, false);
+    for (int mm = 0; mm < RM; ++mm)
+#pragma unroll
+        for (int jb = 0; jb < RN; ++jb) acc[mm][jb] = d4{0.0, 0.0, 0.0, 0.0};
+
+    StageK<NC, KC, GUARD> st;
+    double a[KG][RM];
+    auto load_a = [&](int k0, double (&aa)[KG][RM]) {
+        const int kb = k0 + KG * g;
+#pragma unroll
+        for (int s = 0; s < KG; ++s) {
+            if (!GUARD || (active && kb + s < K))
+                load_rows<RM, GUARD>(aa[s], Ap + (size_t)(kb + s) * lda, c, rvalid);
+            else
+#pragma unroll
+                for (int mm = 0; mm < RM; ++mm) aa[s][mm] = 0.0;
+        }
+    };
+
+    if (K > 0) {
+        st.fetch(U, ldu, K, N);
+        st.store(lds, P);
+        load_a(0, a);
+    }
+    __syncthreads();
+    int it = 0;
+    for (int k0 = 0; k0 < K; k0 += KC, ++it) {
+        const double *cur = lds + (it & 1) * BUF;
+        double *nxt = lds + ((it + 1) & 1) * BUF;
+        const bool more = k0 + KC < K;
+        double an[KG][RM];
+        if (more) {
+            st.fetch(U + k0 + KC, ldu, K - (k0 + KC), N);
+            load_a(k0 + KC, an);
+        }
+        if (active) {
+#pragma unroll
+            for (int s = 0; s < KG; ++s) {
+                double b[RN];
+#pragma unroll
+                for (int jb = 0; jb < RN; ++jb) b[jb] = cur[(KG * g + s) * P + jb * 16 + c];
+#pragma unroll
+                for (int jb = 0; jb < RN; ++jb)
+#pragma unroll
+                    for (int mm = 0; mm < RM; ++mm) acc[mm][jb] = mfma64(a[s][mm], b[jb], acc[mm][jb]);
+            }
+        }
+        if (more) {
+            st.store(nxt, P);
+#pragma unroll
+            for (int s = 0; s < KG; ++s)
+#pragma unroll
+                for (int mm = 0; mm < RM; ++mm) a[s][mm] = an[s][mm];
+        }
+        __syncthreads();
+    }
+
+    if (!active) return;
+#pragma unroll
+    for (int jb = 0; jb < RN; ++jb) {
+        const int col = jb * 16 + c;
+        if (col >= N) continue;
+        d4 o[RM];
+#pragma unroll
+        for (int mm = 0; mm < RM; ++mm) o[mm] = acc[mm][jb];
+        store_rows<RM, GUARD>(gout(d.c) + wrow + (size_t)col * ldc, o, g, rvalid, false);
     }
 }
 
@@ -192,7 +392,7 @@ __device__ __forceinline__ void dts64_tile(const DevDesc &d, int i0)
 // (interleaved, so the group streams neighbouring rows together).  Partial
 // sums meet in LDS and are added in a fixed order: deterministic, no atomics.
 // Workgroup tile: T rows [i0, i0 + 16 RI NG) x all n columns.
-template <int RI, int RJ, int KS, int KG>
+template <int RI, int RJ, int KS, int KG, bool GUARD>
 __device__ __forceinline__ void inn64_tile(const DevDesc &d, int i0, double *lds)
 {
     constexpr int NG = 4 / KS;
@@ -201,26 +401,23 @@ __device__ __forceinline__ void inn64_tile(const DevDesc &d, int i0, double *lds
     const int og = w / KS, ks = w % KS;
     const int M = d.m, N = d.n, K = d.k;
     const size_t ldv = (size_t)d.lda, ldu = (size_t)d.ldb, ldt = (size_t)d.ldc;
-    const double *__restrict__ V1 = static_cast<const double *>(d.a);
-    const double *__restrict__ U2 = static_cast<const double *>(d.b);
-    double *__restrict__ T = static_cast<double *>(d.c);
 
     const int rowbase = i0 + og * 16 * RI;
-    const double *Vp[RI];
+    gcp Vp[RI];
     bool rok[RI];
 #pragma unroll
     for (int bi = 0; bi < RI; ++bi) {
         const int col = rowbase + bi * 16 + rho(c);   // V1 column = T row
         rok[bi] = col < M;
-        Vp[bi] = V1 + (size_t)(rok[bi] ? col : 0) * ldv;
+        Vp[bi] = gin(d.a) + (size_t)(rok[bi] ? col : 0) * ldv;
     }
-    const double *Up[RJ];
+    gcp Up[RJ];
     bool cok[RJ];
 #pragma unroll
     for (int bj = 0; bj < RJ; ++bj) {
         const int col = bj * 16 + c;
         cok[bj] = col < N;
-        Up[bj] = U2 + (size_t)(cok[bj] ? col : 0) * ldu;
+        Up[bj] = gin(d.b) + (size_t)(cok[bj] ? col : 0) * ldu;
     }
 
     d4 acc[RI][RJ];
@@ -234,21 +431,9 @@ __device__ __forceinline__ void inn64_tile(const DevDesc &d, int i0, double *lds
         const int kb = k0 + KG * g;
         const int kvalid = K - kb;
 #pragma unroll
-        for (int bi = 0; bi < RI; ++bi) {
-            if (rok[bi])
-                load_run<KG>(aa[bi], Vp[bi] + kb, kvalid);
-            else
+        for (int bi = 0; bi < RI; ++bi) load_kcol<KG, GUARD>(aa[bi], Vp[bi] + kb, rok[bi], kvalid);
 #pragma unroll
-                for (int s = 0; s < KG; ++s) aa[bi][s] = 0.0;
-        }
-#pragma unroll
-        for (int bj = 0; bj < RJ; ++bj) {
-            if (cok[bj])
-                load_run<KG>(uu[bj], Up[bj] + kb, kvalid);
-            else
-#pragma unroll
-                for (int s = 0; s < KG; ++s) uu[bj][s] = 0.0;
-        }
+        for (int bj = 0; bj < RJ; ++bj) load_kcol<KG, GUARD>(uu[bj], Up[bj] + kb, cok[bj], kvalid);
     };
 
     int k0 = ks * KSTEP;
@@ -317,7 +502,93 @@ __device__ __forceinline__ void inn64_tile(const DevDesc &d, int i0, double *lds
             double o[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) o[v] = acc[bi][bj][v];
-            store_run<4>(T + orow + (size_t)(bj * 16 + c) * ldt, o, ovalid, false);
+            store_run<4, true>(gout(d.c) + orow + (size_t)(bj * 16 + c) * ldt, o, ovalid, false);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// INNER, FP64, both operands staged in LDS (ranks >= 64, matrix-core-bound):
+// each k chunk of V1 (tile rows) and U2 (all columns) crosses HBM -> LDS
+// once, and the 4 waves, arranged WR x WC over the output, each own a
+// 16 RI x 16 RJ block group for the whole contraction (no reduction).
+// Tile: T rows [i0, i0 + 16 RI WR) x columns [0, 16 RJ WC).
+template <int RI, int RJ, int WR, int KG, bool GUARD>
+__device__ __forceinline__ void innl_tile(const DevDesc &d, int i0, double *lds)
+{
+    constexpr int WC = 4 / WR;
+    constexpr int KC = 4 * KG;
+    constexpr int MT = 16 * RI * WR, NT = 16 * RJ * WC;
+    constexpr int PV = MT + 1, PU = NT + 1;
+    constexpr int BUF = KC * (PV + PU);
+    static_assert(2 * BUF * 8 <= kLdsBytes, "INNER staging exceeds LDS");
+    const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
+    const int wr = w / WC, wc = w % WC;
+    const int M = d.m, N = d.n, K = d.k;
+    const size_t ldv = (size_t)d.lda, ldu = (size_t)d.ldb, ldt = (size_t)d.ldc;
+    const gcp V1t = gin(d.a) + (size_t)i0 * ldv;   // column i0 of V1 = T row i0
+    const gcp U2 = gin(d.b);
+    const int mvalid = M - i0;
+
+    d4 acc[RI][RJ];
+#pragma unroll
+    for (int bi = 0; bi < RI; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < RJ; ++bj) acc[bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
+
+    StageK<MT, KC, GUARD> sv;
+    StageK<NT, KC, GUARD> su;
+    if (K > 0) {
+        sv.fetch(V1t, ldv, K, mvalid);
+        su.fetch(U2, ldu, K, N);
+        sv.store(lds, PV);
+        su.store(lds + KC * PV, PU);
+    }
+    __syncthreads();
+    const int arow = wr * 16 * RI, bcol = wc * 16 * RJ;
+    int it = 0;
+    for (int k0 = 0; k0 < K; k0 += KC, ++it) {
+        const double *cv = lds + (it & 1) * BUF;
+        const double *cu = cv + KC * PV;
+        double *nv = lds + ((it + 1) & 1) * BUF;
+        const bool more = k0 + KC < K;
+        if (more) {
+            sv.fetch(V1t + k0 + KC, ldv, K - (k0 + KC), mvalid);
+            su.fetch(U2 + k0 + KC, ldu, K - (k0 + KC), N);
+        }
+#pragma unroll
+        for (int s = 0; s < KG; ++s) {
+            const int kk = KG * g + s;
+            double a[RI], b[RJ];
+#pragma unroll
+            for (int bi = 0; bi < RI; ++bi) a[bi] = cv[kk * PV + arow + bi * 16 + rho(c)];
+#pragma unroll
+            for (int bj = 0; bj < RJ; ++bj) b[bj] = cu[kk * PU + bcol + bj * 16 + c];
+#pragma unroll
+            for (int bi = 0; bi < RI; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < RJ; ++bj) acc[bi][bj] = mfma64(a[bi], b[bj], acc[bi][bj]);
+        }
+        if (more) {
+            sv.store(nv, PV);
+            su.store(nv + KC * PV, PU);
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int bi = 0; bi < RI; ++bi) {
+        const int orow = i0 + arow + bi * 16 + 4 * g;
+        const int ovalid = M - orow;
+        if (ovalid <= 0) continue;
+#pragma unroll
+        for (int bj = 0; bj < RJ; ++bj) {
+            const int col = bcol + bj * 16 + c;
+            if (col >= N) continue;
+            double o[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) o[v] = acc[bi][bj][v];
+            store_run<4, true>(gout(d.c) + orow + (size_t)col * ldt, o, ovalid, false);
         }
     }
 }
@@ -329,33 +600,35 @@ __device__ __forceinline__ void inn64_tile(const DevDesc &d, int i0, double *lds
 // groups of 16 RM rows, streaming U1 (L2-resident, shared by the product's
 // column tiles) against P and writing W with non-temporal stores: the b x b
 // output is the dominant HBM traffic.
-template <int RM, int BNB, int KG>
+template <int RM, int BNB, int KG, bool GUARD>
 __device__ __forceinline__ void rec64_tile(const DevDesc &d, int j0, double *lds)
 {
     constexpr int PW = 16 * BNB;
     constexpr int KSTEP = 4 * KG;
+    static_assert(RM == 1 || RM % 2 == 0, "RM is 1 or even");
     const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
     const int M = d.m, N = d.n, K = d.k;
     const size_t ldu = (size_t)d.lda, ldv = (size_t)d.ldb, lds_ = (size_t)d.lds, ldw = (size_t)d.ldc;
-    const double *__restrict__ U1 = static_cast<const double *>(d.a);
-    const double *__restrict__ V2 = static_cast<const double *>(d.b);
-    const double *__restrict__ S = d.s;
-    double *__restrict__ W = static_cast<double *>(d.c);
+    const gcp U1 = gin(d.a), V2 = gin(d.b), S = gin(d.s);
+    const gp W = gout(d.c);
     double *P = lds;   // P[l * PW + jj], l < 16 * ceil(K / 16)
 
-    // ---- P = S V2^T on the tile's columns
+    // ---- P = S V2^T on the tile's columns (rank-sized, masked branch-free)
     const int KB = (K + 15) >> 4;
     for (int blk = w; blk < KB * BNB; blk += kWaves) {
         const int lb = blk / BNB, jb = blk % BNB;
         const int l = lb * 16 + c;              // A operand row (P row)
         const int jj = j0 + jb * 16 + c;        // B operand column (W column)
         const bool lok = l < K, jok = jj < N;
+        const gcp Sp = S + (lok ? l : 0);
+        const gcp Vp = V2 + (jok ? jj : 0);
         d4 p = d4{0.0, 0.0, 0.0, 0.0};
         for (int q0 = 0; q0 < K; q0 += 4) {
             const int q = q0 + g;
-            const double sa = (lok && q < K) ? S[l + (size_t)q * lds_] : 0.0;
-            const double vb = (jok && q < K) ? V2[jj + (size_t)q * ldv] : 0.0;
-            p = mfma64(sa, vb, p);
+            const bool qok = q < K;
+            const size_t qc = (size_t)(qok ? q : 0);
+            const double sv = Sp[qc * lds_], vv = Vp[qc * ldv];
+            p = mfma64((lok && qok) ? sv : 0.0, (jok && qok) ? vv : 0.0, p);
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) P[(lb * 16 + 4 * v + g) * PW + jb * 16 + c] = p[v];
@@ -373,8 +646,7 @@ __device__ __forceinline__ void rec64_tile(const DevDesc &d, int j0, double *lds
 
     for (int rg = w; rg * 16 * RM < M; rg += kWaves) {
         const int wrow = rg * 16 * RM;
-        const int lrow = wrow + RM * rho(c);
-        const int rvalid = M - lrow;
+        const int rvalid = M - wrow;
         d4 acc[RM][BNB];
 #pragma unroll
         for (int mm = 0; mm < RM; ++mm)
@@ -386,8 +658,8 @@ __device__ __forceinline__ void rec64_tile(const DevDesc &d, int j0, double *lds
             double a[KG][RM];
 #pragma unroll
             for (int s = 0; s < KG; ++s) {
-                if (lb0 + s < K)
-                    load_run<RM>(a[s], U1 + lrow + (size_t)(lb0 + s) * ldu, rvalid);
+                if (!GUARD || lb0 + s < K)
+                    load_rows<RM, GUARD>(a[s], U1 + wrow + (size_t)(lb0 + s) * ldu, c, rvalid);
                 else
 #pragma unroll
                     for (int mm = 0; mm < RM; ++mm) a[s][mm] = 0.0;
@@ -397,26 +669,20 @@ __device__ __forceinline__ void rec64_tile(const DevDesc &d, int j0, double *lds
                 const int l = lb0 + s;
 #pragma unroll
                 for (int jb = 0; jb < BNB; ++jb) {
-                    const double b = (l < K) ? P[l * PW + jb * 16 + c] : 0.0;
+                    const double b = (!GUARD || l < K) ? P[l * PW + jb * 16 + c] : 0.0;
 #pragma unroll
                     for (int mm = 0; mm < RM; ++mm) acc[mm][jb] = mfma64(a[s][mm], b, acc[mm][jb]);
                 }
             }
         }
 
-        const int orow = wrow + 4 * RM * g;
-        const int ovalid = M - orow;
-        if (ovalid > 0) {
 #pragma unroll
-            for (int jb = 0; jb < BNB; ++jb) {
-                if (!colok[jb]) continue;
-                double o[4 * RM];
+        for (int jb = 0; jb < BNB; ++jb) {
+            if (GUARD && !colok[jb]) continue;
+            d4 o[RM];
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-#pragma unroll
-                    for (int mm = 0; mm < RM; ++mm) o[RM * v + mm] = acc[mm][jb][v];
-                store_run<4 * RM>(W + orow + coff[jb], o, ovalid, true);
-            }
+            for (int mm = 0; mm < RM; ++mm) o[mm] = acc[mm][jb];
+            store_rows<RM, GUARD>(W + wrow + coff[jb], o, g, rvalid, true);
         }
     }
     __syncthreads();   // P is reused by the next tile of a persistent workgroup
@@ -425,25 +691,39 @@ __device__ __forceinline__ void rec64_tile(const DevDesc &d, int j0, double *lds
 // ---------------------------------------------------------------------------
 // Dispatch over the compiled variants.
 
-template <int KIND, int P1, int P2, int P3, int P4>
-__device__ __forceinline__ void run_variant(const DevDesc &d, int p0, double *lds)
+template <int KIND, int P1, int P2, int P3, int P4, bool GUARD>
+__device__ __forceinline__ void run_variant_g(const DevDesc &d, int p0, double *lds)
 {
     if constexpr (KIND == K_DTS64)
-        dts64_tile<P1, P2, P3>(d, p0);
+        dts64_tile<P1, P2, P3, GUARD>(d, p0);
     else if constexpr (KIND == K_INN64)
-        inn64_tile<P1, P2, P3, P4>(d, p0, lds);
+        inn64_tile<P1, P2, P3, P4, GUARD>(d, p0, lds);
     else if constexpr (KIND == K_REC64)
-        rec64_tile<P1, P2, P3>(d, p0, lds);
+        rec64_tile<P1, P2, P3, GUARD>(d, p0, lds);
+    else if constexpr (KIND == K_DTSL)
+        dtsl_tile<P1, P2, P3, GUARD>(d, p0, lds);
+    else if constexpr (KIND == K_INNL)
+        innl_tile<P1, P2, P3, P4, GUARD>(d, p0, lds);
+}
+
+template <int KIND, int P1, int P2, int P3, int P4>
+__device__ __forceinline__ void run_variant(const DevDesc &d, int p0, bool edge, double *lds)
+{
+    if (edge)
+        run_variant_g<KIND, P1, P2, P3, P4, true>(d, p0, lds);
+    else
+        run_variant_g<KIND, P1, P2, P3, P4, false>(d, p0, lds);
 }
 
 __device__ __forceinline__ void run_tile(const DevDesc *__restrict__ descs, const Tile &t, double *lds)
 {
     if (t.variant <= 0) return;
     const DevDesc d = descs[t.desc];
+    const bool edge = (t.flags & kTileEdge) != 0;
     switch (t.variant) {
 #define LRBG_CASE(id, kind, p1, p2, p3, p4) \
     case id:                                \
-        run_variant<kind, p1, p2, p3, p4>(d, t.p0, lds); break;
+        run_variant<kind, p1, p2, p3, p4>(d, t.p0, edge, lds); break;
         LRBG_VARIANTS(LRBG_CASE)
 #undef LRBG_CASE
     default:
@@ -451,10 +731,18 @@ __device__ __forceinline__ void run_tile(const DevDesc *__restrict__ descs, cons
     }
 }
 
+// Out-of-line tile call for the persistent kernel: keeps each variant's
+// register state out of the persistent loop.
+__device__ __noinline__ void run_tile_call(const DevDesc *__restrict__ descs, const Tile *tp, double *lds)
+{
+    const Tile t = *tp;
+    run_tile(descs, t, lds);
+}
+
 // One workgroup per tile.  The host lays the tile list out so that tile t
 // lands on XCD t % 8 under the hardware's round-robin dispatch.
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) lrbg_grouped_kernel(const DevDesc *__restrict__ descs,
-                                                                const Tile *__restrict__ tiles, int ntiles)
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+lrbg_grouped_kernel(const DevDesc *__restrict__ descs, const Tile *__restrict__ tiles, int ntiles)
 {
     __shared__ double lds[kLdsBytes / 8];
     const int t = blockIdx.x;
@@ -467,10 +755,9 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
 // round-robin dispatch), then steals from the other queues.  qinfo holds the
 // 9 queue offsets into `tiles`.  Every workgroup leaves once all 8 counters
 // have passed their queue lengths, so the grid always drains.
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) lrbg_persistent_kernel(const DevDesc *__restrict__ descs,
-                                                                   const Tile *__restrict__ tiles,
-                                                                   const int32_t *__restrict__ qinfo,
-                                                                   int32_t *counters)
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+lrbg_persistent_kernel(const DevDesc *__restrict__ descs, const Tile *__restrict__ tiles,
+                       const int32_t *__restrict__ qinfo, int32_t *counters)
 {
     __shared__ double lds[kLdsBytes / 8];
     __shared__ int32_t next;
@@ -484,8 +771,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
             const int32_t idx = next;
             __syncthreads();
             if (idx >= qlen) break;
-            const Tile tl = tiles[qbeg + idx];
-            run_tile(descs, tl, lds);
+            run_tile_call(descs, tiles + qbeg + idx, lds);
         }
     }
 }

@@ -144,12 +144,23 @@ def test_cycle_rejected():
     assert status([d1, d2]) == lrbg.LRBG_EINVAL
 
 
-def test_tile_counts():
-    # DENSE_TS b=1024, r=16 default variant: 256 rows per tile -> 4 tiles
-    st = lrbg.lrbg_schedule_stats([mk(m=1024, n=16, k=1024)])
-    assert st["tiles"] % 8 == 0 and st["tiles"] >= 4
-    st = lrbg.lrbg_schedule_stats([mk(m=1024, n=16, k=1024)], flags=lrbg.LRBG_PLAN_PERSISTENT)
+def test_tile_counts(tmp_path):
+    # DENSE_TS b=1024, r=16 forced to 256-row tiles (RM=4) through a tuning cache
+    cache = tmp_path / "t.tune"
+    cache.write_text("0 0 1024 16 dts64_rm4_rn1_kg8 0\n")
+    st = lrbg.lrbg_schedule_stats([mk(m=1024, n=16, k=1024)], tune_cache=str(cache))
+    assert st["tiles"] == 32         # one product: its 4 tiles share one XCD bin, 8 slots per row
+    st = lrbg.lrbg_schedule_stats([mk(m=1024, n=16, k=1024)], tune_cache=str(cache),
+                                  flags=lrbg.LRBG_PLAN_PERSISTENT)
     assert st["tiles"] == 4
+    # RECOMP 512 x 512, rank 32, 64-column tiles -> 8 tiles
+    cache.write_text("2 0 512 32 rec64_rm2_bn4_kg8 0\n")
+    st = lrbg.lrbg_schedule_stats([mk("recomp", m=512, n=512, k=32)], tune_cache=str(cache),
+                                  flags=lrbg.LRBG_PLAN_PERSISTENT)
+    assert st["tiles"] == 8
+    # an unknown variant name falls back to the built-in choice
+    cache.write_text("0 0 1024 16 no_such_variant 0\n")
+    assert lrbg.lrbg_schedule_stats([mk(m=1024, n=16, k=1024)], tune_cache=str(cache))["tiles"] > 0
 
 
 def test_null_host_arrays_rejected():

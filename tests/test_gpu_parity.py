@@ -163,7 +163,8 @@ def test_recomp_normal(m, n, k):
 
 def _variants():
     lrbg.load()
-    return [(i, n) for i, n in enumerate(lrbg.lrbg_variant_names()) if n != "nop" and not n.startswith(("dts3", "inn3"))]
+    return [(i, n) for i, n in enumerate(lrbg.lrbg_variant_names())
+            if n != "nop" and not n.startswith(("dts3", "inn3"))]
 
 
 def _variant_params():
@@ -175,7 +176,7 @@ def _variant_params():
 
 @pytest.mark.parametrize("vid,name", _variant_params())
 def test_every_variant_forced(vid, name):
-    if name.startswith("dts64"):
+    if name.startswith(("dts64", "dtsl")):
         rn = int(name.split("_rn")[1].split("_")[0])
         n = min(16 * rn, 128) - 3
         m = k = 300
@@ -184,9 +185,10 @@ def test_every_variant_forced(vid, name):
         assert np.array_equal(C, Cref)
         C, Cref, D = _dts_case(m, k, n, False, vid, tune=tune)
         assert oracle.normalized_error(C, Cref, D) <= TOL
-    elif name.startswith("inn64"):
+    elif name.startswith(("inn64", "innl")):
         rj = int(name.split("_rj")[1].split("_")[0])
-        n = min(16 * rj, 128) - 1
+        wc = 4 // int(name.split("_wr")[1].split("_")[0]) if "_wr" in name else 1
+        n = min(16 * rj * wc, 128) - 1
         m = 45
         k = 333
         tune = cache_for(name, 1, 0, bucket(k, 64), bucket(max(m, n), 8))
