@@ -9,7 +9,13 @@ kernel over every tile).  Printed: one JSON line with the throughput, the
 roofline of the grouped kernel and the CPU oracle's rate on a bounded,
 stratified sample of the same workload.
 
-  python bench.py [--steps K] [--warmup W] [--config grouped|dense|chain|chain-bf16x3]
+Extra fields measure the other workloads on the same GPU: a uniform dense x
+skinny batch (64 x 256x256 . 256x16, buffer sets rotated so the 38 MB batch
+does not sit in the 256 MB last-level cache) and the low-rank x low-rank
+chain (4096 instances, b = 512, r = 32: inner products, then recompression).
+
+  python bench.py [--steps K] [--warmup W] [--extras/--no-extras]
+  python bench.py --calibrate-copy      # plain 1 GiB device copy (counter scaling)
 """
 from __future__ import annotations
 
@@ -126,6 +132,69 @@ def run_grouped(args):
     return line
 
 
+def run_dense_uniform(steps=200, warmup=20, sets=16):
+    """64 x (256x256 . 256x16); `sets` independent buffer sets (> 2x the
+    last-level cache in total) replayed round-robin."""
+    import torch
+    from paper_2311_07602_amd import lrbg, workloads
+    stream = torch.cuda.current_stream()
+    ws = [workloads.dense_uniform(64, 256, 16, seed=11 + i) for i in range(sets)]
+    plans = [lrbg.Plan(w.descs) for w in ws]
+    st = plans[0].stats()
+    for i in range(warmup):
+        plans[i % sets].execute(stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(steps):
+        plans[i % sets].execute(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    for p in plans:
+        p.close()
+    roof = max(st["useful_flops"] / (PEAK_FP64_TFLOPS * 1e12), st["hbm_bytes"] / (PEAK_HBM_GBS * 1e9)) * 1e3
+    return {"workload": "64 x (A 256x256 . U 256x16), FP64, N(0,1), 16 rotated buffer sets",
+            "ms_per_step": round(ms, 5), "GFLOP/s": round(st["useful_flops"] / ms / 1e6, 1),
+            "GB/s": round(st["hbm_bytes"] / ms / 1e6, 1), "roofline_ms": round(roof, 5),
+            "frac_of_roofline_time": round(roof / ms, 4),
+            "note": "launch-inclusive (one graph replay per step)"}
+
+
+def run_chain(count=4096, b=512, r=32, steps=20, warmup=3, prec="fp64"):
+    """Low-rank x low-rank chain: T = V1^T U2 (level 1), W = U1 (T V2^T)
+    (level 2), both levels in one captured graph."""
+    import torch
+    from paper_2311_07602_amd import lrbg, workloads
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    w = workloads.chain(count, b, r, prec=prec)
+    torch.cuda.synchronize()
+    log(f"[bench] chain workload ({prec}) built in {time.perf_counter() - t0:.1f} s")
+    plan = lrbg.Plan(w.descs)
+    st = plan.stats()
+    ms, _ = time_plan(plan, steps, warmup, stream)
+    plan.close()
+    f, by = st["useful_flops"], st["hbm_bytes"]
+    roof = max(f / (PEAK_FP64_TFLOPS * 1e12), by / (PEAK_HBM_GBS * 1e9)) * 1e3
+    return {"workload": f"{count} x chain b={b} r={r} ({prec} inner, FP64 recompression)",
+            "levels": st["levels"], "ms_per_step": round(ms, 4), "GFLOP/s": round(f / ms / 1e6, 1),
+            "GB/s": round(by / ms / 1e6, 1), "roofline_ms": round(roof, 4),
+            "frac_of_roofline_time": round(roof / ms, 4), "bound": "hbm"}
+
+
+def calibrate_copy(nbytes=1 << 30, reps=5):
+    """A plain device-to-device copy of known size, for scaling the HBM
+    traffic counters (FETCH_SIZE / WRITE_SIZE) of the profiled kernels."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "copy", "bytes_read": nbytes, "bytes_written": nbytes, "reps": reps}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +206,8 @@ def main():
     ap.add_argument("--persistent", action="store_true")
     ap.add_argument("--mix", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the batched products are "
@@ -149,7 +220,13 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     lrbg.load()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     line = run_grouped(args)
+    if not args.no_extras:
+        log("[bench] extra workloads ...")
+        line["extra"] = {"dense_uniform": run_dense_uniform(), "chain_fp64": run_chain()}
     print(json.dumps(line), flush=True)
 
 

@@ -62,7 +62,7 @@ static std::string variant_name(int v)
     switch (vi.kind) {
     case K_DTS64: snprintf(buf, sizeof buf, "dts64_rm%d_rn%d_kg%d", vi.p1, vi.p2, vi.p3); break;
     case K_INN64: snprintf(buf, sizeof buf, "inn64_ri%d_rj%d_ks%d_kg%d", vi.p1, vi.p2, vi.p3, vi.p4); break;
-    case K_REC64: snprintf(buf, sizeof buf, "rec64_rm%d_bn%d_kg%d", vi.p1, vi.p2, vi.p3); break;
+    case K_REC64: snprintf(buf, sizeof buf, "rec64_rb%d_bn%d_kg%d", vi.p1, vi.p2, vi.p3); break;
     case K_DTS3: snprintf(buf, sizeof buf, "dts3_rm%d_rn%d", vi.p1, vi.p2); break;
     case K_INN3: snprintf(buf, sizeof buf, "inn3_ri%d_rj%d_ks%d", vi.p1, vi.p2, vi.p3); break;
     case K_DTSL: snprintf(buf, sizeof buf, "dtsl_rm%d_rn%d_kg%d", vi.p1, vi.p2, vi.p3); break;
@@ -138,10 +138,10 @@ static void tiles_of(int v, const lrbg_desc &d, std::vector<int32_t> &p0s, std::
         step = 16 * vi.p2; extent = d.n; kc = 4 * vi.p3; break;
     default: return;
     }
-    const bool ktail = d.k % kc != 0;
-    // RECOMP: every row group of 16 RM rows must be full, and so must the
+    const bool ktail = d.k % kc != 0 || d.k == 0;
+    // RECOMP: every row group of 32 RB rows must be full, and so must the
     // tile's columns (block-type W columns).
-    const bool rec_rows_ragged = vi.kind == K_REC64 && d.m % (16 * vi.p1) != 0;
+    const bool rec_rows_ragged = vi.kind == K_REC64 && d.m % (32 * vi.p1) != 0;
     for (int p = 0; p < extent; p += step) {
         bool e = ktail || rec_rows_ragged;
         if ((rows_full_needed || vi.kind == K_REC64) && p + step > extent) e = true;

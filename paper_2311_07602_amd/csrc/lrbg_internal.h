@@ -37,7 +37,7 @@ enum Kind : int32_t {
     K_NOP = 0,
     K_DTS64 = 1,   // DENSE_TS, FP64 MFMA          params: RM, RN, KG
     K_INN64 = 2,   // INNER, FP64 MFMA             params: RI, RJ, KS, KG
-    K_REC64 = 3,   // RECOMP, FP64 MFMA            params: RM, BNB, KG
+    K_REC64 = 3,   // RECOMP, FP64 MFMA            params: RB, BNB, KG
     K_DTS3 = 4,    // DENSE_TS, bf16x3 split MFMA  params: RM, RN
     K_INN3 = 5,    // INNER, bf16x3 split MFMA     params: RI, RJ, KS
     K_DTSL = 6,    // DENSE_TS, FP64, U in LDS     params: RM, RN, KG
@@ -66,12 +66,12 @@ constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies
     X(10, K_INN64, 2, 2, 2, 8)        \
     X(11, K_INN64, 2, 4, 2, 4)        \
     X(12, K_INN64, 1, 4, 4, 4)        \
-    X(13, K_REC64, 2, 4, 2, 0)        \
-    X(14, K_REC64, 2, 4, 8, 0)        \
-    X(15, K_REC64, 1, 4, 8, 0)        \
-    X(16, K_REC64, 2, 2, 8, 0)        \
-    X(17, K_REC64, 2, 8, 8, 0)        \
-    X(18, K_REC64, 4, 4, 8, 0)        \
+    X(13, K_REC64, 1, 4, 2, 0)        \
+    X(14, K_REC64, 1, 4, 8, 0)        \
+    X(15, K_REC64, 2, 4, 4, 0)        \
+    X(16, K_REC64, 1, 2, 8, 0)        \
+    X(17, K_REC64, 1, 8, 4, 0)        \
+    X(18, K_REC64, 2, 2, 8, 0)        \
     X(19, K_DTSL, 2, 2, 8, 0)         \
     X(20, K_DTSL, 4, 2, 4, 0)         \
     X(21, K_DTSL, 2, 4, 4, 0)         \

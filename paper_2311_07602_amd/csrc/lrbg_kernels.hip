@@ -596,16 +596,20 @@ __device__ __forceinline__ void innl_tile(const DevDesc &d, int i0, double *lds)
 // ---------------------------------------------------------------------------
 // RECOMP, FP64.  W = U1 (S V2^T).  Workgroup tile: columns [j0, j0 + 16 BNB)
 // x all rows.  First P = S V2^T restricted to the tile's columns (k x 16 BNB)
-// is formed once on the matrix cores into LDS; then the waves sweep row
-// groups of 16 RM rows, streaming U1 (L2-resident, shared by the product's
-// column tiles) against P and writing W with non-temporal stores: the b x b
-// output is the dominant HBM traffic.
-template <int RM, int BNB, int KG, bool GUARD>
+// is formed once on the matrix cores into LDS.  The waves then sweep row
+// groups of 32 RB rows computing the transposed product W^T = P^T U1^T:
+// in that orientation the matrix-core output puts 16 consecutive W rows on
+// 16 consecutive lanes, and with two row-interleaved blocks (rows 2c, 2c+1)
+// each lane stores 16 contiguous bytes, so one store instruction writes four
+// contiguous 256-byte column segments of W (non-temporal: the b x b output
+// is the dominant HBM traffic).  U1 row pairs (L2-resident, shared by the
+// product's column tiles) are prefetched one step ahead across row groups.
+template <int RB, int BNB, int KG, bool GUARD>
 __device__ __forceinline__ void rec64_tile(const DevDesc &d, int j0, double *lds)
 {
     constexpr int PW = 16 * BNB;
     constexpr int KSTEP = 4 * KG;
-    static_assert(RM == 1 || RM % 2 == 0, "RM is 1 or even");
+    constexpr int RG = 32 * RB;
     const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
     const int M = d.m, N = d.n, K = d.k;
     const size_t ldu = (size_t)d.lda, ldv = (size_t)d.ldb, lds_ = (size_t)d.lds, ldw = (size_t)d.ldc;
@@ -623,66 +627,107 @@ __device__ __forceinline__ void rec64_tile(const DevDesc &d, int j0, double *lds
         const gcp Sp = S + (lok ? l : 0);
         const gcp Vp = V2 + (jok ? jj : 0);
         d4 p = d4{0.0, 0.0, 0.0, 0.0};
-        for (int q0 = 0; q0 < K; q0 += 4) {
-            const int q = q0 + g;
-            const bool qok = q < K;
-            const size_t qc = (size_t)(qok ? q : 0);
-            const double sv = Sp[qc * lds_], vv = Vp[qc * ldv];
-            p = mfma64((lok && qok) ? sv : 0.0, (jok && qok) ? vv : 0.0, p);
+        // all loads of a batch of QB steps are issued before its MFMAs, so a
+        // block waits for one memory round trip per batch, not per step
+        constexpr int QB = 8;
+        for (int q0 = 0; q0 < K; q0 += 4 * QB) {
+            double sv[QB], vv[QB];
+#pragma unroll
+            for (int t = 0; t < QB; ++t) {
+                const int q = q0 + 4 * t + g;
+                const bool qok = q < K;
+                const size_t qc = (size_t)(qok ? q : 0);
+                sv[t] = Sp[qc * lds_];
+                vv[t] = Vp[qc * ldv];
+                sv[t] = (lok && qok) ? sv[t] : 0.0;
+                vv[t] = (jok && qok) ? vv[t] : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < QB; ++t) p = mfma64(sv[t], vv[t], p);
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) P[(lb * 16 + 4 * v + g) * PW + jb * 16 + c] = p[v];
     }
     __syncthreads();
 
-    bool colok[BNB];
-    size_t coff[BNB];
+    // ---- W^T = P^T U1^T, flattened over (row group, k chunk) with prefetch
+    auto load_u = [&](int wrow, int l0, double (&u)[RB][KG][2]) {
 #pragma unroll
-    for (int jb = 0; jb < BNB; ++jb) {
-        const int col = j0 + jb * 16 + c;
-        colok[jb] = col < N;
-        coff[jb] = (size_t)col * ldw;
-    }
-
-    for (int rg = w; rg * 16 * RM < M; rg += kWaves) {
-        const int wrow = rg * 16 * RM;
-        const int rvalid = M - wrow;
-        d4 acc[RM][BNB];
-#pragma unroll
-        for (int mm = 0; mm < RM; ++mm)
-#pragma unroll
-            for (int jb = 0; jb < BNB; ++jb) acc[mm][jb] = d4{0.0, 0.0, 0.0, 0.0};
-
-        for (int l0 = 0; l0 < K; l0 += KSTEP) {
-            const int lb0 = l0 + KG * g;
-            double a[KG][RM];
+        for (int rb = 0; rb < RB; ++rb) {
+            const int row0 = wrow + 32 * rb + 2 * c;
 #pragma unroll
             for (int s = 0; s < KG; ++s) {
-                if (!GUARD || lb0 + s < K)
-                    load_rows<RM, GUARD>(a[s], U1 + wrow + (size_t)(lb0 + s) * ldu, c, rvalid);
+                const int l = l0 + KG * g + s;
+                if (!GUARD || l < K)
+                    load_run<2, GUARD>(u[rb][s], U1 + row0 + (size_t)l * ldu, M - row0);
                 else
-#pragma unroll
-                    for (int mm = 0; mm < RM; ++mm) a[s][mm] = 0.0;
-            }
-#pragma unroll
-            for (int s = 0; s < KG; ++s) {
-                const int l = lb0 + s;
-#pragma unroll
-                for (int jb = 0; jb < BNB; ++jb) {
-                    const double b = (!GUARD || l < K) ? P[l * PW + jb * 16 + c] : 0.0;
-#pragma unroll
-                    for (int mm = 0; mm < RM; ++mm) acc[mm][jb] = mfma64(a[s][mm], b, acc[mm][jb]);
-                }
+                    u[rb][s][0] = u[rb][s][1] = 0.0;
             }
         }
+    };
+    d4 acc[RB][2][BNB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+#pragma unroll
+            for (int bi = 0; bi < BNB; ++bi) acc[rb][e][bi] = d4{0.0, 0.0, 0.0, 0.0};
 
+    int rg = w, l0 = 0;
+    double u[RB][KG][2];
+    if (rg * RG < M) load_u(rg * RG, 0, u);
+    while (rg * RG < M) {
+        int nl0 = l0 + KSTEP, nrg = rg;
+        if (nl0 >= K) {
+            nl0 = 0;
+            nrg = rg + kWaves;
+        }
+        const bool has_next = nrg * RG < M;
+        double un[RB][KG][2];
+        if (has_next) load_u(nrg * RG, nl0, un);
 #pragma unroll
-        for (int jb = 0; jb < BNB; ++jb) {
-            if (GUARD && !colok[jb]) continue;
-            d4 o[RM];
+        for (int s = 0; s < KG; ++s) {
+            const int l = l0 + KG * g + s;
+            double pa[BNB];
 #pragma unroll
-            for (int mm = 0; mm < RM; ++mm) o[mm] = acc[mm][jb];
-            store_rows<RM, GUARD>(W + wrow + coff[jb], o, g, rvalid, true);
+            for (int bi = 0; bi < BNB; ++bi) pa[bi] = (!GUARD || l < K) ? P[l * PW + bi * 16 + c] : 0.0;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int e = 0; e < 2; ++e)
+#pragma unroll
+                    for (int bi = 0; bi < BNB; ++bi) acc[rb][e][bi] = mfma64(pa[bi], u[rb][s][e], acc[rb][e][bi]);
+        }
+        if (nl0 == 0) {   // row group complete: store and reset
+            const int wrow = rg * RG;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const int row0 = wrow + 32 * rb + 2 * c;
+#pragma unroll
+                for (int bi = 0; bi < BNB; ++bi)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int col = j0 + bi * 16 + 4 * v + g;
+                        if (GUARD && col >= N) continue;
+                        const double o[2] = {acc[rb][0][bi][v], acc[rb][1][bi][v]};
+                        store_run<2, GUARD>(W + row0 + (size_t)col * ldw, o, M - row0, true);
+                    }
+#pragma unroll
+                for (int e = 0; e < 2; ++e)
+#pragma unroll
+                    for (int bi = 0; bi < BNB; ++bi) acc[rb][e][bi] = d4{0.0, 0.0, 0.0, 0.0};
+            }
+        }
+        rg = nrg;
+        l0 = nl0;
+        if (has_next) {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int s = 0; s < KG; ++s) {
+                    u[rb][s][0] = un[rb][s][0];
+                    u[rb][s][1] = un[rb][s][1];
+                }
         }
     }
     __syncthreads();   // P is reused by the next tile of a persistent workgroup

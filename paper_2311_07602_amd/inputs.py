@@ -106,6 +106,45 @@ def chain_instance(cfg: int, i: int, b: int, r: int) -> ChainInstance:
     return ChainInstance(U1, V1, U2, V2)
 
 
+def _one_blas_thread():
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:
+        pass
+
+
+def _chain_block(args):
+    cfg, lo, hi, b, r = args
+    out = np.empty((hi - lo, 4, r, b))
+    for i in range(lo, hi):
+        ci = chain_instance(cfg, i, b, r)
+        for t, x in enumerate((ci.U1, ci.V1, ci.U2, ci.V2)):
+            out[i - lo, t] = x.T
+    return lo, out
+
+
+def chain_instances(cfg: int, count: int, b: int, r: int, workers: int = 8) -> np.ndarray:
+    """[count, 4, r, b] array: instance i's U1, V1, U2, V2, each stored
+    column-major (row j of the last two axes is column j of the operand).
+    Generated in worker processes (spawned, so no device state is inherited);
+    every instance comes from its own seed, so the result does not depend on
+    the number of workers."""
+    out = np.empty((count, 4, r, b))
+    step = max(1, min(256, (count + workers - 1) // max(workers, 1)))
+    jobs = [(cfg, lo, min(lo + step, count), b, r) for lo in range(0, count, step)]
+    if workers <= 1 or count < 256:
+        for j in jobs:
+            lo, blk = _chain_block(j)
+            out[lo:lo + len(blk)] = blk
+        return out
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(workers, initializer=_one_blas_thread) as pool:
+        for lo, blk in pool.imap_unordered(_chain_block, jobs):
+            out[lo:lo + len(blk)] = blk
+    return out
+
+
 def grouped_shapes(count: int, seed: int = 3) -> List[Tuple[int, int]]:
     """(b, r) for each instance of the uneven grouped batch.
 

@@ -98,11 +98,7 @@ def chain(count: int = 4096, b: int = 512, r: int = 32, cfg: int = 2, device="cu
     """
     import torch
     per = 4 * b * r
-    host = np.empty((count, 4, r, b))                    # [i, operand, col, row]
-    for i in range(count):
-        ci = inputs.chain_instance(cfg, i, b, r)
-        for t, x in enumerate((ci.U1, ci.V1, ci.U2, ci.V2)):
-            host[i, t] = x.T
+    host = inputs.chain_instances(cfg, count, b, r)      # [i, operand, col, row]
     pin = torch.from_numpy(host.reshape(-1)).to(device)
     del host
     small = None

@@ -154,7 +154,7 @@ def test_tile_counts(tmp_path):
                                   flags=lrbg.LRBG_PLAN_PERSISTENT)
     assert st["tiles"] == 4
     # RECOMP 512 x 512, rank 32, 64-column tiles -> 8 tiles
-    cache.write_text("2 0 512 32 rec64_rm2_bn4_kg8 0\n")
+    cache.write_text("2 0 512 32 rec64_rb1_bn4_kg8 0\n")
     st = lrbg.lrbg_schedule_stats([mk("recomp", m=512, n=512, k=32)], tune_cache=str(cache),
                                   flags=lrbg.LRBG_PLAN_PERSISTENT)
     assert st["tiles"] == 8
