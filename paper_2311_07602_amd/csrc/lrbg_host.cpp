@@ -63,8 +63,8 @@ static std::string variant_name(int v)
     case K_DTS64: snprintf(buf, sizeof buf, "dts64_rm%d_rn%d_kg%d", vi.p1, vi.p2, vi.p3); break;
     case K_INN64: snprintf(buf, sizeof buf, "inn64_ri%d_rj%d_ks%d_kg%d", vi.p1, vi.p2, vi.p3, vi.p4); break;
     case K_REC64: snprintf(buf, sizeof buf, "rec64_rb%d_bn%d_kg%d", vi.p1, vi.p2, vi.p3); break;
-    case K_DTS3: snprintf(buf, sizeof buf, "dts3_rm%d_rn%d", vi.p1, vi.p2); break;
-    case K_INN3: snprintf(buf, sizeof buf, "inn3_ri%d_rj%d_ks%d", vi.p1, vi.p2, vi.p3); break;
+    case K_DTS3: snprintf(buf, sizeof buf, "dts3_rm%d_rn%d_pf%d", vi.p1, vi.p2, vi.p3); break;
+    case K_INN3: snprintf(buf, sizeof buf, "inn3_ri%d_rj%d_ks%d_pf%d", vi.p1, vi.p2, vi.p3, vi.p4); break;
     case K_DTSL: snprintf(buf, sizeof buf, "dtsl_rm%d_rn%d_kg%d", vi.p1, vi.p2, vi.p3); break;
     case K_INNL: snprintf(buf, sizeof buf, "innl_ri%d_rj%d_wr%d_kg%d", vi.p1, vi.p2, vi.p3, vi.p4); break;
     default: snprintf(buf, sizeof buf, "v%d", v);
@@ -200,6 +200,19 @@ static int default_variant(const lrbg_desc &d)
         if (rr <= 64) return pick({26, 11});
         return pick({25, 28});
     }
+    if (kind == K_DTS3) {
+        if (d.n <= 16) return pick({d.m >= 256 ? 29 : 33});
+        if (d.n <= 32) return pick({30});
+        if (d.n <= 64) return pick({31});
+        return pick({32});
+    }
+    if (kind == K_INN3) {
+        const int rr = std::max(d.m, d.n);
+        if (rr <= 16) return pick({34});
+        if (rr <= 32) return pick({35});
+        if (rr <= 64) return pick({36});
+        return pick({37});
+    }
     if (kind == K_REC64) {
         if (d.k <= 16) return pick({13});
         if (d.k <= 32) return pick({14});
@@ -259,7 +272,6 @@ static lrbg_status validate_one(const lrbg_desc &d, int64_t i)
     if (kind_of(d.op, d.prec) == K_NOP)
         return fail(LRBG_EUNSUPPORTED, "product %lld: op %d has no bf16x3 form (recompression stays FP64)",
                     (long long)i, d.op);
-    if (d.prec == LRBG_BF16X3) return fail(LRBG_EUNSUPPORTED, "product %lld: bf16x3 kernels not built", (long long)i);
     int b, r;
     bucket_dims(d, b, r);
     const int rankdims[3][2] = {{d.n, 0}, {d.m, d.n}, {d.k, 0}};

@@ -38,8 +38,8 @@ enum Kind : int32_t {
     K_DTS64 = 1,   // DENSE_TS, FP64 MFMA          params: RM, RN, KG
     K_INN64 = 2,   // INNER, FP64 MFMA             params: RI, RJ, KS, KG
     K_REC64 = 3,   // RECOMP, FP64 MFMA            params: RB, BNB, KG
-    K_DTS3 = 4,    // DENSE_TS, bf16x3 split MFMA  params: RM, RN
-    K_INN3 = 5,    // INNER, bf16x3 split MFMA     params: RI, RJ, KS
+    K_DTS3 = 4,    // DENSE_TS, bf16x3 split MFMA  params: RM, RN, PF (prefetch)
+    K_INN3 = 5,    // INNER, bf16x3 split MFMA     params: RI, RJ, KS, PF
     K_DTSL = 6,    // DENSE_TS, FP64, U in LDS     params: RM, RN, KG
     K_INNL = 7,    // INNER, FP64, LDS-staged      params: RI, RJ, WR, KG
 };
@@ -81,9 +81,19 @@ constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies
     X(25, K_INNL, 4, 4, 2, 2)         \
     X(26, K_INNL, 2, 2, 2, 4)         \
     X(27, K_INNL, 2, 4, 4, 4)         \
-    X(28, K_INNL, 4, 4, 2, 3)
+    X(28, K_INNL, 4, 4, 2, 3)         \
+    X(29, K_DTS3, 4, 1, 0, 0)         \
+    X(30, K_DTS3, 2, 2, 1, 0)         \
+    X(31, K_DTS3, 2, 4, 0, 0)         \
+    X(32, K_DTS3, 1, 8, 0, 0)         \
+    X(33, K_DTS3, 1, 2, 1, 0)         \
+    X(34, K_INN3, 1, 1, 4, 1)         \
+    X(35, K_INN3, 2, 2, 4, 1)         \
+    X(36, K_INN3, 1, 4, 4, 1)         \
+    X(37, K_INN3, 1, 8, 4, 0)         \
+    X(38, K_INN3, 2, 2, 2, 1)
 
-constexpr int kNumVariants = 29;   // ids 0..28 (0 = no-op tile)
+constexpr int kNumVariants = 39;   // ids 0..38 (0 = no-op tile)
 
 struct VariantInfo {
     int32_t kind, p1, p2, p3, p4;

@@ -733,6 +733,337 @@ __device__ __forceinline__ void rec64_tile(const DevDesc &d, int j0, double *lds
     __syncthreads();   // P is reused by the next tile of a persistent workgroup
 }
 
+
+// ---------------------------------------------------------------------------
+// BF16x3 split precision (FP32 operands, FP64 output).  Each FP32 value x is
+// split as x = x0 + x1 + x2 with x0 = RNE_bf16(x), x1 = RNE_bf16(x - x0),
+// x2 = RNE_bf16(x - x0 - x1); the differences are exact in FP32, and three
+// 8-bit-significand terms hold the 24-bit significand.  A product keeps the
+// six term pairs of order i + j <= 2 (Henry, Tang, Heinecke, ARITH 2019),
+// accumulated on v_mfma_f32_16x16x32_bf16 into three FP32 accumulators by
+// order (hi: x0 y0; mid: x0 y1 + x1 y0; lo: x0 y2 + x1 y1 + x2 y0), which are
+// added in FP64 smallest first.  The dropped terms are below 2^-24 relative.
+// The bf16 matrix core takes 8 consecutive k per lane: lane l = c + 16 g
+// holds A(row c, k 8g..8g+7) and B(k 8g..8g+7, col c) and receives D(4g + v,
+// c) as item v.
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+typedef const GLB float *gcf;
+typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+
+__device__ __forceinline__ gcf ginf(const void *p) { return (gcf)(p); }
+
+// Round-to-nearest-even of an FP32 value to bfloat16, from the encoding:
+// add half an ulp of the kept 8 bits (7 fraction bits) plus the kept LSB,
+// truncate.  Infinities and NaN keep their class.
+__device__ __forceinline__ unsigned short bf16_rne(float x)
+{
+    const unsigned u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ float bf16_val(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+struct Split3 {
+    bf8 t0, t1, t2;
+};
+
+__device__ __forceinline__ Split3 split3(const float (&x)[8])
+{
+    us8 a, b, c;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const unsigned short h0 = bf16_rne(x[t]);
+        const float r1 = x[t] - bf16_val(h0);
+        const unsigned short h1 = bf16_rne(r1);
+        const float r2 = r1 - bf16_val(h1);
+        a[t] = h0;
+        b[t] = h1;
+        c[t] = bf16_rne(r2);
+    }
+    Split3 s;
+    s.t0 = __builtin_bit_cast(bf8, a);
+    s.t1 = __builtin_bit_cast(bf8, b);
+    s.t2 = __builtin_bit_cast(bf8, c);
+    return s;
+}
+
+__device__ __forceinline__ f4 mfma_bf16(bf8 a, bf8 b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// acc[0] hi, acc[1] mid, acc[2] lo
+__device__ __forceinline__ void mfma_x6(const Split3 &a, const Split3 &b, f4 (&acc)[3])
+{
+    acc[0] = mfma_bf16(a.t0, b.t0, acc[0]);
+    acc[1] = mfma_bf16(a.t0, b.t1, acc[1]);
+    acc[1] = mfma_bf16(a.t1, b.t0, acc[1]);
+    acc[2] = mfma_bf16(a.t0, b.t2, acc[2]);
+    acc[2] = mfma_bf16(a.t1, b.t1, acc[2]);
+    acc[2] = mfma_bf16(a.t2, b.t0, acc[2]);
+}
+
+__device__ __forceinline__ double combine3(const f4 (&acc)[3], int v)
+{
+    return ((double)acc[2][v] + (double)acc[1][v]) + (double)acc[0][v];
+}
+
+// 8 contiguous floats; with GUARD, elements at or beyond `valid` read 0.
+template <bool GUARD>
+__device__ __forceinline__ void load8f(float (&dst)[8], gcf p, int valid)
+{
+    if (!GUARD || valid >= 8) {
+        const f4u v0 = *reinterpret_cast<const GLB f4u *>(p);
+        const f4u v1 = *reinterpret_cast<const GLB f4u *>(p + 4);
+        dst[0] = v0.x; dst[1] = v0.y; dst[2] = v0.z; dst[3] = v0.w;
+        dst[4] = v1.x; dst[5] = v1.y; dst[6] = v1.z; dst[7] = v1.w;
+    } else {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) dst[t] = (t < valid) ? p[t] : 0.0f;
+    }
+}
+
+// INNER, bf16x3.  Same work split as the FP64 INNER tile: NG = 4 / KS output
+// groups of RI x RJ blocks, KS waves splitting 32-wide k chunks, FP64
+// partials reduced through LDS in a fixed order.
+template <int RI, int RJ, int KS, int PF, bool GUARD>
+__device__ __forceinline__ void inn3_tile(const DevDesc &d, int i0, double *lds)
+{
+    constexpr int NG = 4 / KS;
+    const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
+    const int og = w / KS, ks = w % KS;
+    const int M = d.m, N = d.n, K = d.k;
+    const size_t ldv = (size_t)d.lda, ldu = (size_t)d.ldb, ldt = (size_t)d.ldc;
+
+    const int rowbase = i0 + og * 16 * RI;
+    gcf Vp[RI], Up[RJ];
+    bool rok[RI], cok[RJ];
+#pragma unroll
+    for (int bi = 0; bi < RI; ++bi) {
+        const int col = rowbase + bi * 16 + c;
+        rok[bi] = col < M;
+        Vp[bi] = ginf(d.a) + (size_t)(rok[bi] ? col : 0) * ldv;
+    }
+#pragma unroll
+    for (int bj = 0; bj < RJ; ++bj) {
+        const int col = bj * 16 + c;
+        cok[bj] = col < N;
+        Up[bj] = ginf(d.b) + (size_t)(cok[bj] ? col : 0) * ldu;
+    }
+    f4 acc[RI][RJ][3];
+#pragma unroll
+    for (int bi = 0; bi < RI; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < RJ; ++bj)
+#pragma unroll
+            for (int o = 0; o < 3; ++o) acc[bi][bj][o] = f4{0.f, 0.f, 0.f, 0.f};
+
+    float a[RI][8], u[RJ][8];
+    auto load = [&](int k0, float (&aa)[RI][8], float (&uu)[RJ][8]) {
+        const int kb = k0 + 8 * g, kv = K - kb;
+#pragma unroll
+        for (int bi = 0; bi < RI; ++bi) {
+            load8f<GUARD>(aa[bi], Vp[bi] + kb, kv);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) aa[bi][t] = rok[bi] ? aa[bi][t] : 0.0f;
+        }
+#pragma unroll
+        for (int bj = 0; bj < RJ; ++bj) {
+            load8f<GUARD>(uu[bj], Up[bj] + kb, kv);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) uu[bj][t] = cok[bj] ? uu[bj][t] : 0.0f;
+        }
+    };
+    int k0 = ks * 32;
+    if (PF && k0 < K) load(k0, a, u);
+    for (; k0 < K; k0 += KS * 32) {
+        float an[RI][8], un[RJ][8];
+        const bool more = PF && k0 + KS * 32 < K;
+        if (!PF) load(k0, a, u);
+        if (more) load(k0 + KS * 32, an, un);
+        Split3 sa[RI];
+#pragma unroll
+        for (int bi = 0; bi < RI; ++bi) sa[bi] = split3(a[bi]);
+#pragma unroll
+        for (int bj = 0; bj < RJ; ++bj) {
+            const Split3 sb = split3(u[bj]);
+#pragma unroll
+            for (int bi = 0; bi < RI; ++bi) mfma_x6(sa[bi], sb, acc[bi][bj]);
+        }
+        if (more) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+#pragma unroll
+                for (int bi = 0; bi < RI; ++bi) a[bi][t] = an[bi][t];
+#pragma unroll
+                for (int bj = 0; bj < RJ; ++bj) u[bj][t] = un[bj][t];
+            }
+        }
+    }
+
+    double res[RI][RJ][4];
+#pragma unroll
+    for (int bi = 0; bi < RI; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < RJ; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) res[bi][bj][v] = combine3(acc[bi][bj], v);
+
+    if constexpr (KS > 1) {
+        constexpr int PER = RI * RJ * 4;
+        static_assert((KS - 1) * NG * PER * 64 * 8 <= kLdsBytes, "INNER reduction exceeds LDS");
+        if (ks > 0) {
+            double *slot = lds + (size_t)((og * (KS - 1) + ks - 1) * PER) * 64;
+#pragma unroll
+            for (int bi = 0; bi < RI; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < RJ; ++bj)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) slot[((bi * RJ + bj) * 4 + v) * 64 + lane] = res[bi][bj][v];
+        }
+        __syncthreads();
+        if (ks == 0) {
+#pragma unroll 1
+            for (int p = 1; p < KS; ++p) {
+                const double *slot = lds + (size_t)((og * (KS - 1) + p - 1) * PER) * 64;
+#pragma unroll
+                for (int bi = 0; bi < RI; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < RJ; ++bj)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) res[bi][bj][v] += slot[((bi * RJ + bj) * 4 + v) * 64 + lane];
+            }
+        }
+        __syncthreads();
+    }
+    if (ks != 0) return;
+#pragma unroll
+    for (int bi = 0; bi < RI; ++bi) {
+        const int orow = rowbase + bi * 16 + 4 * g;
+        const int ovalid = M - orow;
+        if (ovalid <= 0) continue;
+#pragma unroll
+        for (int bj = 0; bj < RJ; ++bj) {
+            if (!cok[bj]) continue;
+            double o[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) o[v] = res[bi][bj][v];
+            store_run<4, true>(gout(d.c) + orow + (size_t)(bj * 16 + c) * ldt, o, ovalid, false);
+        }
+    }
+}
+
+// DENSE_TS, bf16x3.  Wave w owns rows i0 + 16 RM w + [0, 16 RM); lane c loads
+// the RM consecutive rows RM c .. RM c + RM - 1 of each of its 8 columns, so
+// row block mm uses row RM c + mm and the lane's outputs are the 4 RM
+// contiguous rows 4 RM g .. 4 RM g + 4 RM - 1.  U columns are 8 contiguous
+// floats per lane.  No barriers.
+template <int RM, int RN, int PF, bool GUARD>
+__device__ __forceinline__ void dts3_tile(const DevDesc &d, int i0)
+{
+    static_assert(RM == 1 || RM == 2 || RM == 4, "RM in {1,2,4}");
+    const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
+    const int M = d.m, N = d.n, K = d.k;
+    const size_t lda = (size_t)d.lda, ldu = (size_t)d.ldb, ldc = (size_t)d.ldc;
+    const int wrow = i0 + 16 * RM * w;
+    if (GUARD && wrow >= M) return;
+    const int lrow = wrow + RM * c;
+    const int rvalid = M - lrow;
+    const gcf Ap = ginf(d.a) + lrow;
+    gcf Up[RN];
+    bool colok[RN];
+#pragma unroll
+    for (int jb = 0; jb < RN; ++jb) {
+        const int col = jb * 16 + c;
+        colok[jb] = col < N;
+        Up[jb] = ginf(d.b) + (size_t)(colok[jb] ? col : 0) * ldu;
+    }
+    f4 acc[RM][RN][3];
+#pragma unroll
+    for (int mm = 0; mm < RM; ++mm)
+#pragma unroll
+        for (int jb = 0; jb < RN; ++jb)
+#pragma unroll
+            for (int o = 0; o < 3; ++o) acc[mm][jb][o] = f4{0.f, 0.f, 0.f, 0.f};
+
+    float a[RM][8], u[RN][8];
+    auto load = [&](int k0, float (&aa)[RM][8], float (&uu)[RN][8]) {
+        const int kb = k0 + 8 * g, kv = K - kb;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            float r[RM];
+            if (!GUARD || (t < kv && rvalid >= RM)) {
+                const gcf p = Ap + (size_t)(kb + t) * lda;
+                if constexpr (RM == 4) {
+                    const f4u v = *reinterpret_cast<const GLB f4u *>(p);
+                    r[0] = v.x; r[1] = v.y; r[2] = v.z; r[3] = v.w;
+                } else if constexpr (RM == 2) {
+                    const f2u v = *reinterpret_cast<const GLB f2u *>(p);
+                    r[0] = v.x; r[1] = v.y;
+                } else {
+                    r[0] = p[0];
+                }
+            } else {
+#pragma unroll
+                for (int mm = 0; mm < RM; ++mm)
+                    r[mm] = (t < kv && mm < rvalid) ? Ap[(size_t)(kb + t) * lda + mm] : 0.0f;
+            }
+#pragma unroll
+            for (int mm = 0; mm < RM; ++mm) aa[mm][t] = r[mm];
+        }
+#pragma unroll
+        for (int jb = 0; jb < RN; ++jb) {
+            load8f<GUARD>(uu[jb], Up[jb] + kb, kv);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) uu[jb][t] = colok[jb] ? uu[jb][t] : 0.0f;
+        }
+    };
+    if (PF && K > 0) load(0, a, u);
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        float an[RM][8], un[RN][8];
+        const bool more = PF && k0 + 32 < K;
+        if (!PF) load(k0, a, u);
+        if (more) load(k0 + 32, an, un);
+        Split3 sa[RM];
+#pragma unroll
+        for (int mm = 0; mm < RM; ++mm) sa[mm] = split3(a[mm]);
+#pragma unroll
+        for (int jb = 0; jb < RN; ++jb) {
+            const Split3 sb = split3(u[jb]);
+#pragma unroll
+            for (int mm = 0; mm < RM; ++mm) mfma_x6(sa[mm], sb, acc[mm][jb]);
+        }
+        if (more) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+#pragma unroll
+                for (int mm = 0; mm < RM; ++mm) a[mm][t] = an[mm][t];
+#pragma unroll
+                for (int jb = 0; jb < RN; ++jb) u[jb][t] = un[jb][t];
+            }
+        }
+    }
+    // lane (c, g): MFMA row 4g + v of block mm is row wrow + RM (4g + v) + mm
+    const int orow = wrow + 4 * RM * g;
+    const int ovalid = M - orow;
+    if (GUARD && ovalid <= 0) return;
+#pragma unroll
+    for (int jb = 0; jb < RN; ++jb) {
+        if (!colok[jb]) continue;
+        double o[4 * RM];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int mm = 0; mm < RM; ++mm) o[RM * v + mm] = combine3(acc[mm][jb], v);
+        store_run<4 * RM, GUARD>(gout(d.c) + orow + (size_t)(jb * 16 + c) * ldc, o, ovalid, false);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Dispatch over the compiled variants.
 
@@ -749,6 +1080,10 @@ __device__ __forceinline__ void run_variant_g(const DevDesc &d, int p0, double *
         dtsl_tile<P1, P2, P3, GUARD>(d, p0, lds);
     else if constexpr (KIND == K_INNL)
         innl_tile<P1, P2, P3, P4, GUARD>(d, p0, lds);
+    else if constexpr (KIND == K_DTS3)
+        dts3_tile<P1, P2, P3, GUARD>(d, p0);
+    else if constexpr (KIND == K_INN3)
+        inn3_tile<P1, P2, P3, P4, GUARD>(d, p0, lds);
 }
 
 template <int KIND, int P1, int P2, int P3, int P4>
