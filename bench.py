@@ -183,6 +183,29 @@ def run_chain(count=4096, b=512, r=32, steps=20, warmup=3, prec="fp64"):
             "frac_of_roofline_time": round(roof / ms, 4), "bound": "hbm"}
 
 
+def run_serving(budget=64e9, slots=8, sat_requests=300, warm=200, measured=1000, rho=0.7):
+    """Continuous-batching loop: saturated request rate first (all requests
+    queued at t=0), then Poisson arrivals at rho x that rate; latency is
+    arrival -> completion, over the requests after the warm-up ones."""
+    import torch
+    from paper_2311_07602_amd import serve
+    ex = serve.GpuExecutor(slots=slots)
+    serve.Scheduler(ex, budget, slots).run(serve.make_requests(30, float("inf"), seed=100))   # warm-up
+    torch.cuda.synchronize()
+    sat = serve.summarize(serve.Scheduler(ex, budget, slots).run(
+        serve.make_requests(sat_requests, float("inf"), seed=101)))
+    mu = sat["requests_per_s"]
+    reqs = serve.make_requests(warm + measured, rho * mu, seed=102)
+    sch = serve.Scheduler(ex, budget, slots)
+    recs = sch.run(reqs)
+    load = serve.summarize(recs, skip=warm)
+    return {"workload": "Poisson arrivals, requests of 16..2048 instances (A.U and V1^T.U2 each, (b,r) as the "
+                        "uneven batch), FP64 or BF16x3 with p=0.5, operands device-resident, HBM budget "
+                        f"{budget / 1e9:.0f} GB, {slots} streams",
+            "saturated": sat, "offered_load": {"rho": rho, "rate_per_s": round(rho * mu, 2), **load},
+            "max_resident_GB": round(sch.max_resident / 1e9, 2)}
+
+
 def calibrate_copy(nbytes=1 << 30, reps=5):
     """A plain device-to-device copy of known size, for scaling the HBM
     traffic counters (FETCH_SIZE / WRITE_SIZE) of the profiled kernels."""
@@ -226,7 +249,10 @@ def main():
     line = run_grouped(args)
     if not args.no_extras:
         log("[bench] extra workloads ...")
-        line["extra"] = {"dense_uniform": run_dense_uniform(), "chain_fp64": run_chain()}
+        line["extra"] = {"dense_uniform": run_dense_uniform(), "chain_fp64": run_chain(),
+                         "chain_bf16x3": run_chain(prec="bf16x3")}
+        log("[bench] serving ...")
+        line["extra"]["serving"] = run_serving()
     print(json.dumps(line), flush=True)
 
 

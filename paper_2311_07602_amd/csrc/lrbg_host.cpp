@@ -673,7 +673,7 @@ static lrbg_status plan_from_schedule(Schedule &sch, uint32_t flags, lrbg_plan *
     p->flags = flags;
     p->levels = sch.levels;
     p->stats = sch.stats;
-    hipGetDevice(&p->device);
+    (void)hipGetDevice(&p->device);
     auto cleanup = [&](lrbg_status st) {
         lrbg_plan_destroy(p);
         return st;
@@ -710,7 +710,7 @@ static lrbg_status plan_from_schedule(Schedule &sch, uint32_t flags, lrbg_plan *
         }
         if (st == LRBG_OK && hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
             st = fail(LRBG_EDEVICE, "hipGraphInstantiate failed");
-        hipStreamDestroy(cs);
+        (void)hipStreamDestroy(cs);
         if (st != LRBG_OK) return cleanup(st);
     }
     *out = p;
@@ -719,54 +719,92 @@ static lrbg_status plan_from_schedule(Schedule &sch, uint32_t flags, lrbg_plan *
 
 // ------------------------------------------------------------- one-shot calls
 
-// One-shot calls upload their schedule into pooled device buffers and
-// release them once an event recorded after the launch has completed, so
-// they never block the host on earlier work.
-struct Pending {
-    hipEvent_t ev;
-    lrbg_plan *plan;
+// One-shot calls stage their schedule (descriptors, tiles) through pooled
+// pinned host buffers and pooled device buffers: hipMemcpyAsync on the
+// caller's stream, the grouped launch(es), then an event; a buffer pair is
+// reused once its event has completed.  After warm-up no call allocates or
+// blocks the host on earlier work, so calls on different streams overlap.
+struct Staging {
+    void *dev = nullptr;
+    void *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool in_use = false;
 };
 static std::mutex g_mu;
-static std::vector<Pending> g_pending;
+static std::vector<Staging *> g_staging;
 
-static void reap(bool wait)
+static Staging *acquire_staging(size_t bytes)
 {
     std::lock_guard<std::mutex> lk(g_mu);
-    std::vector<Pending> keep;
-    for (auto &pd : g_pending) {
-        if (wait) hipEventSynchronize(pd.ev);
-        if (hipEventQuery(pd.ev) == hipSuccess) {
-            hipEventDestroy(pd.ev);
-            lrbg_plan_destroy(pd.plan);
-        } else {
-            keep.push_back(pd);
-        }
+    Staging *best = nullptr;
+    for (Staging *st : g_staging) {
+        if (st->in_use && hipEventQuery(st->ev) == hipSuccess) st->in_use = false;
+        if (!st->in_use && st->cap >= bytes && (!best || st->cap < best->cap)) best = st;
     }
-    g_pending.swap(keep);
+    if (best) {
+        best->in_use = true;
+        return best;
+    }
+    size_t cap = 4096;
+    while (cap < bytes) cap *= 2;
+    Staging *st = new (std::nothrow) Staging();
+    if (!st) return nullptr;
+    if (hipMalloc(&st->dev, cap) != hipSuccess) {
+        delete st;
+        return nullptr;
+    }
+    if (hipHostMalloc(&st->host, cap, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&st->ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipFree(st->dev);
+        if (st->host) (void)hipHostFree(st->host);
+        delete st;
+        return nullptr;
+    }
+    st->cap = cap;
+    st->in_use = true;
+    g_staging.push_back(st);
+    return st;
 }
 
 static lrbg_status run_once(const lrbg_desc *ds, int64_t n, hipStream_t stream)
 {
-    reap(false);
     if (n == 0) return LRBG_OK;
     Schedule sch;
     TuneTable tt;
     load_tune_cache(getenv("LRBG_TUNE_CACHE"), tt);
     lrbg_status st = build_schedule(ds, n, tt, 0, nullptr, sch);
     if (st != LRBG_OK) return st;
-    lrbg_plan *p = nullptr;
-    st = plan_from_schedule(sch, LRBG_PLAN_NO_GRAPH, &p);
-    if (st != LRBG_OK) return st;
-    st = enqueue_levels(p, stream);
-    hipEvent_t ev;
-    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-        hipStreamSynchronize(stream);
-        lrbg_plan_destroy(p);
-        return st != LRBG_OK ? st : fail(LRBG_EDEVICE, "event creation failed");
+    const size_t nd = sch.descs.size() * sizeof(DevDesc), nt = sch.tiles.size() * sizeof(Tile);
+    const size_t toff = (nd + 255) / 256 * 256;
+    Staging *sg = acquire_staging(toff + nt);
+    if (!sg) return fail(LRBG_ENOMEM, "staging allocation failed");
+    memcpy(sg->host, sch.descs.data(), nd);
+    memcpy((char *)sg->host + toff, sch.tiles.data(), nt);
+    hipError_t e = hipMemcpyAsync(sg->dev, sg->host, toff + nt, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        sg->in_use = false;
+        return fail(LRBG_EDEVICE, "hipMemcpyAsync: %s", hipGetErrorString(e));
     }
-    hipEventRecord(ev, stream);
-    std::lock_guard<std::mutex> lk(g_mu);
-    g_pending.push_back(Pending{ev, p});
+    const DevDesc *dd = (const DevDesc *)sg->dev;
+    const Tile *dt = (const Tile *)((char *)sg->dev + toff);
+    for (auto &lv : sch.levels) {
+        if (lv.ntiles <= 0) continue;
+        int rc = launch_grouped(dd, dt + lv.tile_off, lv.ntiles, stream);
+        if (rc) {
+            st = fail(LRBG_EDEVICE, "grouped launch failed: %s", hipGetErrorString((hipError_t)rc));
+            break;
+        }
+    }
+    // the buffers are released only after everything enqueued above has run
+    e = hipEventRecord(sg->ev, stream);
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(stream);
+        std::lock_guard<std::mutex> lk(g_mu);
+        sg->in_use = false;
+        return st != LRBG_OK ? st : fail(LRBG_EDEVICE, "hipEventRecord: %s", hipGetErrorString(e));
+    }
     return st;
 }
 
@@ -822,7 +860,6 @@ lrbg_status lrbg_plan_create(lrbg_plan **out, const lrbg_desc *descs, int64_t co
     *out = nullptr;
     if (flags & ~(uint32_t)(LRBG_PLAN_PERSISTENT | LRBG_PLAN_NO_GRAPH | LRBG_PLAN_SCHED_MIX))
         return fail(LRBG_EINVAL, "unknown plan flags 0x%x", flags);
-    reap(false);
     TuneTable tt;
     load_tune_cache(tune_cache ? tune_cache : getenv("LRBG_TUNE_CACHE"), tt);
     Schedule sch;
@@ -875,15 +912,15 @@ double lrbg_plan_last_ms(lrbg_plan *p)
 lrbg_status lrbg_plan_destroy(lrbg_plan *p)
 {
     if (!p) return LRBG_OK;
-    if (p->timed && p->ev1) hipEventSynchronize(p->ev1);
-    if (p->exec) hipGraphExecDestroy(p->exec);
-    if (p->graph) hipGraphDestroy(p->graph);
-    if (p->ev0) hipEventDestroy(p->ev0);
-    if (p->ev1) hipEventDestroy(p->ev1);
-    if (p->d_descs) hipFree(p->d_descs);
-    if (p->d_tiles) hipFree(p->d_tiles);
-    if (p->d_qinfo) hipFree(p->d_qinfo);
-    if (p->d_counters) hipFree(p->d_counters);
+    if (p->timed && p->ev1) (void)hipEventSynchronize(p->ev1);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->ev0) (void)hipEventDestroy(p->ev0);
+    if (p->ev1) (void)hipEventDestroy(p->ev1);
+    if (p->d_descs) (void)hipFree(p->d_descs);
+    if (p->d_tiles) (void)hipFree(p->d_tiles);
+    if (p->d_qinfo) (void)hipFree(p->d_qinfo);
+    if (p->d_counters) (void)hipFree(p->d_counters);
     delete p;
     return LRBG_OK;
 }
@@ -928,15 +965,15 @@ lrbg_status lrbg_autotune(const lrbg_desc *sample, int64_t count, const char *ca
             if (plan_from_schedule(sch, LRBG_PLAN_NO_GRAPH, &p) != LRBG_OK) continue;
             double ms = 1e300;
             for (int r = 0; r <= reps; ++r) {   // first run warms up
-                hipEventRecord(e0, s);
+                (void)hipEventRecord(e0, s);
                 lrbg_status st = enqueue_levels(p, s);
-                hipEventRecord(e1, s);
+                (void)hipEventRecord(e1, s);
                 if (st != LRBG_OK || hipEventSynchronize(e1) != hipSuccess) {
                     result = st != LRBG_OK ? st : fail(LRBG_EDEVICE, "autotune run failed");
                     break;
                 }
                 float t = 0;
-                hipEventElapsedTime(&t, e0, e1);
+                (void)hipEventElapsedTime(&t, e0, e1);
                 if (r > 0) ms = std::min(ms, (double)t);
             }
             lrbg_plan_destroy(p);
@@ -951,9 +988,9 @@ lrbg_status lrbg_autotune(const lrbg_desc *sample, int64_t count, const char *ca
             os << std::get<0>(kv.first) << " " << std::get<1>(kv.first) << " " << std::get<2>(kv.first) << " "
                << std::get<3>(kv.first) << " " << variant_name(best) << " " << best_ms << "\n";
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipStreamDestroy(s);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(s);
     if (result != LRBG_OK) return result;
     if (cache_out) {
         std::ofstream f(cache_out);

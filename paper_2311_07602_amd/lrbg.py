@@ -52,6 +52,22 @@ class lrbg_plan_stats(ctypes.Structure):
 
 _lib = None
 
+# numpy view of lrbg_desc (same field offsets), for building large
+# descriptor arrays without per-descriptor Python objects
+DESC_NP = None
+
+
+def desc_dtype():
+    global DESC_NP
+    if DESC_NP is None:
+        import numpy as np
+        names = [f for f, _ in lrbg_desc._fields_]
+        fmts = ["<i4" if t is ctypes.c_int32 else "<u8" for _, t in lrbg_desc._fields_]
+        offs = [getattr(lrbg_desc, f).offset for f in names]
+        DESC_NP = np.dtype({"names": names, "formats": fmts, "offsets": offs,
+                            "itemsize": ctypes.sizeof(lrbg_desc)})
+    return DESC_NP
+
 
 def load(path: Optional[str] = None):
     """Load liblrbg.so; raise if it is missing (no fallback path exists)."""
@@ -140,6 +156,14 @@ def lr_batched_gemm(op: int, prec: int, m: Sequence[int], n: Sequence[int], k: S
 def lrbg_grouped(descs: Sequence[lrbg_desc], stream=None) -> int:
     arr = (lrbg_desc * max(len(descs), 1))(*descs)
     return _check(load().lrbg_grouped(arr, len(descs), _stream_ptr(stream)), "lrbg_grouped")
+
+
+def lrbg_grouped_array(arr, stream=None) -> int:
+    """lrbg_grouped over a numpy array of dtype desc_dtype()."""
+    if arr.dtype != desc_dtype() or not arr.flags["C_CONTIGUOUS"]:
+        raise TypeError("descriptor array must be a contiguous desc_dtype() array")
+    ptr = ctypes.cast(arr.ctypes.data, ctypes.POINTER(lrbg_desc))
+    return _check(load().lrbg_grouped(ptr, len(arr), _stream_ptr(stream)), "lrbg_grouped")
 
 
 def lrbg_plan_create(descs: Sequence[lrbg_desc], tune_cache: Optional[str] = None, flags: int = 0) -> int:
