@@ -21,11 +21,15 @@
 //    contiguous bytes of a column per lane group, and a lane's outputs are
 //    runs of contiguous rows: 4g .. 4g+3 (RM = 1) or 32 h + 8g .. +7.
 //
-// Ragged edges: rank-type dimensions (< 16 or not a multiple of 16) are
-// masked branch-free (clamped address, then select).  Block-type dimensions
-// and contraction tails are handled by a GUARD instantiation of each tile
-// that the host selects per tile (Tile::flags bit 0); interior tiles run
-// straight-line vector loads.
+// Ragged edges: a lane's A-operand value only reaches output row c and its
+// B-operand value only output column c, so lanes beyond a rank-type edge
+// load from a clamped, valid address and their outputs are never stored.
+// Only contraction tails must read zeros; they, and block-type edges, are
+// handled by a GUARD instantiation of each tile that the host selects per
+// tile (Tile::flags bit 0); interior tiles run straight-line vector loads.
+// Loads of chunk i+1 are issued before the matrix-core work of chunk i into
+// a second register buffer (explicit ping-pong, no copies), and no loaded
+// value is touched before it is consumed, so each wait covers one chunk.
 //
 // The products (column-major, see include/lrbg.h):
 //   DENSE_TS C = A U          (dense block x skinny basis)
@@ -155,23 +159,14 @@ __device__ __forceinline__ void store_rows(gp col, const d4 (&acc)[RM], int g, i
     }
 }
 
-// KG doubles of a k-contiguous column selected by a lane-dependent mask:
-// the column pointer is already clamped to a valid column; masked lanes get 0.
-template <int KG, bool GUARD>
-__device__ __forceinline__ void load_kcol(double (&dst)[KG], gcp colp, bool ok, int kvalid)
-{
-    load_run<KG, GUARD>(dst, colp, kvalid);
-#pragma unroll
-    for (int s = 0; s < KG; ++s) dst[s] = ok ? dst[s] : 0.0;
-}
-
 // ---------------------------------------------------------------------------
 // Staging of a k-contiguous operand chunk (KC rows of NCOL columns of a
 // column-major matrix) into LDS as buf[kk * P + j]: threads read 16-byte row
 // pairs, consecutive threads walking down a column, and write them
 // transposed so that the matrix-core operand reads (16 consecutive j per
-// lane group) are conflict-free.  Columns at or beyond `nvalid` are stored
-// as 0; with GUARD, so are rows at or beyond `kvalid`.
+// lane group) are conflict-free.  Columns at or beyond `nvalid` hold
+// clamped (valid) data, used only for outputs that are never stored; with
+// GUARD, rows at or beyond `kvalid` are stored as 0.
 template <int NCOL, int KC, bool GUARD>
 struct StageK {
     static_assert(KC % 2 == 0, "row pairs");
@@ -185,12 +180,8 @@ struct StageK {
         for (int p = 0; p < PPT; ++p) {
             const int idx = threadIdx.x + kThreads * p;
             const int j = idx / (KC / 2), kk = 2 * (idx % (KC / 2));
-            const bool ok = idx < NPAIR && j < nvalid;
-            const int jc = ok ? j : 0;
-            double t[2];
-            load_run<2, GUARD>(t, base + kk + (size_t)jc * ld, kvalid - kk);
-            r[p][0] = ok ? t[0] : 0.0;
-            r[p][1] = ok ? t[1] : 0.0;
+            const int jc = (idx < NPAIR && j < nvalid) ? j : 0;
+            load_run<2, GUARD>(r[p], base + kk + (size_t)jc * ld, kvalid - kk);
         }
     }
     __device__ __forceinline__ void store(double *buf, int P) const
@@ -227,12 +218,10 @@ __device__ __forceinline__ void dts64_tile(const DevDesc &d, int i0)
     const gcp Ap = gin(d.a) + wrow;
 
     gcp Up[RN];
-    bool colok[RN];
 #pragma unroll
     for (int jb = 0; jb < RN; ++jb) {
         const int col = jb * 16 + c;
-        colok[jb] = col < N;
-        Up[jb] = gin(d.b) + (size_t)(colok[jb] ? col : 0) * ldu;
+        Up[jb] = gin(d.b) + (size_t)(col < N ? col : 0) * ldu;
     }
 
     d4 acc[RM][RN];
@@ -241,7 +230,6 @@ __device__ __forceinline__ void dts64_tile(const DevDesc &d, int i0)
 #pragma unroll
         for (int jb = 0; jb < RN; ++jb) acc[mm][jb] = d4{0.0, 0.0, 0.0, 0.0};
 
-    double a[KG][RM], u[RN][KG];
     auto load = [&](int k0, double (&aa)[KG][RM], double (&uu)[RN][KG]) {
         const int kb = k0 + KG * g;
         const int kvalid = K - kb;
@@ -254,36 +242,32 @@ __device__ __forceinline__ void dts64_tile(const DevDesc &d, int i0)
                 for (int mm = 0; mm < RM; ++mm) aa[s][mm] = 0.0;
         }
 #pragma unroll
-        for (int jb = 0; jb < RN; ++jb) load_kcol<KG, GUARD>(uu[jb], Up[jb] + kb, colok[jb], kvalid);
+        for (int jb = 0; jb < RN; ++jb) load_run<KG, GUARD>(uu[jb], Up[jb] + kb, kvalid);
     };
-
-    if (K > 0) load(0, a, u);
-    for (int k0 = 0; k0 < K; k0 += KSTEP) {
-        double an[KG][RM], un[RN][KG];
-        const bool more = k0 + KSTEP < K;
-        if (more) load(k0 + KSTEP, an, un);
+    auto compute = [&](const double (&aa)[KG][RM], const double (&uu)[RN][KG]) {
 #pragma unroll
         for (int s = 0; s < KG; ++s)
 #pragma unroll
             for (int jb = 0; jb < RN; ++jb)
 #pragma unroll
-                for (int mm = 0; mm < RM; ++mm)
-                    acc[mm][jb] = mfma64(a[s][mm], u[jb][s], acc[mm][jb]);
-        if (more) {
-#pragma unroll
-            for (int s = 0; s < KG; ++s)
-#pragma unroll
-                for (int mm = 0; mm < RM; ++mm) a[s][mm] = an[s][mm];
-#pragma unroll
-            for (int jb = 0; jb < RN; ++jb)
-#pragma unroll
-                for (int s = 0; s < KG; ++s) u[jb][s] = un[jb][s];
-        }
+                for (int mm = 0; mm < RM; ++mm) acc[mm][jb] = mfma64(aa[s][mm], uu[jb][s], acc[mm][jb]);
+    };
+
+    double a0[KG][RM], u0[RN][KG], a1[KG][RM], u1[RN][KG];
+    if (K > 0) load(0, a0, u0);
+    for (int k0 = 0; k0 < K;) {
+        if (k0 + KSTEP < K) load(k0 + KSTEP, a1, u1);
+        compute(a0, u0);
+        k0 += KSTEP;
+        if (k0 >= K) break;
+        if (k0 + KSTEP < K) load(k0 + KSTEP, a0, u0);
+        compute(a1, u1);
+        k0 += KSTEP;
     }
 
 #pragma unroll
     for (int jb = 0; jb < RN; ++jb) {
-        if (!colok[jb]) continue;
+        if (jb * 16 + c >= N) continue;
         d4 o[RM];
 #pragma unroll
         for (int mm = 0; mm < RM; ++mm) o[mm] = acc[mm][jb];
@@ -321,8 +305,6 @@ __device__ __forceinline__ void dtsl_tile(const DevDesc &d, int i0, double *lds)
 #pragma unroll
         for (int jb = 0; jb < RN; ++jb) acc[mm][jb] = d4{0.0, 0.0, 0.0, 0.0};
 
-    StageK<NC, KC, GUARD> st;
-    double a[KG][RM];
     auto load_a = [&](int k0, double (&aa)[KG][RM]) {
         const int kb = k0 + KG * g;
 #pragma unroll
@@ -334,37 +316,42 @@ __device__ __forceinline__ void dtsl_tile(const DevDesc &d, int i0, double *lds)
                 for (int mm = 0; mm < RM; ++mm) aa[s][mm] = 0.0;
         }
     };
+    auto compute = [&](const double *cur, const double (&aa)[KG][RM]) {
+        if (!active) return;
+#pragma unroll
+        for (int s = 0; s < KG; ++s) {
+            double b[RN];
+#pragma unroll
+            for (int jb = 0; jb < RN; ++jb) b[jb] = cur[(KG * g + s) * P + jb * 16 + c];
+#pragma unroll
+            for (int jb = 0; jb < RN; ++jb)
+#pragma unroll
+                for (int mm = 0; mm < RM; ++mm) acc[mm][jb] = mfma64(aa[s][mm], b[jb], acc[mm][jb]);
+        }
+    };
 
+    // Chunk i lives in LDS buffer i % 2.  The next chunk's U and A are
+    // fetched before this chunk's matrix-core work and first touched after
+    // it (LDS store, register copy), so their latency is covered by one chunk.
+    StageK<NC, KC, GUARD> st;
+    double a[KG][RM];
     if (K > 0) {
         st.fetch(U, ldu, K, N);
-        st.store(lds, P);
         load_a(0, a);
+        st.store(lds, P);
     }
     __syncthreads();
     int it = 0;
     for (int k0 = 0; k0 < K; k0 += KC, ++it) {
-        const double *cur = lds + (it & 1) * BUF;
-        double *nxt = lds + ((it + 1) & 1) * BUF;
         const bool more = k0 + KC < K;
         double an[KG][RM];
         if (more) {
             st.fetch(U + k0 + KC, ldu, K - (k0 + KC), N);
             load_a(k0 + KC, an);
         }
-        if (active) {
-#pragma unroll
-            for (int s = 0; s < KG; ++s) {
-                double b[RN];
-#pragma unroll
-                for (int jb = 0; jb < RN; ++jb) b[jb] = cur[(KG * g + s) * P + jb * 16 + c];
-#pragma unroll
-                for (int jb = 0; jb < RN; ++jb)
-#pragma unroll
-                    for (int mm = 0; mm < RM; ++mm) acc[mm][jb] = mfma64(a[s][mm], b[jb], acc[mm][jb]);
-            }
-        }
+        compute(lds + (it & 1) * BUF, a);
         if (more) {
-            st.store(nxt, P);
+            st.store(lds + ((it + 1) & 1) * BUF, P);
 #pragma unroll
             for (int s = 0; s < KG; ++s)
 #pragma unroll
@@ -403,16 +390,13 @@ __device__ __forceinline__ void inn64_tile(const DevDesc &d, int i0, double *lds
     const size_t ldv = (size_t)d.lda, ldu = (size_t)d.ldb, ldt = (size_t)d.ldc;
 
     const int rowbase = i0 + og * 16 * RI;
-    gcp Vp[RI];
-    bool rok[RI];
+    gcp Vp[RI], Up[RJ];
+    bool cok[RJ];
 #pragma unroll
     for (int bi = 0; bi < RI; ++bi) {
         const int col = rowbase + bi * 16 + rho(c);   // V1 column = T row
-        rok[bi] = col < M;
-        Vp[bi] = gin(d.a) + (size_t)(rok[bi] ? col : 0) * ldv;
+        Vp[bi] = gin(d.a) + (size_t)(col < M ? col : 0) * ldv;
     }
-    gcp Up[RJ];
-    bool cok[RJ];
 #pragma unroll
     for (int bj = 0; bj < RJ; ++bj) {
         const int col = bj * 16 + c;
@@ -426,39 +410,35 @@ __device__ __forceinline__ void inn64_tile(const DevDesc &d, int i0, double *lds
 #pragma unroll
         for (int bj = 0; bj < RJ; ++bj) acc[bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
 
-    double a[RI][KG], u[RJ][KG];
     auto load = [&](int k0, double (&aa)[RI][KG], double (&uu)[RJ][KG]) {
         const int kb = k0 + KG * g;
         const int kvalid = K - kb;
 #pragma unroll
-        for (int bi = 0; bi < RI; ++bi) load_kcol<KG, GUARD>(aa[bi], Vp[bi] + kb, rok[bi], kvalid);
+        for (int bi = 0; bi < RI; ++bi) load_run<KG, GUARD>(aa[bi], Vp[bi] + kb, kvalid);
 #pragma unroll
-        for (int bj = 0; bj < RJ; ++bj) load_kcol<KG, GUARD>(uu[bj], Up[bj] + kb, cok[bj], kvalid);
+        for (int bj = 0; bj < RJ; ++bj) load_run<KG, GUARD>(uu[bj], Up[bj] + kb, kvalid);
     };
-
-    int k0 = ks * KSTEP;
-    if (k0 < K) load(k0, a, u);
-    for (; k0 < K; k0 += KS * KSTEP) {
-        double an[RI][KG], un[RJ][KG];
-        const bool more = k0 + KS * KSTEP < K;
-        if (more) load(k0 + KS * KSTEP, an, un);
+    auto compute = [&](const double (&aa)[RI][KG], const double (&uu)[RJ][KG]) {
 #pragma unroll
         for (int s = 0; s < KG; ++s)
 #pragma unroll
             for (int bi = 0; bi < RI; ++bi)
 #pragma unroll
-                for (int bj = 0; bj < RJ; ++bj)
-                    acc[bi][bj] = mfma64(a[bi][s], u[bj][s], acc[bi][bj]);
-        if (more) {
-#pragma unroll
-            for (int bi = 0; bi < RI; ++bi)
-#pragma unroll
-                for (int s = 0; s < KG; ++s) a[bi][s] = an[bi][s];
-#pragma unroll
-            for (int bj = 0; bj < RJ; ++bj)
-#pragma unroll
-                for (int s = 0; s < KG; ++s) u[bj][s] = un[bj][s];
-        }
+                for (int bj = 0; bj < RJ; ++bj) acc[bi][bj] = mfma64(aa[bi][s], uu[bj][s], acc[bi][bj]);
+    };
+
+    double a0[RI][KG], u0[RJ][KG], a1[RI][KG], u1[RJ][KG];
+    constexpr int STRIDE = KS * KSTEP;
+    int k0 = ks * KSTEP;
+    if (k0 < K) load(k0, a0, u0);
+    while (k0 < K) {
+        if (k0 + STRIDE < K) load(k0 + STRIDE, a1, u1);
+        compute(a0, u0);
+        k0 += STRIDE;
+        if (k0 >= K) break;
+        if (k0 + STRIDE < K) load(k0 + STRIDE, a0, u0);
+        compute(a1, u1);
+        k0 += STRIDE;
     }
 
     if constexpr (KS > 1) {
@@ -536,26 +516,9 @@ __device__ __forceinline__ void innl_tile(const DevDesc &d, int i0, double *lds)
 #pragma unroll
         for (int bj = 0; bj < RJ; ++bj) acc[bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
 
-    StageK<MT, KC, GUARD> sv;
-    StageK<NT, KC, GUARD> su;
-    if (K > 0) {
-        sv.fetch(V1t, ldv, K, mvalid);
-        su.fetch(U2, ldu, K, N);
-        sv.store(lds, PV);
-        su.store(lds + KC * PV, PU);
-    }
-    __syncthreads();
     const int arow = wr * 16 * RI, bcol = wc * 16 * RJ;
-    int it = 0;
-    for (int k0 = 0; k0 < K; k0 += KC, ++it) {
-        const double *cv = lds + (it & 1) * BUF;
+    auto compute = [&](const double *cv) {
         const double *cu = cv + KC * PV;
-        double *nv = lds + ((it + 1) & 1) * BUF;
-        const bool more = k0 + KC < K;
-        if (more) {
-            sv.fetch(V1t + k0 + KC, ldv, K - (k0 + KC), mvalid);
-            su.fetch(U2 + k0 + KC, ldu, K - (k0 + KC), N);
-        }
 #pragma unroll
         for (int s = 0; s < KG; ++s) {
             const int kk = KG * g + s;
@@ -569,7 +532,26 @@ __device__ __forceinline__ void innl_tile(const DevDesc &d, int i0, double *lds)
 #pragma unroll
                 for (int bj = 0; bj < RJ; ++bj) acc[bi][bj] = mfma64(a[bi], b[bj], acc[bi][bj]);
         }
+    };
+    StageK<MT, KC, GUARD> sv;
+    StageK<NT, KC, GUARD> su;
+    if (K > 0) {
+        sv.fetch(V1t, ldv, K, mvalid);
+        su.fetch(U2, ldu, K, N);
+        sv.store(lds, PV);
+        su.store(lds + KC * PV, PU);
+    }
+    __syncthreads();
+    int it = 0;
+    for (int k0 = 0; k0 < K; k0 += KC, ++it) {
+        const bool more = k0 + KC < K;
         if (more) {
+            sv.fetch(V1t + k0 + KC, ldv, K - (k0 + KC), mvalid);
+            su.fetch(U2 + k0 + KC, ldu, K - (k0 + KC), N);
+        }
+        compute(lds + (it & 1) * BUF);
+        if (more) {
+            double *nv = lds + ((it + 1) & 1) * BUF;
             sv.store(nv, PV);
             su.store(nv + KC * PV, PU);
         }
@@ -842,12 +824,11 @@ __device__ __forceinline__ void inn3_tile(const DevDesc &d, int i0, double *lds)
 
     const int rowbase = i0 + og * 16 * RI;
     gcf Vp[RI], Up[RJ];
-    bool rok[RI], cok[RJ];
+    bool cok[RJ];
 #pragma unroll
     for (int bi = 0; bi < RI; ++bi) {
         const int col = rowbase + bi * 16 + c;
-        rok[bi] = col < M;
-        Vp[bi] = ginf(d.a) + (size_t)(rok[bi] ? col : 0) * ldv;
+        Vp[bi] = ginf(d.a) + (size_t)(col < M ? col : 0) * ldv;
     }
 #pragma unroll
     for (int bj = 0; bj < RJ; ++bj) {
@@ -867,17 +848,9 @@ __device__ __forceinline__ void inn3_tile(const DevDesc &d, int i0, double *lds)
     auto load = [&](int k0, float (&aa)[RI][8], float (&uu)[RJ][8]) {
         const int kb = k0 + 8 * g, kv = K - kb;
 #pragma unroll
-        for (int bi = 0; bi < RI; ++bi) {
-            load8f<GUARD>(aa[bi], Vp[bi] + kb, kv);
+        for (int bi = 0; bi < RI; ++bi) load8f<GUARD>(aa[bi], Vp[bi] + kb, kv);
 #pragma unroll
-            for (int t = 0; t < 8; ++t) aa[bi][t] = rok[bi] ? aa[bi][t] : 0.0f;
-        }
-#pragma unroll
-        for (int bj = 0; bj < RJ; ++bj) {
-            load8f<GUARD>(uu[bj], Up[bj] + kb, kv);
-#pragma unroll
-            for (int t = 0; t < 8; ++t) uu[bj][t] = cok[bj] ? uu[bj][t] : 0.0f;
-        }
+        for (int bj = 0; bj < RJ; ++bj) load8f<GUARD>(uu[bj], Up[bj] + kb, kv);
     };
     int k0 = ks * 32;
     if (PF && k0 < K) load(k0, a, u);
@@ -1017,11 +990,7 @@ __device__ __forceinline__ void dts3_tile(const DevDesc &d, int i0)
             for (int mm = 0; mm < RM; ++mm) aa[mm][t] = r[mm];
         }
 #pragma unroll
-        for (int jb = 0; jb < RN; ++jb) {
-            load8f<GUARD>(uu[jb], Up[jb] + kb, kv);
-#pragma unroll
-            for (int t = 0; t < 8; ++t) uu[jb][t] = colok[jb] ? uu[jb][t] : 0.0f;
-        }
+        for (int jb = 0; jb < RN; ++jb) load8f<GUARD>(uu[jb], Up[jb] + kb, kv);
     };
     if (PF && K > 0) load(0, a, u);
     for (int k0 = 0; k0 < K; k0 += 32) {
