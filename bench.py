@@ -30,6 +30,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "useful GFLOP/s + % of roofline on uneven batches; p50/p99 latency at fixed load"
+PROFILE = os.path.join(ROOT, "profiles", "lrbg_grouped_kernel.uneven_batch_20000.md")
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 
@@ -94,7 +95,7 @@ def run_grouped(args):
     flags = 0
     if args.persistent:
         flags |= lrbg.LRBG_PLAN_PERSISTENT
-    if args.mix:
+    if not args.lpt:
         flags |= lrbg.LRBG_PLAN_SCHED_MIX
     plan = lrbg.Plan(w.descs, tune_cache=args.tune_cache, flags=flags)
     st = plan.stats()
@@ -102,6 +103,8 @@ def run_grouped(args):
     ms, per = time_plan(plan, args.steps, args.warmup, stream)
     flops, bytes_ = st["useful_flops"], st["hbm_bytes"]
     achieved_tf = flops / (ms * 1e-3) / 1e12
+    from paper_2311_07602_amd import profiling
+    traffic = profiling.current_traffic(PROFILE) if (args.count == 20000 and flags == lrbg.LRBG_PLAN_SCHED_MIX) else None
     line = {
         "metric": METRIC,
         "value": round(flops / (ms * 1e-3) / 1e9, 2),
@@ -115,7 +118,7 @@ def run_grouped(args):
                    "instances": args.count, "products": len(w.descs), "tiles": st["tiles"],
                    "plan_flags": flags, "launch": "hipGraph replay, one grouped kernel"},
         "roofline": {"bound": "mfma", "achieved": round(achieved_tf, 3), "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved_tf / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved_tf / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
                      "kernel": "lrbg_grouped_kernel",
                      "algorithmic_flops": flops, "algorithmic_bytes": bytes_,
                      "hbm_GBs": round(bytes_ / (ms * 1e-3) / 1e9, 1),
@@ -227,7 +230,8 @@ def main():
     ap.add_argument("--count", type=int, default=20000)
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2311_07602_amd", "tune", "mi355x.tune"))
     ap.add_argument("--persistent", action="store_true")
-    ap.add_argument("--mix", action="store_true")
+    ap.add_argument("--lpt", action="store_true", help="longest-first tile order instead of the mixed "
+                    "compute-/memory-bound order")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")

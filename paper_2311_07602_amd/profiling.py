@@ -1,0 +1,176 @@
+"""Summaries of rocprofv3 runs of the grouped kernel.
+
+A summary (markdown, committed under profiles/) holds the kernel-trace
+statistics of the benchmark command and the HBM traffic per launch from two
+counter runs (FETCH_SIZE, then WRITE_SIZE, in KiB per dispatch), each scaled
+by what the same counter reads for a plain device copy of known size.  It is
+tagged with a digest of the kernel sources and the tuning cache, so a
+benchmark can tell whether the counters still describe the kernel it runs.
+
+    python -m paper_2311_07602_amd.profiling summarize --kt DIR --fetch DIR \\
+        --write DIR --cal-fetch DIR --cal-write DIR --out FILE.md \\
+        --kernel lrbg_grouped_kernel --flops F --bytes B --cmd "..." ...
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import os
+import statistics
+from typing import Dict, List, Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ["csrc/lrbg_kernels.hip", "csrc/lrbg_internal.h", "tune/mi355x.tune"]
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(rel.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _csv(d: str, suffix: str) -> str:
+    hits = glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True)
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    return hits[0]
+
+
+def kernel_stats(kt_dir: str, kernel: str) -> dict:
+    for row in csv.DictReader(open(_csv(kt_dir, "kernel_stats.csv"))):
+        if kernel in row["Name"]:
+            return {"calls": int(row["Calls"]), "avg_ns": float(row["AverageNs"]),
+                    "min_ns": float(row["MinNs"]), "max_ns": float(row["MaxNs"])}
+    raise KeyError(kernel)
+
+
+def counter_per_dispatch(pmc_dir: str, kernel: str) -> List[float]:
+    per: Dict[str, float] = {}
+    for row in csv.DictReader(open(_csv(pmc_dir, "counter_collection.csv"))):
+        if kernel in row["Kernel_Name"]:
+            per[row["Dispatch_Id"]] = per.get(row["Dispatch_Id"], 0.0) + float(row["Counter_Value"])
+    if not per:
+        raise KeyError(kernel)
+    return [per[k] for k in sorted(per, key=int)]
+
+
+def summarize(args) -> str:
+    st = kernel_stats(args.kt, args.kernel)
+    fetch = counter_per_dispatch(args.fetch, args.kernel)
+    write = counter_per_dispatch(args.write, args.kernel)
+    cal_f = statistics.median(counter_per_dispatch(args.cal_fetch, args.cal_kernel))
+    cal_w = statistics.median(counter_per_dispatch(args.cal_write, args.cal_kernel))
+    fs = args.cal_bytes / (cal_f * 1024.0)
+    ws = args.cal_bytes / (cal_w * 1024.0)
+    f_b = statistics.median(fetch) * 1024.0 * fs
+    w_b = statistics.median(write) * 1024.0 * ws
+    avg_ms = st["avg_ns"] * 1e-6
+    lines = [
+        f"# {args.kernel}: {args.workload}",
+        "",
+        "rocprofv3 summaries of the benchmark's grouped kernel (one launch per step).",
+        "",
+        "## Commands",
+        "",
+    ]
+    for c in args.cmd:
+        lines.append(f"    {c}")
+    lines += [
+        "",
+        "## Kernel trace (--kernel-trace --stats)",
+        "",
+        f"| kernel | calls | average ms | min ms | max ms |",
+        f"|---|---|---|---|---|",
+        f"| {args.kernel} | {st['calls']} | {avg_ms:.4f} | {st['min_ns'] * 1e-6:.4f} | {st['max_ns'] * 1e-6:.4f} |",
+        "",
+        "## HBM traffic (--pmc FETCH_SIZE, then --pmc WRITE_SIZE; KiB per dispatch)",
+        "",
+        f"| counter | grouped kernel (median of {len(fetch)}) | copy of {args.cal_bytes / 2**30:.0f} GiB | scale |",
+        f"|---|---|---|---|",
+        f"| FETCH_SIZE | {statistics.median(fetch):.0f} | {cal_f:.0f} | {fs:.4f} |",
+        f"| WRITE_SIZE | {statistics.median(write):.0f} | {cal_w:.0f} | {ws:.4f} |",
+        "",
+        f"Scaled traffic per launch: read {f_b / 1e9:.3f} GB + write {w_b / 1e9:.3f} GB = "
+        f"{(f_b + w_b) / 1e9:.3f} GB; algorithmic (compulsory) bytes {args.bytes / 1e9:.3f} GB "
+        f"(ratio {(f_b + w_b) / args.bytes:.3f}).",
+        f"Achieved: {args.flops / (avg_ms * 1e-3) / 1e12:.2f} TFLOP/s useful "
+        f"({args.flops / (avg_ms * 1e-3) / 78.6e12 * 100:.1f}% of 78.6), "
+        f"{args.bytes / (avg_ms * 1e-3) / 1e9:.0f} GB/s algorithmic.",
+        "",
+        "## Machine-readable",
+        "",
+        "```",
+        f"kernel: {args.kernel}",
+        f"source_digest: {args.digest or source_digest()}",
+        f"avg_duration_ms: {avg_ms:.6f}",
+        f"algorithmic_flops: {args.flops:.6g}",
+        f"algorithmic_bytes: {args.bytes:.6g}",
+        f"fetch_bytes_per_launch: {f_b:.6g}",
+        f"write_bytes_per_launch: {w_b:.6g}",
+        f"traffic_bytes_per_launch: {f_b + w_b:.6g}",
+        "```",
+        "",
+    ]
+    text = "\n".join(lines)
+    with open(args.out, "w") as f:
+        f.write(text)
+    return text
+
+
+def read_summary(path: str) -> Optional[dict]:
+    if not os.path.exists(path):
+        return None
+    out, inside = {}, False
+    for ln in open(path):
+        ln = ln.rstrip("\n")
+        if ln.strip() == "```":
+            inside = not inside
+            continue
+        if inside and ":" in ln:
+            k, v = ln.split(":", 1)
+            out[k.strip()] = v.strip()
+    return out or None
+
+
+def current_traffic(path: str) -> Optional[float]:
+    """Traffic per launch from a summary, or None once the kernel sources or
+    tuning cache have changed since the counters were taken."""
+    s = read_summary(path)
+    if not s or s.get("source_digest") != source_digest():
+        return None
+    return float(s["traffic_bytes_per_launch"])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    sm = sub.add_parser("summarize")
+    sm.add_argument("--kt", required=True)
+    sm.add_argument("--fetch", required=True)
+    sm.add_argument("--write", required=True)
+    sm.add_argument("--cal-fetch", required=True)
+    sm.add_argument("--cal-write", required=True)
+    sm.add_argument("--cal-kernel", default="copyBuffer")
+    sm.add_argument("--cal-bytes", type=float, default=float(1 << 30))
+    sm.add_argument("--kernel", default="lrbg_grouped_kernel")
+    sm.add_argument("--workload", default="")
+    sm.add_argument("--flops", type=float, required=True)
+    sm.add_argument("--bytes", type=float, required=True)
+    sm.add_argument("--digest", default=None)
+    sm.add_argument("--cmd", action="append", default=[])
+    sm.add_argument("--out", required=True)
+    sub.add_parser("digest")
+    a = ap.parse_args()
+    if a.what == "digest":
+        print(source_digest())
+    else:
+        print(summarize(a))
+
+
+if __name__ == "__main__":
+    main()

@@ -169,3 +169,32 @@ def test_chain_bf16x3_inner_fp64_recomp():
                      oracle.normalized_error(dW.numpy(), Wref[0], Dw)))
     assert max(e[0] for e in errs) <= TOL, errs
     assert max(e[1] for e in errs) <= TOL, errs
+
+
+def test_error_table_every_bucket():
+    """BF16x3 error against the FP64 oracle on the FP64 originals, for both
+    products on every (b, r) bucket of the uneven batch; written to
+    gpurun_out/bf16x3_error_table.txt when that folder exists."""
+    import os
+    rows = []
+    for b in inputs.GROUPED_B:
+        for r in [x for x in inputs.GROUPED_R if x <= b // 2]:
+            e_d = e_i = 0.0
+            for i in range(2):
+                A, U = inputs.dense_ts_instance(9, 1000 * b + 10 * r + i, b, r)
+                dA, dU, dC = f32dev(A), f32dev(U), DevMat(b, r)
+                V1, U2 = inputs.inner_instance(9, 2000 * b + 10 * r + i, b, r)
+                dV, dU2, dT = f32dev(V1), f32dev(U2), DevMat(r, r)
+                run([lrbg.desc("dense_ts", dA.view, dU.view, dC.view, prec="bf16x3"),
+                     lrbg.desc("inner", dV.view, dU2.view, dT.view, prec="bf16x3")])
+                Cref, Dc = ref_dense_ts(A, U)
+                Tref, Dt = ref_inner(V1, U2)
+                e_d = max(e_d, oracle.normalized_error(dC.numpy(), Cref, Dc))
+                e_i = max(e_i, oracle.normalized_error(dT.numpy(), Tref, Dt))
+            rows.append((b, r, e_d, e_i))
+    text = "b r dense_ts_err inner_err\n" + "\n".join(f"{b} {r} {d:.3e} {i:.3e}" for b, r, d, i in rows)
+    if os.path.isdir("gpurun_out"):
+        with open("gpurun_out/bf16x3_error_table.txt", "w") as f:
+            f.write(text + "\n")
+    print(text)
+    assert max(max(d, i) for _, _, d, i in rows) <= TOL
