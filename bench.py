@@ -12,7 +12,9 @@ stratified sample of the same workload.
 Extra fields measure the other workloads on the same GPU: a uniform dense x
 skinny batch (64 x 256x256 . 256x16, buffer sets rotated so the 38 MB batch
 does not sit in the 256 MB last-level cache) and the low-rank x low-rank
-chain (4096 instances, b = 512, r = 32: inner products, then recompression).
+chain (4096 instances, b = 512, r = 32: inner products, then recompression),
+the paper's fused low-rank product G = X_A (V_A^T U_B) X_B at batch 20 000
+for b in {512, 1024, 2048} and r in {8, 16, 32}, and the serving loop.
 
   python bench.py [--steps K] [--warmup W] [--extras/--no-extras]
   python bench.py --calibrate-copy      # plain 1 GiB device copy (counter scaling)
@@ -186,6 +188,32 @@ def run_chain(count=4096, b=512, r=32, steps=20, warmup=3, prec="fp64"):
             "frac_of_roofline_time": round(roof / ms, 4), "bound": "hbm"}
 
 
+def run_lrmult_paper(count=20000, bs=(512, 1024, 2048), rs=(8, 16, 32), steps=10, warmup=2):
+    """The paper's batched low-rank product G = X_A (V_A^T U_B) X_B at its
+    measured shapes (batch 20 000 per (b, r)); GFLOP/s by the paper's count
+    4 r^3 + 2 r^2 b per instance."""
+    import torch
+    from paper_2311_07602_amd import lrbg, workloads
+    stream = torch.cuda.current_stream()
+    out = []
+    for b in bs:
+        for r in rs:
+            w = workloads.lrmult(count, b, r)
+            plan = lrbg.Plan(w.descs)
+            st = plan.stats()
+            ms, _ = time_plan(plan, steps, warmup, stream)
+            plan.close()
+            del w
+            torch.cuda.empty_cache()
+            f, by = st["useful_flops"], st["hbm_bytes"]
+            roof = max(f / (PEAK_FP64_TFLOPS * 1e12), by / (PEAK_HBM_GBS * 1e9)) * 1e3
+            out.append({"b": b, "r": r, "ms_per_step": round(ms, 4), "GFLOP/s": round(f / ms / 1e6, 1),
+                        "GB/s": round(by / ms / 1e6, 1), "frac_of_roofline_time": round(roof / ms, 4)})
+            log(f"[bench] lrmult b={b} r={r}: {ms:.4f} ms, {f / ms / 1e6:.0f} GFLOP/s, {by / ms / 1e6:.0f} GB/s")
+    return {"workload": f"{count} x G = X_A (V_A^T U_B) X_B per (b, r), FP64, N(0,1), fused (one tile per "
+                        f"instance)", "flops_per_instance": "4 r^3 + 2 r^2 b", "bound": "hbm", "shapes": out}
+
+
 def run_serving(budget=64e9, slots=8, sat_requests=300, warm=200, measured=1000, rho=0.7):
     """Continuous-batching loop: saturated request rate first (all requests
     queued at t=0), then Poisson arrivals at rho x that rate; latency is
@@ -255,6 +283,8 @@ def main():
         log("[bench] extra workloads ...")
         line["extra"] = {"dense_uniform": run_dense_uniform(), "chain_fp64": run_chain(),
                          "chain_bf16x3": run_chain(prec="bf16x3")}
+        log("[bench] paper-shape low-rank products ...")
+        line["extra"]["lrmult_paper_shapes"] = run_lrmult_paper()
         log("[bench] serving ...")
         line["extra"]["serving"] = run_serving()
     print(json.dumps(line), flush=True)

@@ -19,6 +19,14 @@
  *                     (rebuild a block from the rank x rank core of a
  *                      low-rank product, the small-core-times-skinny role of
  *                      Alg. 1 steps 2-3; k = r, m = n = b)
+ *   LRBG_OP_LRMULT    G = X_A * (V_A^T * U_B) * X_B
+ *                     V_A k x m (a), U_B k x n (b), X_A m x m (s),
+ *                     X_B n x n (e), G m x n (c): the paper's low-rank
+ *                     product of two blocks (Alg. 1: C_temp = A_{V^T} B_U,
+ *                     E_temp = A_X C_temp, G_XY = E_temp B_X), evaluated in
+ *                     that order with the rank-sized intermediates kept on
+ *                     chip (the fusion of Alg. 2); k = b, m = rank_A,
+ *                     n = rank_B; FP64; m, n <= 64.
  *
  * Conventions for every entry point:
  *   - All matrices are column-major: element (i, j) of X is at
@@ -34,8 +42,8 @@
  *     accumulation and returns the output in FP64 (double *).  RECOMP is
  *     FP64 only (LRBG_EUNSUPPORTED otherwise).
  *   - Limits: rank-type dimensions (DENSE_TS n; INNER m, n; RECOMP k) at
- *     most 128; block-type dimensions at most 65536; violating either is
- *     LRBG_EUNSUPPORTED.
+ *     most 128 (LRMULT m, n at most 64); block-type dimensions at most
+ *     65536; violating either is LRBG_EUNSUPPORTED.
  *   - Pointers named "device" are device (HBM) addresses on the current HIP
  *     device, naturally aligned (8 bytes for FP64, 4 for FP32).  Host arrays
  *     (sizes, leading dimensions, pointer arrays, descriptor arrays) are read
@@ -74,7 +82,8 @@ typedef enum lrbg_status {
 typedef enum lrbg_op {
     LRBG_OP_DENSE_TS = 0,
     LRBG_OP_INNER = 1,
-    LRBG_OP_RECOMP = 2
+    LRBG_OP_RECOMP = 2,
+    LRBG_OP_LRMULT = 3
 } lrbg_op;
 
 typedef enum lrbg_prec {
@@ -83,17 +92,22 @@ typedef enum lrbg_prec {
 } lrbg_prec;
 
 /* One product of a grouped call.  a/b/c are device pointers whose element
- * type follows `prec` (see above); s is the RECOMP core (device, FP64,
- * k x k, lds >= k), NULL for the other ops.  `flags` is reserved (0). */
+ * type follows `prec` (see above); s is the RECOMP core (k x k) or the
+ * LRMULT X_A (m x m), e the LRMULT X_B (n x n), both FP64 with lds/lde >=
+ * their rows; NULL (and ld ignored) for the ops that do not use them.
+ * `flags` and `reserved` must be 0. */
 typedef struct lrbg_desc {
     int32_t op, prec;
     int32_t m, n, k;
     int32_t lda, ldb, lds, ldc;
     int32_t flags;
+    int32_t lde;
+    int32_t reserved;
     const void *a;
     const void *b;
     const double *s;
     void *c;
+    const double *e;
 } lrbg_desc;
 
 /*
@@ -116,6 +130,29 @@ lrbg_status lr_batched_gemm(int32_t op, int32_t prec, int64_t count,
                             const double *const *S, const int32_t *lds,
                             void *const *C, const int32_t *ldc,
                             void *stream);
+
+/*
+ * lr_batched_lrmult -- `count` low-rank products G_i = X_A,i (V_A,i^T U_B,i)
+ * X_B,i, the paper's batched Alg. 1 (Alg. 2's operand arrays), FP64.
+ *   b             : host array [count]: the shared inner (block) dimension.
+ *   ra, rb        : host arrays [count]: ranks of the two operands (<= 64).
+ *   AV, ldav      : device V_A, b x ra (the stored A_{V^T} transposed).
+ *   BU, ldbu      : device U_B, b x rb.
+ *   AX, ldax      : device X_A, ra x ra.
+ *   BX, ldbx      : device X_B, rb x rb.
+ *   G, ldg        : device G, ra x rb (overwritten).
+ *   stream        : hipStream_t.
+ * Same as lrbg_grouped over LRBG_OP_LRMULT descriptors (m = ra, n = rb,
+ * k = b; a = AV, b = BU, s = AX, e = BX, c = G).
+ */
+lrbg_status lr_batched_lrmult(int64_t count, const int32_t *b,
+                              const int32_t *ra, const int32_t *rb,
+                              const double *const *AV, const int32_t *ldav,
+                              const double *const *BU, const int32_t *ldbu,
+                              const double *const *AX, const int32_t *ldax,
+                              const double *const *BX, const int32_t *ldbx,
+                              double *const *G, const int32_t *ldg,
+                              void *stream);
 
 /*
  * lrbg_grouped -- one launch sequence over `count` heterogeneous products

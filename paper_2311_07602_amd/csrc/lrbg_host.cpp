@@ -67,6 +67,7 @@ static std::string variant_name(int v)
     case K_INN3: snprintf(buf, sizeof buf, "inn3_ri%d_rj%d_ks%d_pf%d", vi.p1, vi.p2, vi.p3, vi.p4); break;
     case K_DTSL: snprintf(buf, sizeof buf, "dtsl_rm%d_rn%d_kg%d", vi.p1, vi.p2, vi.p3); break;
     case K_INNL: snprintf(buf, sizeof buf, "innl_ri%d_rj%d_wr%d_kg%d", vi.p1, vi.p2, vi.p3, vi.p4); break;
+    case K_LRM: snprintf(buf, sizeof buf, "lrm_ri%d_rj%d_ks%d_kg%d", vi.p1, vi.p2, vi.p3, vi.p4); break;
     default: snprintf(buf, sizeof buf, "v%d", v);
     }
     return buf;
@@ -78,6 +79,7 @@ static int kind_of(int op, int prec)
         if (op == LRBG_OP_DENSE_TS) return K_DTS64;
         if (op == LRBG_OP_INNER) return K_INN64;
         if (op == LRBG_OP_RECOMP) return K_REC64;
+        if (op == LRBG_OP_LRMULT) return K_LRM;
     } else if (prec == LRBG_BF16X3) {
         if (op == LRBG_OP_DENSE_TS) return K_DTS3;
         if (op == LRBG_OP_INNER) return K_INN3;
@@ -108,6 +110,7 @@ static bool variant_fits(int v, const lrbg_desc &d)
     case K_DTS3: return d.n <= 16 * vi.p2;
     case K_INN64: return d.n <= 16 * vi.p2;
     case K_INN3: return d.n <= 16 * vi.p2;
+    case K_LRM: return d.m <= 16 * vi.p1 * (4 / vi.p3) && d.n <= 16 * vi.p2;
     case K_REC64: {
         const int kp = (d.k + 15) / 16 * 16;
         return (size_t)kp * 16 * vi.p2 * 8 <= (size_t)kLdsBytes;
@@ -132,6 +135,8 @@ static void tiles_of(int v, const lrbg_desc &d, std::vector<int32_t> &p0s, std::
         step = 16 * vi.p1 * (4 / vi.p3); extent = d.m; kc = 4 * vi.p4; break;
     case K_INN3:
         step = 16 * vi.p1 * (4 / vi.p3); extent = d.m; kc = 32; break;
+    case K_LRM:   // one tile per product (variant_fits: m <= step)
+        step = 16 * vi.p1 * (4 / vi.p3); extent = d.m; kc = 4 * vi.p4; break;
     case K_INNL:
         step = 16 * vi.p1 * vi.p3; extent = d.m; kc = 4 * vi.p4; break;
     case K_REC64:
@@ -155,7 +160,7 @@ static void bucket_dims(const lrbg_desc &d, int &b, int &r)
 {
     switch (d.op) {
     case LRBG_OP_DENSE_TS: b = std::max(d.m, d.k); r = d.n; break;
-    case LRBG_OP_INNER: b = d.k; r = std::max(d.m, d.n); break;
+    case LRBG_OP_INNER: case LRBG_OP_LRMULT: b = d.k; r = std::max(d.m, d.n); break;
     default: b = std::max(d.m, d.n); r = d.k; break;
     }
 }
@@ -213,6 +218,12 @@ static int default_variant(const lrbg_desc &d)
         if (rr <= 64) return pick({36});
         return pick({37});
     }
+    if (kind == K_LRM) {
+        const int rr = std::max(d.m, d.n);
+        if (rr <= 16) return pick({39});
+        if (rr <= 32) return pick({40});
+        return pick({41});
+    }
     if (kind == K_REC64) {
         if (d.k <= 16) return pick({13});
         if (d.k <= 32) return pick({14});
@@ -243,15 +254,20 @@ static Range span(const void *p, int rows, int cols, int ld, size_t es, int64_t 
 
 static bool overlaps(const Range &a, const Range &b) { return a.lo < b.hi && b.lo < a.hi && a.hi > a.lo && b.hi > b.lo; }
 
-// Operand shapes (rows, cols) of a product: a, b, s, c.
-static void shapes(const lrbg_desc &d, int sh[4][2])
+// Operand shapes (rows, cols) of a product: a, b, s, c, e (0 x 0 when unused).
+static void shapes(const lrbg_desc &d, int sh[5][2])
 {
+    sh[4][0] = sh[4][1] = 0;
     switch (d.op) {
     case LRBG_OP_DENSE_TS:
         sh[0][0] = d.m; sh[0][1] = d.k; sh[1][0] = d.k; sh[1][1] = d.n; sh[2][0] = 0; sh[2][1] = 0;
         break;
     case LRBG_OP_INNER:
         sh[0][0] = d.k; sh[0][1] = d.m; sh[1][0] = d.k; sh[1][1] = d.n; sh[2][0] = 0; sh[2][1] = 0;
+        break;
+    case LRBG_OP_LRMULT:
+        sh[0][0] = d.k; sh[0][1] = d.m; sh[1][0] = d.k; sh[1][1] = d.n; sh[2][0] = d.m; sh[2][1] = d.m;
+        sh[4][0] = d.n; sh[4][1] = d.n;
         break;
     default:
         sh[0][0] = d.m; sh[0][1] = d.k; sh[1][0] = d.n; sh[1][1] = d.k; sh[2][0] = d.k; sh[2][1] = d.k;
@@ -263,32 +279,34 @@ static void shapes(const lrbg_desc &d, int sh[4][2])
 
 static lrbg_status validate_one(const lrbg_desc &d, int64_t i)
 {
-    if (d.op < 0 || d.op > 2) return fail(LRBG_EINVAL, "product %lld: bad op %d", (long long)i, d.op);
+    if (d.op < 0 || d.op > 3) return fail(LRBG_EINVAL, "product %lld: bad op %d", (long long)i, d.op);
     if (d.prec != LRBG_FP64 && d.prec != LRBG_BF16X3)
         return fail(LRBG_EINVAL, "product %lld: bad precision %d", (long long)i, d.prec);
     if (d.m < 0 || d.n < 0 || d.k < 0)
         return fail(LRBG_EINVAL, "product %lld: negative size (m=%d n=%d k=%d)", (long long)i, d.m, d.n, d.k);
-    if (d.flags != 0) return fail(LRBG_EINVAL, "product %lld: flags must be 0", (long long)i);
+    if (d.flags != 0 || d.reserved != 0)
+        return fail(LRBG_EINVAL, "product %lld: flags and reserved must be 0", (long long)i);
     if (kind_of(d.op, d.prec) == K_NOP)
-        return fail(LRBG_EUNSUPPORTED, "product %lld: op %d has no bf16x3 form (recompression stays FP64)",
-                    (long long)i, d.op);
+        return fail(LRBG_EUNSUPPORTED, "product %lld: op %d has no bf16x3 form (FP64 only)", (long long)i, d.op);
     int b, r;
     bucket_dims(d, b, r);
-    const int rankdims[3][2] = {{d.n, 0}, {d.m, d.n}, {d.k, 0}};
+    const int rankdims[4][2] = {{d.n, 0}, {d.m, d.n}, {d.k, 0}, {d.m, d.n}};
+    const int rankmax = d.op == LRBG_OP_LRMULT ? kMaxLrRank : kMaxRank;
     for (int t = 0; t < 2; ++t)
-        if (rankdims[d.op][t] > kMaxRank)
+        if (rankdims[d.op][t] > rankmax)
             return fail(LRBG_EUNSUPPORTED, "product %lld: rank dimension %d exceeds %d", (long long)i,
-                        rankdims[d.op][t], kMaxRank);
+                        rankdims[d.op][t], rankmax);
     if (b > kMaxBlock)
         return fail(LRBG_EUNSUPPORTED, "product %lld: block dimension %d exceeds %d", (long long)i, b, kMaxBlock);
-    int sh[4][2];
+    int sh[5][2];
     shapes(d, sh);
-    const void *ptr[4] = {d.a, d.b, d.s, d.c};
-    const int ld[4] = {d.lda, d.ldb, d.lds, d.ldc};
-    const char *nm[4] = {"a", "b", "s", "c"};
-    const size_t es[4] = {elem_size(d.prec), elem_size(d.prec), 8, 8};
-    for (int t = 0; t < 4; ++t) {
-        if (t == 2 && d.op != LRBG_OP_RECOMP) continue;
+    const void *ptr[5] = {d.a, d.b, d.s, d.c, d.e};
+    const int ld[5] = {d.lda, d.ldb, d.lds, d.ldc, d.lde};
+    const char *nm[5] = {"a", "b", "s", "c", "e"};
+    const size_t es[5] = {elem_size(d.prec), elem_size(d.prec), 8, 8, 8};
+    const bool uses_s = d.op == LRBG_OP_RECOMP || d.op == LRBG_OP_LRMULT, uses_e = d.op == LRBG_OP_LRMULT;
+    for (int t = 0; t < 5; ++t) {
+        if ((t == 2 && !uses_s) || (t == 4 && !uses_e)) continue;
         const int rows = sh[t][0], cols = sh[t][1];
         if (ld[t] < std::max(1, rows))
             return fail(LRBG_EINVAL, "product %lld: ld%s=%d < rows=%d", (long long)i, nm[t], ld[t], rows);
@@ -299,8 +317,8 @@ static lrbg_status validate_one(const lrbg_desc &d, int64_t i)
         }
     }
     const Range out = span(d.c, sh[3][0], sh[3][1], d.ldc, 8, i);
-    for (int t = 0; t < 3; ++t) {
-        if (t == 2 && d.op != LRBG_OP_RECOMP) continue;
+    for (int t = 0; t < 5; ++t) {
+        if (t == 3 || (t == 2 && !uses_s) || (t == 4 && !uses_e)) continue;
         if (overlaps(out, span(ptr[t], sh[t][0], sh[t][1], ld[t], es[t], i)))
             return fail(LRBG_EINVAL, "product %lld: output overlaps input %s", (long long)i, nm[t]);
     }
@@ -352,6 +370,10 @@ static void work_of(const lrbg_desc &d, double &flops, double &bytes)
     case LRBG_OP_INNER:
         flops = 2.0 * m * n * k;
         bytes = es * (k * m + k * n) + 8.0 * m * n;
+        break;
+    case LRBG_OP_LRMULT:   // C = V_A^T U_B, E = X_A C, G = E X_B
+        flops = 2.0 * m * n * k + 2.0 * m * m * n + 2.0 * m * n * n;
+        bytes = 8.0 * (k * m + k * n + m * m + n * n + m * n);
         break;
     default:
         flops = 2.0 * m * n * k + 2.0 * k * k * n;
@@ -412,15 +434,15 @@ struct Schedule {
     lrbg_plan_stats stats{};
 };
 
-// Dependency level of every product: a product reading (a, b or s) memory
-// written by another product runs one level after it.
+// Dependency level of every product: a product reading (a, b, s or e)
+// memory written by another product runs one level after it.
 static lrbg_status compute_levels(const lrbg_desc *ds, int64_t n, std::vector<int> &level)
 {
     level.assign((size_t)n, 0);
     std::vector<Range> outs;
     outs.reserve((size_t)n);
     for (int64_t i = 0; i < n; ++i) {
-        int sh[4][2];
+        int sh[5][2];
         shapes(ds[i], sh);
         Range r = span(ds[i].c, sh[3][0], sh[3][1], ds[i].ldc, 8, i);
         if (r.hi > r.lo) outs.push_back(r);
@@ -435,14 +457,16 @@ static lrbg_status compute_levels(const lrbg_desc *ds, int64_t n, std::vector<in
     bool any = false;
     for (int64_t i = 0; i < n; ++i) {
         const lrbg_desc &d = ds[i];
-        int sh[4][2];
+        int sh[5][2];
         shapes(d, sh);
-        const void *ptr[3] = {d.a, d.b, d.s};
-        const int ld[3] = {d.lda, d.ldb, d.lds};
-        const size_t es[3] = {elem_size(d.prec), elem_size(d.prec), 8};
-        for (int t = 0; t < 3; ++t) {
-            if (t == 2 && d.op != LRBG_OP_RECOMP) continue;
-            Range in = span(ptr[t], sh[t][0], sh[t][1], ld[t], es[t], i);
+        const void *ptr[4] = {d.a, d.b, d.s, d.e};
+        const int ld[4] = {d.lda, d.ldb, d.lds, d.lde};
+        const int si[4] = {0, 1, 2, 4};
+        const size_t es[4] = {elem_size(d.prec), elem_size(d.prec), 8, 8};
+        for (int t = 0; t < 4; ++t) {
+            if (t == 2 && d.op != LRBG_OP_RECOMP && d.op != LRBG_OP_LRMULT) continue;
+            if (t == 3 && d.op != LRBG_OP_LRMULT) continue;
+            Range in = span(ptr[t], sh[si[t]][0], sh[si[t]][1], ld[t], es[t], i);
             if (in.hi <= in.lo) continue;
             // outputs starting before in.hi; walk back while they may overlap
             auto it = std::lower_bound(outs.begin(), outs.end(), in.hi,
@@ -592,6 +616,7 @@ static lrbg_status build_schedule(const lrbg_desc *ds, int64_t n, const TuneTabl
         dd.b = d.b;
         dd.s = d.s;
         dd.c = d.c;
+        dd.e = d.op == LRBG_OP_LRMULT ? d.e : nullptr;
         dd.m = d.m;
         dd.n = d.n;
         dd.k = d.k;
@@ -599,7 +624,7 @@ static lrbg_status build_schedule(const lrbg_desc *ds, int64_t n, const TuneTabl
         dd.ldb = d.ldb;
         dd.lds = d.lds;
         dd.ldc = d.ldc;
-        dd.pad = 0;
+        dd.lde = d.op == LRBG_OP_LRMULT ? d.lde : 0;
         double f, b;
         work_of(d, f, b);
         flops += f;
@@ -826,6 +851,7 @@ lrbg_status lr_batched_gemm(int32_t op, int32_t prec, int64_t count, const int32
     if (!m || !n || !k || !A || !lda || !B || !ldb || !C || !ldc)
         return fail(LRBG_EINVAL, "a required host array is NULL");
     if (op == LRBG_OP_RECOMP && (!S || !lds)) return fail(LRBG_EINVAL, "RECOMP needs S and lds arrays");
+    if (op == LRBG_OP_LRMULT) return fail(LRBG_EINVAL, "LRMULT takes five operands: use lr_batched_lrmult");
     std::vector<lrbg_desc> ds((size_t)count);
     for (int64_t i = 0; i < count; ++i) {
         lrbg_desc &d = ds[(size_t)i];
@@ -843,6 +869,38 @@ lrbg_status lr_batched_gemm(int32_t op, int32_t prec, int64_t count, const int32
         d.c = C[i];
         d.ldc = ldc[i];
         d.flags = 0;
+    }
+    return run_once(ds.data(), count, (hipStream_t)stream);
+}
+
+lrbg_status lr_batched_lrmult(int64_t count, const int32_t *b, const int32_t *ra, const int32_t *rb,
+                              const double *const *AV, const int32_t *ldav, const double *const *BU,
+                              const int32_t *ldbu, const double *const *AX, const int32_t *ldax,
+                              const double *const *BX, const int32_t *ldbx, double *const *G, const int32_t *ldg,
+                              void *stream)
+{
+    if (count < 0) return fail(LRBG_EINVAL, "negative count");
+    if (count == 0) return LRBG_OK;
+    if (!b || !ra || !rb || !AV || !ldav || !BU || !ldbu || !AX || !ldax || !BX || !ldbx || !G || !ldg)
+        return fail(LRBG_EINVAL, "a required host array is NULL");
+    std::vector<lrbg_desc> ds((size_t)count);
+    for (int64_t i = 0; i < count; ++i) {
+        lrbg_desc &d = ds[(size_t)i];
+        d.op = LRBG_OP_LRMULT;
+        d.prec = LRBG_FP64;
+        d.m = ra[i];
+        d.n = rb[i];
+        d.k = b[i];
+        d.a = AV[i];
+        d.lda = ldav[i];
+        d.b = BU[i];
+        d.ldb = ldbu[i];
+        d.s = AX[i];
+        d.lds = ldax[i];
+        d.e = BX[i];
+        d.lde = ldbx[i];
+        d.c = G[i];
+        d.ldc = ldg[i];
     }
     return run_once(ds.data(), count, (hipStream_t)stream);
 }

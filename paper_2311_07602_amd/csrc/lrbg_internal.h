@@ -6,7 +6,7 @@
 
 namespace lrbg {
 
-// One product as the kernels see it (64 bytes).  Element types follow the
+// One product as the kernels see it (72 bytes).  Element types follow the
 // variant: FP64 variants read double a/b, BF16X3 variants read float a/b;
 // every output c is double.
 struct DevDesc {
@@ -14,11 +14,11 @@ struct DevDesc {
     const void *b;
     const double *s;
     void *c;
+    const double *e;
     int32_t m, n, k;
-    int32_t lda, ldb, lds, ldc;
-    int32_t pad;
+    int32_t lda, ldb, lds, ldc, lde;
 };
-static_assert(sizeof(DevDesc) == 64, "DevDesc layout");
+static_assert(sizeof(DevDesc) == 72, "DevDesc layout");
 
 // One workgroup's unit of work: product `desc`, computed by `variant`,
 // starting at row (DENSE_TS, INNER) or column (RECOMP) `p0`.  flags bit 0
@@ -42,12 +42,14 @@ enum Kind : int32_t {
     K_INN3 = 5,    // INNER, bf16x3 split MFMA     params: RI, RJ, KS, PF
     K_DTSL = 6,    // DENSE_TS, FP64, U in LDS     params: RM, RN, KG
     K_INNL = 7,    // INNER, FP64, LDS-staged      params: RI, RJ, WR, KG
+    K_LRM = 8,     // LRMULT, FP64, fused          params: RI, RJ, KS, KG (INNER phase)
 };
 
 constexpr int kThreads = 256;       // 4 wavefronts of 64
 constexpr int kWaves = 4;
 constexpr int kLdsBytes = 65536;    // static LDS per workgroup (2 workgroups per CU)
 constexpr int kMaxRank = 128;
+constexpr int kMaxLrRank = 64;     // LRMULT: C and E both staged in LDS
 constexpr int kMaxBlock = 65536;
 constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies
 
@@ -91,9 +93,12 @@ constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies
     X(35, K_INN3, 2, 2, 4, 1)         \
     X(36, K_INN3, 1, 4, 4, 1)         \
     X(37, K_INN3, 1, 8, 4, 0)         \
-    X(38, K_INN3, 2, 2, 2, 1)
+    X(38, K_INN3, 2, 2, 2, 1)         \
+    X(39, K_LRM, 1, 1, 4, 8)          \
+    X(40, K_LRM, 2, 2, 4, 8)          \
+    X(41, K_LRM, 2, 4, 2, 4)
 
-constexpr int kNumVariants = 39;   // ids 0..38 (0 = no-op tile)
+constexpr int kNumVariants = 42;   // ids 0..41 (0 = no-op tile)
 
 struct VariantInfo {
     int32_t kind, p1, p2, p3, p4;

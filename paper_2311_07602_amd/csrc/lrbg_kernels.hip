@@ -35,6 +35,7 @@
 //   DENSE_TS C = A U          (dense block x skinny basis)
 //   INNER    T = V1^T U2      (Alg. 1 step 1 / Alg. 2 loop 4 of the paper)
 //   RECOMP   W = U1 (S V2^T)  (S V2^T formed in LDS, then streamed against U1)
+//   LRMULT   G = X_A (V_A^T U_B) X_B  (Alg. 1, rank-sized intermediates in LDS)
 #include <hip/hip_runtime.h>
 #include "lrbg_internal.h"
 
@@ -379,19 +380,26 @@ __device__ __forceinline__ void dtsl_tile(const DevDesc &d, int i0, double *lds)
 // (interleaved, so the group streams neighbouring rows together).  Partial
 // sums meet in LDS and are added in a fixed order: deterministic, no atomics.
 // Workgroup tile: T rows [i0, i0 + 16 RI NG) x all n columns.
-template <int RI, int RJ, int KS, int KG, bool GUARD>
-__device__ __forceinline__ void inn64_tile(const DevDesc &d, int i0, double *lds)
+//
+// inn64_accumulate leaves the finished sums in the ks == 0 waves: lane
+// (c, g) of output group og holds T(rowbase + 16 bi + 4 g + v, 16 bj + c) in
+// acc[bi][bj][v], rowbase = i0 + 16 RI og.  Rows >= m and columns >= n hold
+// finite filler (clamped operand columns), never an output.  LDS is free
+// again when it returns.  `after_first` runs once the first chunk's loads
+// are in flight (before any LDS use of the reduction).
+template <int RI, int RJ, int KS, int KG, bool GUARD, typename Hook>
+__device__ __forceinline__ void inn64_accumulate(const DevDesc &d, int i0, double *lds, d4 (&acc)[RI][RJ],
+                                                 Hook after_first)
 {
     constexpr int NG = 4 / KS;
     constexpr int KSTEP = 4 * KG;
     const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
     const int og = w / KS, ks = w % KS;
     const int M = d.m, N = d.n, K = d.k;
-    const size_t ldv = (size_t)d.lda, ldu = (size_t)d.ldb, ldt = (size_t)d.ldc;
+    const size_t ldv = (size_t)d.lda, ldu = (size_t)d.ldb;
 
     const int rowbase = i0 + og * 16 * RI;
     gcp Vp[RI], Up[RJ];
-    bool cok[RJ];
 #pragma unroll
     for (int bi = 0; bi < RI; ++bi) {
         const int col = rowbase + bi * 16 + rho(c);   // V1 column = T row
@@ -400,11 +408,9 @@ __device__ __forceinline__ void inn64_tile(const DevDesc &d, int i0, double *lds
 #pragma unroll
     for (int bj = 0; bj < RJ; ++bj) {
         const int col = bj * 16 + c;
-        cok[bj] = col < N;
-        Up[bj] = gin(d.b) + (size_t)(cok[bj] ? col : 0) * ldu;
+        Up[bj] = gin(d.b) + (size_t)(col < N ? col : 0) * ldu;
     }
 
-    d4 acc[RI][RJ];
 #pragma unroll
     for (int bi = 0; bi < RI; ++bi)
 #pragma unroll
@@ -431,6 +437,7 @@ __device__ __forceinline__ void inn64_tile(const DevDesc &d, int i0, double *lds
     constexpr int STRIDE = KS * KSTEP;
     int k0 = ks * KSTEP;
     if (k0 < K) load(k0, a0, u0);
+    after_first();
     while (k0 < K) {
         if (k0 + STRIDE < K) load(k0 + STRIDE, a1, u1);
         compute(a0, u0);
@@ -467,9 +474,20 @@ __device__ __forceinline__ void inn64_tile(const DevDesc &d, int i0, double *lds
                         for (int v = 0; v < 4; ++v) acc[bi][bj][v] += slot[((bi * RJ + bj) * 4 + v) * 64 + lane];
             }
         }
-        __syncthreads();   // LDS is reused by the next tile of a persistent workgroup
+        __syncthreads();   // LDS is reused after this
     }
+}
 
+template <int RI, int RJ, int KS, int KG, bool GUARD>
+__device__ __forceinline__ void inn64_tile(const DevDesc &d, int i0, double *lds)
+{
+    const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
+    const int og = w / KS, ks = w % KS;
+    const int M = d.m, N = d.n;
+    const size_t ldt = (size_t)d.ldc;
+    const int rowbase = i0 + og * 16 * RI;
+    d4 acc[RI][RJ];
+    inn64_accumulate<RI, RJ, KS, KG, GUARD>(d, i0, lds, acc, [] {});
     if (ks != 0) return;
 #pragma unroll
     for (int bi = 0; bi < RI; ++bi) {
@@ -478,13 +496,152 @@ __device__ __forceinline__ void inn64_tile(const DevDesc &d, int i0, double *lds
         if (ovalid <= 0) continue;
 #pragma unroll
         for (int bj = 0; bj < RJ; ++bj) {
-            if (!cok[bj]) continue;
+            if (bj * 16 + c >= N) continue;
             double o[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) o[v] = acc[bi][bj][v];
             store_run<4, true>(gout(d.c) + orow + (size_t)(bj * 16 + c) * ldt, o, ovalid, false);
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// LRMULT, FP64, fused.  G = X_A (V_A^T U_B) X_B for one product per
+// workgroup (ranks m, n <= R = 16 RI NG = 16 RJ), in the order of Alg. 1:
+//   C = V_A^T U_B   the INNER accumulation above (the long k = b contraction)
+//   E = X_A C       from LDS, on the matrix cores
+//   G = E X_B       from LDS, on the matrix cores; only G is written to HBM.
+// Alg. 2 fuses the same chain so that the rank-sized intermediates never
+// leave the cache; here they never leave LDS.  LDS, R x R doubles each:
+//   R0 (bottom): C row-major (the E phase reads C(kk, J0 + c): consecutive
+//       lanes, consecutive banks), then E column-major (the G phase reads
+//       E(I0 + rho(c), kk), again consecutive)
+//   R1 (top, clear of the reduction slots of the C phase): X_A column-major,
+//       then X_B row-major.
+// X_A is fetched before the long contraction and parked in R1 once the first
+// chunk's loads are in flight; X_B is fetched with it when it fits in a few
+// registers, else at the start of the E phase.  The small contractions run
+// over k in steps of 4 with k >= rank read as 0; rows and columns beyond the
+// ranks hold finite filler and are never stored.
+template <int RI, int RJ, int KS, int KG, bool GUARD>
+__device__ __forceinline__ void lrm_tile(const DevDesc &d, int i0, double *lds)
+{
+    constexpr int NG = 4 / KS;
+    constexpr int R = 16 * RJ;
+    static_assert(16 * RI * NG == R, "LRMULT tile covers a square R x R core");
+    constexpr int SLOTS = (KS - 1) * NG * RI * RJ * 4 * 64;   // reduction doubles of the C phase
+    static_assert(SLOTS + R * R <= kLdsBytes / 8 && 2 * R * R <= kLdsBytes / 8, "LRMULT staging exceeds LDS");
+    constexpr int XE = (R * R + kThreads - 1) / kThreads;   // X elements per thread
+    constexpr bool XB_EARLY = XE <= 4;
+    constexpr int NB = R / 16;                             // 16 x 16 blocks per side
+    constexpr int QB = (NB * NB + kWaves - 1) / kWaves;    // blocks per wave
+    const int tid = threadIdx.x, lane = tid & 63, c = lane & 15, g = lane >> 4, w = tid >> 6;
+    const int ra = d.m, rb = d.n;
+    double *R0 = lds, *R1 = lds + kLdsBytes / 8 - R * R;
+
+    // Thread tid takes linear elements idx = tid + 256 e of the R x R square
+    // (row = idx % R, col = idx / R): coalesced down the columns.
+    auto fetch = [&](double (&x)[XE], const double *p, int ld, int r) {
+#pragma unroll
+        for (int e = 0; e < XE; ++e) {
+            const int idx = tid + kThreads * e, row = idx % R, col = idx / R;
+            x[e] = (idx < R * R && row < r && col < r) ? gin(p)[row + (size_t)col * ld] : 0.0;
+        }
+    };
+    double xa[XE], xb[XE];
+    fetch(xa, d.s, d.lds, ra);
+    if constexpr (XB_EARLY) fetch(xb, d.e, d.lde, rb);
+
+    d4 acc[RI][RJ];
+    inn64_accumulate<RI, RJ, KS, KG, GUARD>(d, i0, lds, acc, [&] {
+#pragma unroll
+        for (int e = 0; e < XE; ++e) {
+            const int idx = tid + kThreads * e;
+            if (idx < R * R) R1[idx] = xa[e];   // column-major
+        }
+    });
+
+    // C -> R0, row-major
+    const int og = w / KS, ks = w % KS;
+    if (ks == 0) {
+        const int rowbase = i0 + og * 16 * RI;
+#pragma unroll
+        for (int bi = 0; bi < RI; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < RJ; ++bj)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) R0[(rowbase + bi * 16 + 4 * g + v) * R + bj * 16 + c] = acc[bi][bj][v];
+    }
+    __syncthreads();
+    if constexpr (!XB_EARLY) fetch(xb, d.e, d.lde, rb);
+
+    // Wave w owns output blocks q = w + 4 qq (I-blocks fastest).
+    const int nbi = (ra + 15) / 16, nbj = (rb + 15) / 16, nb = nbi * nbj;
+    int I0[QB], J0[QB];
+#pragma unroll
+    for (int qq = 0; qq < QB; ++qq) {
+        const int q = w + kWaves * qq;
+        I0[qq] = q < nb ? (q % nbi) * 16 : 0;
+        J0[qq] = q < nb ? (q / nbi) * 16 : 0;
+    }
+    d4 o[QB];
+
+    // E = X_A C, contraction over ra
+#pragma unroll
+    for (int qq = 0; qq < QB; ++qq) o[qq] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int l0 = 0; l0 < ra; l0 += 4) {
+        const bool ok = l0 + g < ra;
+        const int kk = ok ? l0 + g : 0;   // masked lanes read a valid LDS address
+#pragma unroll
+        for (int qq = 0; qq < QB; ++qq) {
+            if (w + kWaves * qq >= nb) continue;
+            const double a = ok ? R1[I0[qq] + rho(c) + kk * R] : 0.0;
+            const double b = ok ? R0[kk * R + J0[qq] + c] : 0.0;
+            o[qq] = mfma64(a, b, o[qq]);
+        }
+    }
+    __syncthreads();   // C and X_A are dead
+
+    // E -> R0 (column-major), X_B -> R1 (row-major)
+#pragma unroll
+    for (int qq = 0; qq < QB; ++qq) {
+        if (w + kWaves * qq >= nb) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) R0[I0[qq] + 4 * g + v + (J0[qq] + c) * R] = o[qq][v];
+    }
+#pragma unroll
+    for (int e = 0; e < XE; ++e) {
+        const int idx = tid + kThreads * e, row = idx % R, col = idx / R;
+        if (idx < R * R) R1[row * R + col] = xb[e];
+    }
+    __syncthreads();
+
+    // G = E X_B, contraction over rb
+#pragma unroll
+    for (int qq = 0; qq < QB; ++qq) o[qq] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int l0 = 0; l0 < rb; l0 += 4) {
+        const bool ok = l0 + g < rb;
+        const int kk = ok ? l0 + g : 0;
+#pragma unroll
+        for (int qq = 0; qq < QB; ++qq) {
+            if (w + kWaves * qq >= nb) continue;
+            const double a = ok ? R0[I0[qq] + rho(c) + kk * R] : 0.0;
+            const double b = ok ? R1[kk * R + J0[qq] + c] : 0.0;
+            o[qq] = mfma64(a, b, o[qq]);
+        }
+    }
+    const size_t ldg = (size_t)d.ldc;
+#pragma unroll
+    for (int qq = 0; qq < QB; ++qq) {
+        if (w + kWaves * qq >= nb) continue;
+        const int orow = I0[qq] + 4 * g, col = J0[qq] + c;
+        if (orow >= ra || col >= rb) continue;
+        double out[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[v] = o[qq][v];
+        store_run<4, true>(gout(d.c) + orow + (size_t)col * ldg, out, ra - orow, false);
+    }
+    __syncthreads();   // LDS is reused by the next tile of a persistent workgroup
 }
 
 // ---------------------------------------------------------------------------
@@ -1053,6 +1210,8 @@ __device__ __forceinline__ void run_variant_g(const DevDesc &d, int p0, double *
         dts3_tile<P1, P2, P3, GUARD>(d, p0);
     else if constexpr (KIND == K_INN3)
         inn3_tile<P1, P2, P3, P4, GUARD>(d, p0, lds);
+    else if constexpr (KIND == K_LRM)
+        lrm_tile<P1, P2, P3, P4, GUARD>(d, p0, lds);
 }
 
 template <int KIND, int P1, int P2, int P3, int P4>

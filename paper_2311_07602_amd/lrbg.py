@@ -21,11 +21,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblrbg.so")
 
 LRBG_OK, LRBG_EINVAL, LRBG_EUNSUPPORTED, LRBG_ENOMEM, LRBG_EDEVICE, LRBG_EBUDGET = range(6)
-LRBG_OP_DENSE_TS, LRBG_OP_INNER, LRBG_OP_RECOMP = 0, 1, 2
+LRBG_OP_DENSE_TS, LRBG_OP_INNER, LRBG_OP_RECOMP, LRBG_OP_LRMULT = 0, 1, 2, 3
 LRBG_FP64, LRBG_BF16X3 = 0, 1
 LRBG_PLAN_PERSISTENT, LRBG_PLAN_NO_GRAPH, LRBG_PLAN_SCHED_MIX = 0x1, 0x2, 0x4
 
-OPS = {"dense_ts": LRBG_OP_DENSE_TS, "inner": LRBG_OP_INNER, "recomp": LRBG_OP_RECOMP}
+OPS = {"dense_ts": LRBG_OP_DENSE_TS, "inner": LRBG_OP_INNER, "recomp": LRBG_OP_RECOMP,
+       "lrmult": LRBG_OP_LRMULT}
 PRECS = {"fp64": LRBG_FP64, "bf16x3": LRBG_BF16X3}
 
 
@@ -40,8 +41,9 @@ class lrbg_desc(ctypes.Structure):
                 ("m", ctypes.c_int32), ("n", ctypes.c_int32), ("k", ctypes.c_int32),
                 ("lda", ctypes.c_int32), ("ldb", ctypes.c_int32), ("lds", ctypes.c_int32),
                 ("ldc", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("lde", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("a", ctypes.c_void_p), ("b", ctypes.c_void_p), ("s", ctypes.c_void_p),
-                ("c", ctypes.c_void_p)]
+                ("c", ctypes.c_void_p), ("e", ctypes.c_void_p)]
 
 
 class lrbg_plan_stats(ctypes.Structure):
@@ -88,6 +90,8 @@ def load(path: Optional[str] = None):
     P = ctypes.POINTER
     lib.lr_batched_gemm.argtypes = [i32, i32, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.lr_batched_gemm.restype = ctypes.c_int
+    lib.lr_batched_lrmult.argtypes = [i64] + [vp] * 13 + [vp]
+    lib.lr_batched_lrmult.restype = ctypes.c_int
     lib.lrbg_grouped.argtypes = [P(lrbg_desc), i64, vp]
     lib.lrbg_grouped.restype = ctypes.c_int
     lib.lrbg_plan_create.argtypes = [P(vp), P(lrbg_desc), i64, ctypes.c_char_p, u32]
@@ -151,6 +155,20 @@ def lr_batched_gemm(op: int, prec: int, m: Sequence[int], n: Sequence[int], k: S
     ptrs = [ctypes.cast(a, vp) if a is not None else None for a in args]
     st = load().lr_batched_gemm(op, prec, count, *ptrs, _stream_ptr(stream))
     return _check(st, "lr_batched_gemm")
+
+
+def lr_batched_lrmult(b: Sequence[int], ra: Sequence[int], rb: Sequence[int],
+                      AV: Sequence[int], ldav: Sequence[int], BU: Sequence[int], ldbu: Sequence[int],
+                      AX: Sequence[int], ldax: Sequence[int], BX: Sequence[int], ldbx: Sequence[int],
+                      G: Sequence[int], ldg: Sequence[int], stream=None) -> int:
+    count = len(b)
+    i32, vp = ctypes.c_int32, ctypes.c_void_p
+    args = [_arr(i32, b), _arr(i32, ra), _arr(i32, rb), _arr(vp, AV), _arr(i32, ldav), _arr(vp, BU),
+            _arr(i32, ldbu), _arr(vp, AX), _arr(i32, ldax), _arr(vp, BX), _arr(i32, ldbx),
+            _arr(vp, G), _arr(i32, ldg)]
+    ptrs = [ctypes.cast(a, vp) for a in args]
+    st = load().lr_batched_lrmult(count, *ptrs, _stream_ptr(stream))
+    return _check(st, "lr_batched_lrmult")
 
 
 def lrbg_grouped(descs: Sequence[lrbg_desc], stream=None) -> int:
@@ -233,26 +251,30 @@ def _mat(x):
     return x.data_ptr(), rows, cols, max(ld, 1)
 
 
-def desc(op: str, a, b, c, s=None, prec: str = "fp64") -> lrbg_desc:
+def desc(op: str, a, b, c, s=None, prec: str = "fp64", e=None) -> lrbg_desc:
     """Descriptor of one product from column-major tensors.
 
     dense_ts: a = A (m x k), b = U (k x n), c = C (m x n)
     inner:    a = V1 (k x m), b = U2 (k x n), c = T (m x n)
     recomp:   a = U1 (m x k), b = V2 (n x k), s = S (k x k), c = W (m x n)
+    lrmult:   a = V_A (k x m), b = U_B (k x n), s = X_A (m x m),
+              e = X_B (n x n), c = G (m x n)
     """
     pa, ra, ca, la = _mat(a)
     pb, rb, cb, lb = _mat(b)
     pc, rc, cc, lc = _mat(c)
     ps, rs, cs, ls = _mat(s)
+    pe, re, ce, le = _mat(e)
     o = OPS[op]
     if o == LRBG_OP_DENSE_TS:
         m, k, n = ra, ca, cb
-    elif o == LRBG_OP_INNER:
+    elif o in (LRBG_OP_INNER, LRBG_OP_LRMULT):
         k, m, n = ra, ca, cb
     else:
         m, k, n = ra, ca, rb
     return lrbg_desc(op=o, prec=PRECS[prec], m=m, n=n, k=k, lda=la, ldb=lb, lds=ls if s is not None else 1,
-                     ldc=lc, flags=0, a=pa or None, b=pb or None, s=ps or None, c=pc or None)
+                     ldc=lc, flags=0, lde=le if e is not None else 1, reserved=0,
+                     a=pa or None, b=pb or None, s=ps or None, c=pc or None, e=pe or None)
 
 
 class Plan:

@@ -11,6 +11,8 @@ arithmetic happens here.
   chain(count)     low-rank x low-rank chain: T = V1^T U2, W = U1 (T V2^T)
                    with orthonormal bases and log-spaced singular values
                    folded into V (generated on the host per instance).
+  lrmult(count)    the paper's batched low-rank product at one (b, r):
+                   G = X_A (V_A^T U_B) X_B, all four operands N(0,1).
 """
 from __future__ import annotations
 
@@ -132,6 +134,37 @@ def chain_host_instance(w: Workload, i: int):
     return dict(U1=ops[0], V1=ops[1], U2=ops[2], V2=ops[3],
                 T=np.asfortranarray(_cm(T, i * r * r, r, r).cpu().numpy()),
                 W=np.asfortranarray(_cm(W, i * b * b, b, b).cpu().numpy()))
+
+
+def lrmult(count: int = 20000, b: int = 1024, r: int = 16, seed: int = 5, device="cuda") -> Workload:
+    """`count` instances of G = X_A (V_A^T U_B) X_B with V_A, U_B b x r and
+    X_A, X_B, G r x r, the operands of one instance adjacent in one pool."""
+    import torch
+    sizes = [b * r, b * r, r * r, r * r]
+    off1, per = inputs.pool_layout(sizes)
+    pin = inputs.device_normal(count * per, seed=seed, device=device)
+    offg, per_g = inputs.pool_layout([r * r])
+    pout = torch.empty(count * per_g, dtype=torch.float64, device=device)
+    descs, index = [], []
+    for i in range(count):
+        base = i * per
+        oV, oU, oXA, oXB = (base + int(o) for o in off1)
+        oG = i * per_g
+        descs.append(lrbg.desc("lrmult", _cm(pin, oV, b, r), _cm(pin, oU, b, r), _cm(pout, oG, r, r),
+                               s=_cm(pin, oXA, r, r), e=_cm(pin, oXB, r, r)))
+        index.append((oV, oU, oXA, oXB, oG))
+    return Workload("lrmult", descs, [pin, pout], {"count": count, "b": b, "r": r, "seed": seed}, index)
+
+
+def lrmult_operands(w: Workload, i: int):
+    """Host copies (float64, column-major) of lrmult instance i."""
+    pin, pout = w.pools
+    b, r = w.meta["b"], w.meta["r"]
+    oV, oU, oXA, oXB, oG = w.index[i]
+    def host(pool, off, rows, cols):
+        return np.asfortranarray(_cm(pool, off, rows, cols).cpu().numpy())
+    return dict(AV=host(pin, oV, b, r), BU=host(pin, oU, b, r), AX=host(pin, oXA, r, r),
+                BX=host(pin, oXB, r, r), G=host(pout, oG, r, r))
 
 
 def work_totals(descs) -> Tuple[float, float]:

@@ -65,3 +65,10 @@ def ref_recomp(U1, S, V2):
     D = oracle.recomp([np.asfortranarray(np.abs(U1))], [np.asfortranarray(np.abs(S))],
                       [np.asfortranarray(np.abs(V2))])[0]
     return W, D
+
+
+def ref_lrmult(AV, BU, AX, BX):
+    G = oracle.lr_mult([AV], [BU], [AX], [BX])[0]
+    ab = [np.asfortranarray(np.abs(x)) for x in (AV, BU, AX, BX)]
+    D = oracle.lr_mult([ab[0]], [ab[1]], [ab[2]], [ab[3]])[0]
+    return G, D

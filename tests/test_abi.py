@@ -47,23 +47,27 @@ def test_version_and_status_strings():
 
 
 def mk(op="dense_ts", prec=0, m=64, n=16, k=64, lda=None, ldb=None, lds=None, ldc=None, a=None, b=None, s=None,
-       c=None, base=BASE):
+       c=None, base=BASE, e=None, lde=None):
     o = lrbg.OPS[op]
     if lda is None:
-        lda = {0: m, 1: k, 2: m}[o]
+        lda = {0: m, 1: k, 2: m, 3: k}[o]
     if ldb is None:
-        ldb = {0: k, 1: k, 2: n}[o]
+        ldb = {0: k, 1: k, 2: n, 3: k}[o]
     if ldc is None:
         ldc = m
     a = base if a is None else a
     b = base + (1 << 30) if b is None else b
     c = base + (2 << 30) if c is None else c
-    if o == 2 and s is None:
+    if o in (2, 3) and s is None:
         s = base + (3 << 30)
+    if o == 3 and e is None:
+        e = base + (4 << 30)
     if lds is None:
-        lds = k if o == 2 else 1
+        lds = {2: k, 3: m}.get(o, 1)
+    if lde is None:
+        lde = n if o == 3 else 1
     return lrbg.lrbg_desc(op=o, prec=prec, m=m, n=n, k=k, lda=lda, ldb=ldb, lds=lds, ldc=ldc, flags=0,
-                          a=a, b=b, s=s, c=c)
+                          lde=lde, reserved=0, a=a, b=b, s=s, c=c, e=e)
 
 
 def status(descs):
@@ -102,6 +106,53 @@ def test_other_ops_validation():
     assert status([d]) == lrbg.LRBG_EINVAL
     d = mk(); d.flags = 1
     assert status([d]) == lrbg.LRBG_EINVAL
+
+
+def test_lrmult_validation_and_accounting():
+    b, r = 1024, 32
+    assert status([mk("lrmult", m=r, n=r, k=b)]) == 0
+    assert status([mk("lrmult", m=r, n=17, k=b)]) == 0
+    assert status([mk("lrmult", m=65, n=16, k=b)]) == lrbg.LRBG_EUNSUPPORTED     # rank > 64
+    assert status([mk("lrmult", m=r, n=r, k=b, prec=1)]) == lrbg.LRBG_EUNSUPPORTED
+    assert status([mk("lrmult", m=r, n=r, k=b, e=0)]) == lrbg.LRBG_EINVAL
+    assert status([mk("lrmult", m=r, n=r, k=b, s=0)]) == lrbg.LRBG_EINVAL
+    assert status([mk("lrmult", m=r, n=r, k=b, lde=r - 1)]) == lrbg.LRBG_EINVAL
+    assert status([mk("lrmult", m=r, n=r, k=b, lds=r - 1)]) == lrbg.LRBG_EINVAL
+    assert status([mk("lrmult", m=r, n=r, k=b, e=BASE + (4 << 30) + 4)]) == lrbg.LRBG_EINVAL   # misaligned
+    assert status([mk("lrmult", m=r, n=r, k=b, c=BASE + (4 << 30) + 8)]) == lrbg.LRBG_EINVAL   # G overlaps X_B
+    d = mk("lrmult", m=r, n=r, k=b); d.reserved = 1
+    assert status([d]) == lrbg.LRBG_EINVAL
+    # e is ignored (may be anything) for the other ops
+    d = mk(); d.e = 12345; d.lde = 0
+    assert status([d]) == 0
+    st = lrbg.lrbg_schedule_stats([mk("lrmult", m=r, n=r, k=b)])
+    assert st["useful_flops"] == pytest.approx(4 * r ** 3 + 2 * r * r * b)   # the paper's Alg. 1 count
+    assert st["hbm_bytes"] == pytest.approx(8 * (2 * b * r + 3 * r * r))
+    assert st["tiles"] == 8 and st["levels"] == 1                           # one tile, padded to 8 XCD slots
+    # X_B written by an INNER of the same call: the product runs one level later
+    T = BASE + (10 << 30)
+    inner = mk("inner", m=r, n=r, k=512, c=T, ldc=r, base=BASE * 3)
+    lm = mk("lrmult", m=r, n=r, k=b, e=T, lde=r)
+    assert lrbg.lrbg_schedule_stats([lm, inner])["levels"] == 2
+    # lr_batched_gemm does not take LRMULT (it has no X_B operand)
+    lib = lrbg.load()
+    one = (ctypes.c_int32 * 1)(8)
+    ptr = (ctypes.c_void_p * 1)(BASE)
+    assert lib.lr_batched_gemm(3, 0, 1, one, one, one, ptr, one, ptr, one, ptr, one, ptr, one, None) == \
+        lrbg.LRBG_EINVAL
+
+
+def test_lrmult_entry_validates_before_launch():
+    lib = lrbg.load()
+    assert lib.lr_batched_lrmult(1, *([None] * 13), None) == lrbg.LRBG_EINVAL
+    assert lib.lr_batched_lrmult(0, *([None] * 13), None) == 0
+    i32 = lambda v: (ctypes.c_int32 * 1)(v)
+    p = lambda v: (ctypes.c_void_p * 1)(v)
+    # rank 65 is rejected by validation (nothing launched, no device touched)
+    st = lib.lr_batched_lrmult(1, i32(512), i32(65), i32(8), p(BASE), i32(512), p(BASE + (1 << 30)), i32(512),
+                               p(BASE + (2 << 30)), i32(65), p(BASE + (3 << 30)), i32(8), p(BASE + (4 << 30)),
+                               i32(65), None)
+    assert st == lrbg.LRBG_EUNSUPPORTED
 
 
 def test_empty_and_zero_sizes():
