@@ -50,7 +50,7 @@ static lrbg_status fail(lrbg_status st, const char *fmt, ...)
 static const VariantInfo kVariants[kNumVariants] = {
     {K_NOP, 0, 0, 0, 0},
 #define LRBG_INFO(id, kind, p1, p2, p3, p4) {kind, p1, p2, p3, p4},
-    LRBG_VARIANTS(LRBG_INFO)
+    LRBG_ALL_VARIANTS(LRBG_INFO)
 #undef LRBG_INFO
 };
 
@@ -404,6 +404,8 @@ struct Level {
     int64_t tile_off = 0;   // into the plan's tile array
     int32_t ntiles = 0;     // grid of the one-workgroup-per-tile launch
     int32_t qinfo_off = 0;  // 9 queue offsets (persistent mode)
+    int64_t lrm_off = 0;    // fused low-rank product tiles (their own kernel)
+    int32_t lrm_ntiles = 0;
     int32_t grid = 0;
 };
 
@@ -502,8 +504,8 @@ static lrbg_status compute_levels(const lrbg_desc *ds, int64_t n, std::vector<in
 // bin, so tiles sharing its operands share an L2); within a bin products run
 // longest first (or interleaved compute-/memory-bound with SCHED_MIX); the
 // bins are interleaved so that tile t is dispatched to XCD t % 8.
-static void layout_level(const std::vector<int64_t> &prods, const lrbg_desc *ds, const std::vector<int> &variant,
-                         uint32_t flags, Schedule &sch, Level &lv)
+static void lay_tiles(const std::vector<int64_t> &prods, const lrbg_desc *ds, const std::vector<int> &variant,
+                      uint32_t flags, Schedule &sch, int64_t &tile_off, int32_t &ntiles, bool queues)
 {
     struct P {
         int64_t i;
@@ -560,8 +562,7 @@ static void layout_level(const std::vector<int64_t> &prods, const lrbg_desc *ds,
         maxlen = std::max(maxlen, v.size());
         total += v.size();
     }
-    lv.tile_off = (int64_t)sch.tiles.size();
-    lv.qinfo_off = (int32_t)sch.qinfo.size();
+    tile_off = (int64_t)sch.tiles.size();
     if (flags & LRBG_PLAN_PERSISTENT) {
         // queue q = bins[q], contiguous
         int32_t off = 0;
@@ -571,15 +572,28 @@ static void layout_level(const std::vector<int64_t> &prods, const lrbg_desc *ds,
             off += (int32_t)bt[b].size();
         }
         sch.qinfo.push_back(off);
-        lv.ntiles = off;
+        ntiles = off;
     } else {
         for (size_t slot = 0; slot < maxlen; ++slot)
             for (int b = 0; b < kXcds; ++b)
                 sch.tiles.push_back(slot < bt[b].size() ? bt[b][slot] : Tile{0, 0, 0, 0});
-        lv.ntiles = (int32_t)(maxlen * kXcds);
-        for (int b = 0; b <= kXcds; ++b) sch.qinfo.push_back(0);
+        ntiles = (int32_t)(maxlen * kXcds);
+        if (queues)
+            for (int b = 0; b <= kXcds; ++b) sch.qinfo.push_back(0);
     }
     (void)total;
+}
+
+// A level's products go to two kernels: the grouped kernel (or its
+// persistent form) and the fused low-rank product kernel.
+static void layout_level(const std::vector<int64_t> &prods, const lrbg_desc *ds, const std::vector<int> &variant,
+                         uint32_t flags, Schedule &sch, Level &lv)
+{
+    std::vector<int64_t> grouped, lrm;
+    for (int64_t i : prods) (kVariants[variant[(size_t)i]].kind == K_LRM ? lrm : grouped).push_back(i);
+    lv.qinfo_off = (int32_t)sch.qinfo.size();
+    lay_tiles(grouped, ds, variant, flags, sch, lv.tile_off, lv.ntiles, true);
+    lay_tiles(lrm, ds, variant, flags & ~LRBG_PLAN_PERSISTENT, sch, lv.lrm_off, lv.lrm_ntiles, false);
 }
 
 static lrbg_status build_schedule(const lrbg_desc *ds, int64_t n, const TuneTable &tt, uint32_t flags,
@@ -644,8 +658,8 @@ static lrbg_status build_schedule(const lrbg_desc *ds, int64_t n, const TuneTabl
     int64_t ntiles = 0;
     int32_t grid = 0;
     for (auto &lv : sch.levels) {
-        ntiles += lv.ntiles;
-        grid = std::max(grid, lv.ntiles);
+        ntiles += lv.ntiles + lv.lrm_ntiles;
+        grid = std::max(grid, std::max(lv.ntiles, lv.lrm_ntiles));
     }
     sch.stats.products = n;
     sch.stats.tiles = ntiles;
@@ -676,6 +690,10 @@ static int persistent_grid()
 static lrbg_status enqueue_levels(lrbg_plan *p, hipStream_t stream)
 {
     for (auto &lv : p->levels) {
+        if (lv.lrm_ntiles > 0) {
+            const int rc = launch_lrmult(p->d_descs, p->d_tiles + lv.lrm_off, lv.lrm_ntiles, stream);
+            if (rc) return fail(LRBG_EDEVICE, "lrmult launch failed: %s", hipGetErrorString((hipError_t)rc));
+        }
         if (lv.ntiles <= 0) continue;
         int rc;
         if (p->flags & LRBG_PLAN_PERSISTENT) {
@@ -815,8 +833,8 @@ static lrbg_status run_once(const lrbg_desc *ds, int64_t n, hipStream_t stream)
     const DevDesc *dd = (const DevDesc *)sg->dev;
     const Tile *dt = (const Tile *)((char *)sg->dev + toff);
     for (auto &lv : sch.levels) {
-        if (lv.ntiles <= 0) continue;
-        int rc = launch_grouped(dd, dt + lv.tile_off, lv.ntiles, stream);
+        int rc = lv.lrm_ntiles > 0 ? launch_lrmult(dd, dt + lv.lrm_off, lv.lrm_ntiles, stream) : 0;
+        if (!rc && lv.ntiles > 0) rc = launch_grouped(dd, dt + lv.tile_off, lv.ntiles, stream);
         if (rc) {
             st = fail(LRBG_EDEVICE, "grouped launch failed: %s", hipGetErrorString((hipError_t)rc));
             break;

@@ -55,6 +55,9 @@ constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies
 
 // X(id, kind, p1, p2, p3, p4): the compiled tile variants.  Ids are dense
 // and stable within a build; tuning caches refer to variants by name.
+// LRBG_VARIANTS run in the grouped kernel; LRBG_LRM_VARIANTS (the fused
+// low-rank product) in a kernel of their own, so that their code and
+// register pressure stay out of the grouped kernel.
 #define LRBG_VARIANTS(X)              \
     X(1, K_DTS64, 1, 1, 8, 0)         \
     X(2, K_DTS64, 2, 1, 8, 0)         \
@@ -93,10 +96,14 @@ constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies
     X(35, K_INN3, 2, 2, 4, 1)         \
     X(36, K_INN3, 1, 4, 4, 1)         \
     X(37, K_INN3, 1, 8, 4, 0)         \
-    X(38, K_INN3, 2, 2, 2, 1)         \
+    X(38, K_INN3, 2, 2, 2, 1)
+
+#define LRBG_LRM_VARIANTS(X)          \
     X(39, K_LRM, 1, 1, 4, 8)          \
     X(40, K_LRM, 2, 2, 4, 8)          \
     X(41, K_LRM, 2, 4, 2, 4)
+
+#define LRBG_ALL_VARIANTS(X) LRBG_VARIANTS(X) LRBG_LRM_VARIANTS(X)
 
 constexpr int kNumVariants = 42;   // ids 0..41 (0 = no-op tile)
 
@@ -109,6 +116,7 @@ int launch_grouped(const DevDesc *descs, const Tile *tiles, int ntiles, void *st
 int launch_persistent(const DevDesc *descs, const Tile *tiles, const int32_t *qinfo,
                       int32_t *counters, int grid, void *stream);
 int launch_reset(int32_t *counters, int n, void *stream);
+int launch_lrmult(const DevDesc *descs, const Tile *tiles, int ntiles, void *stream);
 int persistent_blocks_per_cu();
 
 }  // namespace lrbg

@@ -1239,6 +1239,22 @@ __device__ __forceinline__ void run_tile(const DevDesc *__restrict__ descs, cons
     }
 }
 
+__device__ __forceinline__ void run_lrm_tile(const DevDesc *__restrict__ descs, const Tile &t, double *lds)
+{
+    if (t.variant <= 0) return;
+    const DevDesc d = descs[t.desc];
+    const bool edge = (t.flags & kTileEdge) != 0;
+    switch (t.variant) {
+#define LRBG_CASE(id, kind, p1, p2, p3, p4) \
+    case id:                                \
+        run_variant<kind, p1, p2, p3, p4>(d, t.p0, edge, lds); break;
+        LRBG_LRM_VARIANTS(LRBG_CASE)
+#undef LRBG_CASE
+    default:
+        break;
+    }
+}
+
 // Out-of-line tile call for the persistent kernel: keeps each variant's
 // register state out of the persistent loop.
 __device__ __noinline__ void run_tile_call(const DevDesc *__restrict__ descs, const Tile *tp, double *lds)
@@ -1284,6 +1300,18 @@ lrbg_persistent_kernel(const DevDesc *__restrict__ descs, const Tile *__restrict
     }
 }
 
+// The fused low-rank products, one workgroup per tile (same tile layout and
+// XCD interleave as the grouped kernel).
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+lrbg_lrmult_kernel(const DevDesc *__restrict__ descs, const Tile *__restrict__ tiles, int ntiles)
+{
+    __shared__ double lds[kLdsBytes / 8];
+    const int t = blockIdx.x;
+    if (t >= ntiles) return;
+    const Tile tl = tiles[t];
+    run_lrm_tile(descs, tl, lds);
+}
+
 __global__ void lrbg_reset_kernel(int32_t *counters, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1304,6 +1332,14 @@ int launch_persistent(const DevDesc *descs, const Tile *tiles, const int32_t *qi
     if (grid <= 0) return 0;
     hipLaunchKernelGGL(lrbg_persistent_kernel, dim3(grid), dim3(kThreads), 0, (hipStream_t)stream, descs, tiles,
                        qinfo, counters);
+    return (int)hipGetLastError();
+}
+
+int launch_lrmult(const DevDesc *descs, const Tile *tiles, int ntiles, void *stream)
+{
+    if (ntiles <= 0) return 0;
+    hipLaunchKernelGGL(lrbg_lrmult_kernel, dim3(ntiles), dim3(kThreads), 0, (hipStream_t)stream, descs, tiles,
+                       ntiles);
     return (int)hipGetLastError();
 }
 
