@@ -1,6 +1,6 @@
 """Build ``liblrbg.so`` (the C-ABI library) with hipcc for gfx950.
 
-Always recompiles.  Packed-FP32 instructions are disabled in the device code
+Always recompiles (the sources in parallel).  Packed-FP32 instructions are disabled in the device code
 generator.  The library depends on the HIP runtime by its SONAME
 (libamdhip64.so.7), so in a process that has already loaded PyTorch's bundled
 copy of the runtime (same SONAME) it binds to that one; standalone it
@@ -34,14 +34,22 @@ def _run(cmd, verbose):
         print("\n".join(msgs))
 
 
+SOURCES = ("lrbg_kernels.hip", "lrbg_lrmult.hip", "lrbg_host.cpp")
+
+
 def build(verbose: bool = False) -> str:
+    """Compile every source (in parallel, one process each) and link."""
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
-    for src in ("lrbg_kernels.hip", "lrbg_host.cpp"):
+    cmds, objs = [], []
+    for src in SOURCES:
         obj = os.path.join(BUILD, src.rsplit(".", 1)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        _run([HIPCC, *COMMON, *lang, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        cmds.append([HIPCC, *COMMON, *lang, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    with ThreadPoolExecutor(len(cmds)) as ex:
+        for f in [ex.submit(_run, c, verbose) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     link_rt = ["-L", os.path.join(ROCM, "lib"), "-lamdhip64"]
     clang = os.path.join(ROCM, "llvm", "bin", "clang++")

@@ -68,6 +68,7 @@ static std::string variant_name(int v)
     case K_DTSL: snprintf(buf, sizeof buf, "dtsl_rm%d_rn%d_kg%d", vi.p1, vi.p2, vi.p3); break;
     case K_INNL: snprintf(buf, sizeof buf, "innl_ri%d_rj%d_wr%d_kg%d", vi.p1, vi.p2, vi.p3, vi.p4); break;
     case K_LRM: snprintf(buf, sizeof buf, "lrm_ri%d_rj%d_ks%d_kg%d", vi.p1, vi.p2, vi.p3, vi.p4); break;
+    case K_LRM4: snprintf(buf, sizeof buf, "lrm4_ri%d_rj%d_ks%d_kg%d", vi.p1, vi.p2, vi.p3, vi.p4); break;
     default: snprintf(buf, sizeof buf, "v%d", v);
     }
     return buf;
@@ -94,6 +95,7 @@ static bool kind_matches(int kind, int op, int prec)
     if (kind == base) return base != K_NOP;
     if (prec == LRBG_FP64 && op == LRBG_OP_DENSE_TS) return kind == K_DTSL;
     if (prec == LRBG_FP64 && op == LRBG_OP_INNER) return kind == K_INNL;
+    if (prec == LRBG_FP64 && op == LRBG_OP_LRMULT) return kind == K_LRM4;
     return false;
 }
 
@@ -110,7 +112,7 @@ static bool variant_fits(int v, const lrbg_desc &d)
     case K_DTS3: return d.n <= 16 * vi.p2;
     case K_INN64: return d.n <= 16 * vi.p2;
     case K_INN3: return d.n <= 16 * vi.p2;
-    case K_LRM: return d.m <= 16 * vi.p1 * (4 / vi.p3) && d.n <= 16 * vi.p2;
+    case K_LRM: case K_LRM4: return d.m <= 16 * vi.p1 * (4 / vi.p3) && d.n <= 16 * vi.p2;
     case K_REC64: {
         const int kp = (d.k + 15) / 16 * 16;
         return (size_t)kp * 16 * vi.p2 * 8 <= (size_t)kLdsBytes;
@@ -135,7 +137,7 @@ static void tiles_of(int v, const lrbg_desc &d, std::vector<int32_t> &p0s, std::
         step = 16 * vi.p1 * (4 / vi.p3); extent = d.m; kc = 4 * vi.p4; break;
     case K_INN3:
         step = 16 * vi.p1 * (4 / vi.p3); extent = d.m; kc = 32; break;
-    case K_LRM:   // one tile per product (variant_fits: m <= step)
+    case K_LRM: case K_LRM4:   // one tile per product (variant_fits: m <= step)
         step = 16 * vi.p1 * (4 / vi.p3); extent = d.m; kc = 4 * vi.p4; break;
     case K_INNL:
         step = 16 * vi.p1 * vi.p3; extent = d.m; kc = 4 * vi.p4; break;
@@ -220,8 +222,8 @@ static int default_variant(const lrbg_desc &d)
     }
     if (kind == K_LRM) {
         const int rr = std::max(d.m, d.n);
-        if (rr <= 16) return pick({39});
-        if (rr <= 32) return pick({40});
+        if (rr <= 16) return pick({42, 39});   // 4 workgroups per CU: memory-bound, latency-limited
+        if (rr <= 32) return pick({40, 44});
         return pick({41});
     }
     if (kind == K_REC64) {
@@ -401,11 +403,9 @@ static bool compute_bound(const lrbg_desc &d)
 // ------------------------------------------------------------- plans
 
 struct Level {
-    int64_t tile_off = 0;   // into the plan's tile array
-    int32_t ntiles = 0;     // grid of the one-workgroup-per-tile launch
-    int32_t qinfo_off = 0;  // 9 queue offsets (persistent mode)
-    int64_t lrm_off = 0;    // fused low-rank product tiles (their own kernel)
-    int32_t lrm_ntiles = 0;
+    int64_t off[kFamilies] = {};   // per kernel family: first tile in the plan's tile array
+    int32_t n[kFamilies] = {};     // and the grid of its one-workgroup-per-tile launch
+    int32_t qinfo_off = 0;         // 9 queue offsets (persistent mode, grouped family)
     int32_t grid = 0;
 };
 
@@ -584,16 +584,23 @@ static void lay_tiles(const std::vector<int64_t> &prods, const lrbg_desc *ds, co
     (void)total;
 }
 
-// A level's products go to two kernels: the grouped kernel (or its
-// persistent form) and the fused low-rank product kernel.
+static int family_of(int v)
+{
+    const int kind = kVariants[v].kind;
+    return kind == K_LRM ? F_LRM : kind == K_LRM4 ? F_LRM4 : F_GROUPED;
+}
+
+// A level's products go to one kernel per family: the grouped kernel (or
+// its persistent form) and the two fused low-rank product kernels.
 static void layout_level(const std::vector<int64_t> &prods, const lrbg_desc *ds, const std::vector<int> &variant,
                          uint32_t flags, Schedule &sch, Level &lv)
 {
-    std::vector<int64_t> grouped, lrm;
-    for (int64_t i : prods) (kVariants[variant[(size_t)i]].kind == K_LRM ? lrm : grouped).push_back(i);
+    std::vector<int64_t> fam[kFamilies];
+    for (int64_t i : prods) fam[family_of(variant[(size_t)i])].push_back(i);
     lv.qinfo_off = (int32_t)sch.qinfo.size();
-    lay_tiles(grouped, ds, variant, flags, sch, lv.tile_off, lv.ntiles, true);
-    lay_tiles(lrm, ds, variant, flags & ~LRBG_PLAN_PERSISTENT, sch, lv.lrm_off, lv.lrm_ntiles, false);
+    for (int f = 0; f < kFamilies; ++f)
+        lay_tiles(fam[f], ds, variant, f == F_GROUPED ? flags : flags & ~LRBG_PLAN_PERSISTENT, sch, lv.off[f],
+                  lv.n[f], f == F_GROUPED);
 }
 
 static lrbg_status build_schedule(const lrbg_desc *ds, int64_t n, const TuneTable &tt, uint32_t flags,
@@ -657,10 +664,11 @@ static lrbg_status build_schedule(const lrbg_desc *ds, int64_t n, const TuneTabl
     if (sch.descs.empty()) sch.descs.push_back(DevDesc{});
     int64_t ntiles = 0;
     int32_t grid = 0;
-    for (auto &lv : sch.levels) {
-        ntiles += lv.ntiles + lv.lrm_ntiles;
-        grid = std::max(grid, std::max(lv.ntiles, lv.lrm_ntiles));
-    }
+    for (auto &lv : sch.levels)
+        for (int f = 0; f < kFamilies; ++f) {
+            ntiles += lv.n[f];
+            grid = std::max(grid, lv.n[f]);
+        }
     sch.stats.products = n;
     sch.stats.tiles = ntiles;
     sch.stats.levels = (int32_t)sch.levels.size();
@@ -690,19 +698,19 @@ static int persistent_grid()
 static lrbg_status enqueue_levels(lrbg_plan *p, hipStream_t stream)
 {
     for (auto &lv : p->levels) {
-        if (lv.lrm_ntiles > 0) {
-            const int rc = launch_lrmult(p->d_descs, p->d_tiles + lv.lrm_off, lv.lrm_ntiles, stream);
+        for (int f = F_GROUPED + 1; f < kFamilies; ++f) {
+            const int rc = launch_family(f, p->d_descs, p->d_tiles + lv.off[f], lv.n[f], stream);
             if (rc) return fail(LRBG_EDEVICE, "lrmult launch failed: %s", hipGetErrorString((hipError_t)rc));
         }
-        if (lv.ntiles <= 0) continue;
+        if (lv.n[F_GROUPED] <= 0) continue;
         int rc;
         if (p->flags & LRBG_PLAN_PERSISTENT) {
             rc = launch_reset(p->d_counters + lv.qinfo_off, kXcds, stream);
             if (rc) return fail(LRBG_EDEVICE, "reset launch failed: %s", hipGetErrorString((hipError_t)rc));
-            rc = launch_persistent(p->d_descs, p->d_tiles + lv.tile_off, p->d_qinfo + lv.qinfo_off,
-                                   p->d_counters + lv.qinfo_off, std::min(lv.grid, lv.ntiles), stream);
+            rc = launch_persistent(p->d_descs, p->d_tiles + lv.off[F_GROUPED], p->d_qinfo + lv.qinfo_off,
+                                   p->d_counters + lv.qinfo_off, std::min(lv.grid, lv.n[F_GROUPED]), stream);
         } else {
-            rc = launch_grouped(p->d_descs, p->d_tiles + lv.tile_off, lv.ntiles, stream);
+            rc = launch_family(F_GROUPED, p->d_descs, p->d_tiles + lv.off[F_GROUPED], lv.n[F_GROUPED], stream);
         }
         if (rc) return fail(LRBG_EDEVICE, "grouped launch failed: %s", hipGetErrorString((hipError_t)rc));
     }
@@ -833,8 +841,8 @@ static lrbg_status run_once(const lrbg_desc *ds, int64_t n, hipStream_t stream)
     const DevDesc *dd = (const DevDesc *)sg->dev;
     const Tile *dt = (const Tile *)((char *)sg->dev + toff);
     for (auto &lv : sch.levels) {
-        int rc = lv.lrm_ntiles > 0 ? launch_lrmult(dd, dt + lv.lrm_off, lv.lrm_ntiles, stream) : 0;
-        if (!rc && lv.ntiles > 0) rc = launch_grouped(dd, dt + lv.tile_off, lv.ntiles, stream);
+        int rc = 0;
+        for (int f = 0; f < kFamilies && !rc; ++f) rc = launch_family(f, dd, dt + lv.off[f], lv.n[f], stream);
         if (rc) {
             st = fail(LRBG_EDEVICE, "grouped launch failed: %s", hipGetErrorString((hipError_t)rc));
             break;

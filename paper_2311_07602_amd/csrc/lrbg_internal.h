@@ -43,7 +43,18 @@ enum Kind : int32_t {
     K_DTSL = 6,    // DENSE_TS, FP64, U in LDS     params: RM, RN, KG
     K_INNL = 7,    // INNER, FP64, LDS-staged      params: RI, RJ, WR, KG
     K_LRM = 8,     // LRMULT, FP64, fused          params: RI, RJ, KS, KG (INNER phase)
+    K_LRM4 = 9,    // as K_LRM in the high-occupancy fused kernel (32 KB LDS, <= 128 VGPRs)
 };
+
+// Kernel families: each family of variants is compiled into its own kernel
+// and a plan level issues one launch per non-empty family.
+enum Family : int32_t {
+    F_GROUPED = 0,   // lrbg_grouped_kernel / lrbg_persistent_kernel
+    F_LRM = 1,       // lrbg_lrmult_kernel: 64 KB LDS, 2 workgroups per CU
+    F_LRM4 = 2,      // lrbg_lrmult4_kernel: 32 KB LDS, 4 workgroups per CU
+};
+constexpr int kFamilies = 3;
+constexpr int kLdsBytes4 = 32768;
 
 constexpr int kThreads = 256;       // 4 wavefronts of 64
 constexpr int kWaves = 4;
@@ -103,20 +114,26 @@ constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies
     X(40, K_LRM, 2, 2, 4, 8)          \
     X(41, K_LRM, 2, 4, 2, 4)
 
-#define LRBG_ALL_VARIANTS(X) LRBG_VARIANTS(X) LRBG_LRM_VARIANTS(X)
+#define LRBG_LRM4_VARIANTS(X)         \
+    X(42, K_LRM4, 1, 1, 4, 8)         \
+    X(43, K_LRM4, 1, 1, 4, 4)         \
+    X(44, K_LRM4, 1, 2, 2, 4)         \
+    X(45, K_LRM4, 2, 2, 4, 2)
 
-constexpr int kNumVariants = 42;   // ids 0..41 (0 = no-op tile)
+#define LRBG_ALL_VARIANTS(X) LRBG_VARIANTS(X) LRBG_LRM_VARIANTS(X) LRBG_LRM4_VARIANTS(X)
+
+constexpr int kNumVariants = 46;   // ids 0..45 (0 = no-op tile)
 
 struct VariantInfo {
     int32_t kind, p1, p2, p3, p4;
 };
 
-// Kernel launch helpers (defined in lrbg_kernels.hip).
-int launch_grouped(const DevDesc *descs, const Tile *tiles, int ntiles, void *stream);
+// Kernel launch helpers (defined in lrbg_kernels.hip and lrbg_lrmult.hip).
 int launch_persistent(const DevDesc *descs, const Tile *tiles, const int32_t *qinfo,
                       int32_t *counters, int grid, void *stream);
 int launch_reset(int32_t *counters, int n, void *stream);
-int launch_lrmult(const DevDesc *descs, const Tile *tiles, int ntiles, void *stream);
+int launch_family(int family, const DevDesc *descs, const Tile *tiles, int ntiles, void *stream);
+int launch_lrm_family(int family, const DevDesc *descs, const Tile *tiles, int ntiles, void *stream);
 int persistent_blocks_per_cu();
 
 }  // namespace lrbg

@@ -1,0 +1,223 @@
+// Kernels of the fused low-rank product G = X_A (V_A^T U_B) X_B (Alg. 1).
+// They share the INNER accumulation of lrbg_tiles.h with the grouped kernel
+// but are compiled into kernels of their own, each with the LDS size and
+// register budget its tiles need.
+#include "lrbg_tiles.h"
+
+namespace lrbg {
+
+// ---------------------------------------------------------------------------
+// LRMULT, FP64, fused.  G = X_A (V_A^T U_B) X_B for one product per
+// workgroup (ranks m, n <= R = 16 RI NG = 16 RJ), in the order of Alg. 1:
+//   C = V_A^T U_B   the INNER accumulation above (the long k = b contraction)
+//   E = X_A C       from LDS, on the matrix cores
+//   G = E X_B       from LDS, on the matrix cores; only G is written to HBM.
+// Alg. 2 fuses the same chain so that the rank-sized intermediates never
+// leave the cache; here they never leave LDS.  LDS (LDSD doubles), R x R
+// doubles each:
+//   R0 (bottom): C row-major (the E phase reads C(kk, J0 + c): consecutive
+//       lanes, consecutive banks), then E column-major (the G phase reads
+//       E(I0 + rho(c), kk), again consecutive)
+//   R1 (top, clear of the reduction slots of the C phase): X_A column-major,
+//       then X_B row-major.
+// X_A is fetched before the long contraction and parked in R1 once the first
+// chunk's loads are in flight; X_B is fetched with it when it fits in a few
+// registers, else at the start of the E phase.  The small contractions run
+// over k in steps of 4 with k >= rank read as 0; rows and columns beyond the
+// ranks hold finite filler and are never stored.
+template <int RI, int RJ, int KS, int KG, bool GUARD, int LDSD>
+__device__ __forceinline__ void lrm_tile(const DevDesc &d, int i0, double *lds)
+{
+    constexpr int NG = 4 / KS;
+    constexpr int R = 16 * RJ;
+    static_assert(16 * RI * NG == R, "LRMULT tile covers a square R x R core");
+    constexpr int SLOTS = (KS - 1) * NG * RI * RJ * 4 * 64;   // reduction doubles of the C phase
+    static_assert(SLOTS + R * R <= LDSD && 2 * R * R <= LDSD, "LRMULT staging exceeds LDS");
+    constexpr int XE = (R * R + kThreads - 1) / kThreads;   // X elements per thread
+    constexpr bool XB_EARLY = XE <= 4;
+    constexpr int NB = R / 16;                             // 16 x 16 blocks per side
+    constexpr int QB = (NB * NB + kWaves - 1) / kWaves;    // blocks per wave
+    const int tid = threadIdx.x, lane = tid & 63, c = lane & 15, g = lane >> 4, w = tid >> 6;
+    const int ra = d.m, rb = d.n;
+    double *R0 = lds, *R1 = lds + LDSD - R * R;
+
+    // Thread tid takes linear elements idx = tid + 256 e of the R x R square
+    // (row = idx % R, col = idx / R): coalesced down the columns.
+    auto fetch = [&](double (&x)[XE], const double *p, int ld, int r) {
+#pragma unroll
+        for (int e = 0; e < XE; ++e) {
+            const int idx = tid + kThreads * e, row = idx % R, col = idx / R;
+            x[e] = (idx < R * R && row < r && col < r) ? gin(p)[row + (size_t)col * ld] : 0.0;
+        }
+    };
+    double xa[XE], xb[XE];
+    fetch(xa, d.s, d.lds, ra);
+    if constexpr (XB_EARLY) fetch(xb, d.e, d.lde, rb);
+
+    d4 acc[RI][RJ];
+    inn64_accumulate<RI, RJ, KS, KG, GUARD>(d, i0, lds, acc, [&] {
+#pragma unroll
+        for (int e = 0; e < XE; ++e) {
+            const int idx = tid + kThreads * e;
+            if (idx < R * R) R1[idx] = xa[e];   // column-major
+        }
+    });
+
+    // C -> R0, row-major
+    const int og = w / KS, ks = w % KS;
+    if (ks == 0) {
+        const int rowbase = i0 + og * 16 * RI;
+#pragma unroll
+        for (int bi = 0; bi < RI; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < RJ; ++bj)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) R0[(rowbase + bi * 16 + 4 * g + v) * R + bj * 16 + c] = acc[bi][bj][v];
+    }
+    __syncthreads();
+    if constexpr (!XB_EARLY) fetch(xb, d.e, d.lde, rb);
+
+    // Wave w owns output blocks q = w + 4 qq (I-blocks fastest).
+    const int nbi = (ra + 15) / 16, nbj = (rb + 15) / 16, nb = nbi * nbj;
+    int I0[QB], J0[QB];
+#pragma unroll
+    for (int qq = 0; qq < QB; ++qq) {
+        const int q = w + kWaves * qq;
+        I0[qq] = q < nb ? (q % nbi) * 16 : 0;
+        J0[qq] = q < nb ? (q / nbi) * 16 : 0;
+    }
+    d4 o[QB];
+
+    // E = X_A C, contraction over ra
+#pragma unroll
+    for (int qq = 0; qq < QB; ++qq) o[qq] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int l0 = 0; l0 < ra; l0 += 4) {
+        const bool ok = l0 + g < ra;
+        const int kk = ok ? l0 + g : 0;   // masked lanes read a valid LDS address
+#pragma unroll
+        for (int qq = 0; qq < QB; ++qq) {
+            if (w + kWaves * qq >= nb) continue;
+            const double a = ok ? R1[I0[qq] + rho(c) + kk * R] : 0.0;
+            const double b = ok ? R0[kk * R + J0[qq] + c] : 0.0;
+            o[qq] = mfma64(a, b, o[qq]);
+        }
+    }
+    __syncthreads();   // C and X_A are dead
+
+    // E -> R0 (column-major), X_B -> R1 (row-major)
+#pragma unroll
+    for (int qq = 0; qq < QB; ++qq) {
+        if (w + kWaves * qq >= nb) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) R0[I0[qq] + 4 * g + v + (J0[qq] + c) * R] = o[qq][v];
+    }
+#pragma unroll
+    for (int e = 0; e < XE; ++e) {
+        const int idx = tid + kThreads * e, row = idx % R, col = idx / R;
+        if (idx < R * R) R1[row * R + col] = xb[e];
+    }
+    __syncthreads();
+
+    // G = E X_B, contraction over rb
+#pragma unroll
+    for (int qq = 0; qq < QB; ++qq) o[qq] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int l0 = 0; l0 < rb; l0 += 4) {
+        const bool ok = l0 + g < rb;
+        const int kk = ok ? l0 + g : 0;
+#pragma unroll
+        for (int qq = 0; qq < QB; ++qq) {
+            if (w + kWaves * qq >= nb) continue;
+            const double a = ok ? R0[I0[qq] + rho(c) + kk * R] : 0.0;
+            const double b = ok ? R1[kk * R + J0[qq] + c] : 0.0;
+            o[qq] = mfma64(a, b, o[qq]);
+        }
+    }
+    const size_t ldg = (size_t)d.ldc;
+#pragma unroll
+    for (int qq = 0; qq < QB; ++qq) {
+        if (w + kWaves * qq >= nb) continue;
+        const int orow = I0[qq] + 4 * g, col = J0[qq] + c;
+        if (orow >= ra || col >= rb) continue;
+        double out[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[v] = o[qq][v];
+        store_run<4, true>(gout(d.c) + orow + (size_t)col * ldg, out, ra - orow, false);
+    }
+    __syncthreads();   // LDS is reused by the next tile of a persistent workgroup
+}
+
+template <int KIND, int P1, int P2, int P3, int P4>
+__device__ __forceinline__ void run_lrm_variant(const DevDesc &d, int p0, bool edge, double *lds)
+{
+    constexpr int LDSD = (KIND == K_LRM ? kLdsBytes : kLdsBytes4) / 8;
+    if (edge)
+        lrm_tile<P1, P2, P3, P4, true, LDSD>(d, p0, lds);
+    else
+        lrm_tile<P1, P2, P3, P4, false, LDSD>(d, p0, lds);
+}
+
+template <int FAMILY>
+__device__ __forceinline__ void run_lrm_tile(const DevDesc *__restrict__ descs, const Tile &t, double *lds)
+{
+    if (t.variant <= 0) return;
+    const DevDesc d = descs[t.desc];
+    const bool edge = (t.flags & kTileEdge) != 0;
+#define LRBG_CASE(id, kind, p1, p2, p3, p4) \
+    case id:                                \
+        run_lrm_variant<kind, p1, p2, p3, p4>(d, t.p0, edge, lds); break;
+    if constexpr (FAMILY == F_LRM) {
+        switch (t.variant) {
+            LRBG_LRM_VARIANTS(LRBG_CASE)
+        default:
+            break;
+        }
+    } else {
+        switch (t.variant) {
+            LRBG_LRM4_VARIANTS(LRBG_CASE)
+        default:
+            break;
+        }
+    }
+#undef LRBG_CASE
+}
+
+// The fused low-rank products, one workgroup per tile (same tile layout and
+// XCD interleave as the grouped kernel): ranks up to 64 with 64 KB of LDS
+// (2 workgroups per CU), and ranks up to 32 with 32 KB and at most 128
+// VGPRs (4 workgroups per CU, twice the loads in flight per CU for the
+// memory-bound small ranks).
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2)))
+lrbg_lrmult_kernel(const DevDesc *__restrict__ descs, const Tile *__restrict__ tiles, int ntiles)
+{
+    __shared__ double lds[kLdsBytes / 8];
+    const int t = blockIdx.x;
+    if (t >= ntiles) return;
+    const Tile tl = tiles[t];
+    run_lrm_tile<F_LRM>(descs, tl, lds);
+}
+
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4)))
+lrbg_lrmult4_kernel(const DevDesc *__restrict__ descs, const Tile *__restrict__ tiles, int ntiles)
+{
+    __shared__ double lds[kLdsBytes4 / 8];
+    const int t = blockIdx.x;
+    if (t >= ntiles) return;
+    const Tile tl = tiles[t];
+    run_lrm_tile<F_LRM4>(descs, tl, lds);
+}
+
+int launch_lrm_family(int family, const DevDesc *descs, const Tile *tiles, int ntiles, void *stream)
+{
+    if (ntiles <= 0) return 0;
+    const dim3 grid(ntiles), block(kThreads);
+    hipStream_t s = (hipStream_t)stream;
+    if (family == F_LRM)
+        hipLaunchKernelGGL(lrbg_lrmult_kernel, grid, block, 0, s, descs, tiles, ntiles);
+    else if (family == F_LRM4)
+        hipLaunchKernelGGL(lrbg_lrmult4_kernel, grid, block, 0, s, descs, tiles, ntiles);
+    else
+        return (int)hipErrorInvalidValue;
+    return (int)hipGetLastError();
+}
+
+}  // namespace lrbg

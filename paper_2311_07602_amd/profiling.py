@@ -22,7 +22,7 @@ import statistics
 from typing import Dict, List, Optional
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ["csrc/lrbg_kernels.hip", "csrc/lrbg_internal.h", "tune/mi355x.tune"]
+KERNEL_SOURCES = ["csrc/lrbg_kernels.hip", "csrc/lrbg_tiles.h", "csrc/lrbg_internal.h", "tune/mi355x.tune"]
 
 
 def source_digest() -> str:
