@@ -14,7 +14,8 @@ skinny batch (64 x 256x256 . 256x16, buffer sets rotated so the 38 MB batch
 does not sit in the 256 MB last-level cache) and the low-rank x low-rank
 chain (4096 instances, b = 512, r = 32: inner products, then recompression),
 the paper's fused low-rank product G = X_A (V_A^T U_B) X_B at batch 20 000
-for b in {512, 1024, 2048} and r in {8, 16, 32}, and the serving loop.
+for b in {512, 1024, 2048} and r in {8, 16, 32, 96, 128}, and the serving
+loop.
 
   python bench.py [--steps K] [--warmup W] [--extras/--no-extras]
   python bench.py --calibrate-copy      # plain 1 GiB device copy (counter scaling)
@@ -188,7 +189,7 @@ def run_chain(count=4096, b=512, r=32, steps=20, warmup=3, prec="fp64"):
             "frac_of_roofline_time": round(roof / ms, 4), "bound": "hbm"}
 
 
-def run_lrmult_paper(count=20000, bs=(512, 1024, 2048), rs=(8, 16, 32), steps=10, warmup=2):
+def run_lrmult_paper(count=20000, bs=(512, 1024, 2048), rs=(8, 16, 32, 96, 128), steps=10, warmup=2):
     """The paper's batched low-rank product G = X_A (V_A^T U_B) X_B at its
     measured shapes (batch 20 000 per (b, r)); GFLOP/s by the paper's count
     4 r^3 + 2 r^2 b per instance."""
@@ -211,7 +212,7 @@ def run_lrmult_paper(count=20000, bs=(512, 1024, 2048), rs=(8, 16, 32), steps=10
                         "GB/s": round(by / ms / 1e6, 1), "frac_of_roofline_time": round(roof / ms, 4)})
             log(f"[bench] lrmult b={b} r={r}: {ms:.4f} ms, {f / ms / 1e6:.0f} GFLOP/s, {by / ms / 1e6:.0f} GB/s")
     return {"workload": f"{count} x G = X_A (V_A^T U_B) X_B per (b, r), FP64, N(0,1), fused (one tile per "
-                        f"instance)", "flops_per_instance": "4 r^3 + 2 r^2 b", "bound": "hbm", "shapes": out}
+                        f"instance)", "flops_per_instance": "4 r^3 + 2 r^2 b", "bound": "hbm for r <= 32, mfma for r >= 96", "shapes": out}
 
 
 def run_serving(budget=64e9, slots=8, sat_requests=300, warm=200, measured=1000, rho=0.7):

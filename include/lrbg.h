@@ -225,6 +225,15 @@ double lrbg_plan_last_ms(lrbg_plan *plan);
 lrbg_status lrbg_schedule_stats(const lrbg_desc *descs, int64_t count, const char *tune_cache,
                                 uint32_t flags, lrbg_plan_stats *out);
 
+/*
+ * lrbg_schedule_variants -- the tile variant that lrbg_plan_create with the
+ * same arguments would run for each product (host only, nothing launched).
+ * variant_out: host array [count], receives variant ids (0 for a no-op
+ * product); lrbg_variant_name gives their names.
+ */
+lrbg_status lrbg_schedule_variants(const lrbg_desc *descs, int64_t count, const char *tune_cache,
+                                   uint32_t flags, int32_t *variant_out);
+
 /* ---------------------------------------------------------- tuning ---- */
 
 /*

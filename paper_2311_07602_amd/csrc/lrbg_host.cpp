@@ -69,6 +69,7 @@ static std::string variant_name(int v)
     case K_INNL: snprintf(buf, sizeof buf, "innl_ri%d_rj%d_wr%d_kg%d", vi.p1, vi.p2, vi.p3, vi.p4); break;
     case K_LRM: snprintf(buf, sizeof buf, "lrm_ri%d_rj%d_ks%d_kg%d", vi.p1, vi.p2, vi.p3, vi.p4); break;
     case K_LRM4: snprintf(buf, sizeof buf, "lrm4_ri%d_rj%d_ks%d_kg%d", vi.p1, vi.p2, vi.p3, vi.p4); break;
+    case K_LRMB: snprintf(buf, sizeof buf, "lrmb_ri%d_rj%d_kg%d", vi.p1, vi.p2, vi.p4); break;
     default: snprintf(buf, sizeof buf, "v%d", v);
     }
     return buf;
@@ -95,7 +96,7 @@ static bool kind_matches(int kind, int op, int prec)
     if (kind == base) return base != K_NOP;
     if (prec == LRBG_FP64 && op == LRBG_OP_DENSE_TS) return kind == K_DTSL;
     if (prec == LRBG_FP64 && op == LRBG_OP_INNER) return kind == K_INNL;
-    if (prec == LRBG_FP64 && op == LRBG_OP_LRMULT) return kind == K_LRM4;
+    if (prec == LRBG_FP64 && op == LRBG_OP_LRMULT) return kind == K_LRM4 || kind == K_LRMB;
     return false;
 }
 
@@ -113,6 +114,7 @@ static bool variant_fits(int v, const lrbg_desc &d)
     case K_INN64: return d.n <= 16 * vi.p2;
     case K_INN3: return d.n <= 16 * vi.p2;
     case K_LRM: case K_LRM4: return d.m <= 16 * vi.p1 * (4 / vi.p3) && d.n <= 16 * vi.p2;
+    case K_LRMB: return d.m <= 128 && d.n <= 128;
     case K_REC64: {
         const int kp = (d.k + 15) / 16 * 16;
         return (size_t)kp * 16 * vi.p2 * 8 <= (size_t)kLdsBytes;
@@ -139,6 +141,8 @@ static void tiles_of(int v, const lrbg_desc &d, std::vector<int32_t> &p0s, std::
         step = 16 * vi.p1 * (4 / vi.p3); extent = d.m; kc = 32; break;
     case K_LRM: case K_LRM4:   // one tile per product (variant_fits: m <= step)
         step = 16 * vi.p1 * (4 / vi.p3); extent = d.m; kc = 4 * vi.p4; break;
+    case K_LRMB:
+        step = 128; extent = d.m; kc = 4 * vi.p4; break;
     case K_INNL:
         step = 16 * vi.p1 * vi.p3; extent = d.m; kc = 4 * vi.p4; break;
     case K_REC64:
@@ -224,7 +228,8 @@ static int default_variant(const lrbg_desc &d)
         const int rr = std::max(d.m, d.n);
         if (rr <= 16) return pick({42, 39});   // 4 workgroups per CU: memory-bound, latency-limited
         if (rr <= 32) return pick({40, 44});
-        return pick({41});
+        if (rr <= 64) return pick({41});
+        return pick({46});
     }
     if (kind == K_REC64) {
         if (d.k <= 16) return pick({13});
@@ -433,6 +438,7 @@ struct Schedule {
     std::vector<Tile> tiles;      // all levels, each laid out for its launch
     std::vector<int32_t> qinfo;   // 9 per level
     std::vector<Level> levels;
+    std::vector<int> variant;     // per product, 0 = no-op
     lrbg_plan_stats stats{};
 };
 
@@ -587,7 +593,7 @@ static void lay_tiles(const std::vector<int64_t> &prods, const lrbg_desc *ds, co
 static int family_of(int v)
 {
     const int kind = kVariants[v].kind;
-    return kind == K_LRM ? F_LRM : kind == K_LRM4 ? F_LRM4 : F_GROUPED;
+    return kind == K_LRM ? F_LRM : kind == K_LRM4 ? F_LRM4 : kind == K_LRMB ? F_LRMB : F_GROUPED;
 }
 
 // A level's products go to one kernel per family: the grouped kernel (or
@@ -652,6 +658,7 @@ static lrbg_status build_schedule(const lrbg_desc *ds, int64_t n, const TuneTabl
         bytes += b;
         nlev = std::max(nlev, level[(size_t)i] + 1);
     }
+    sch.variant = variant;
     std::vector<std::vector<int64_t>> bylevel((size_t)std::max(nlev, 1));
     for (int64_t i = 0; i < n; ++i)
         if (variant[(size_t)i]) bylevel[(size_t)level[(size_t)i]].push_back(i);
@@ -964,6 +971,21 @@ lrbg_status lrbg_schedule_stats(const lrbg_desc *descs, int64_t count, const cha
     lrbg_status st = build_schedule(descs, count, tt, flags, nullptr, sch);
     if (st != LRBG_OK) return st;
     *out = sch.stats;
+    return LRBG_OK;
+}
+
+lrbg_status lrbg_schedule_variants(const lrbg_desc *descs, int64_t count, const char *tune_cache, uint32_t flags,
+                                   int32_t *variant_out)
+{
+    if (count > 0 && !variant_out) return fail(LRBG_EINVAL, "variant_out is NULL");
+    if (flags & ~(uint32_t)(LRBG_PLAN_PERSISTENT | LRBG_PLAN_NO_GRAPH | LRBG_PLAN_SCHED_MIX))
+        return fail(LRBG_EINVAL, "unknown plan flags 0x%x", flags);
+    TuneTable tt;
+    load_tune_cache(tune_cache, tt);
+    Schedule sch;
+    lrbg_status st = build_schedule(descs, count, tt, flags, nullptr, sch);
+    if (st != LRBG_OK) return st;
+    for (int64_t i = 0; i < count; ++i) variant_out[i] = sch.variant[(size_t)i];
     return LRBG_OK;
 }
 

@@ -44,6 +44,7 @@ enum Kind : int32_t {
     K_INNL = 7,    // INNER, FP64, LDS-staged      params: RI, RJ, WR, KG
     K_LRM = 8,     // LRMULT, FP64, fused          params: RI, RJ, KS, KG (INNER phase)
     K_LRM4 = 9,    // as K_LRM in the high-occupancy fused kernel (32 KB LDS, <= 128 VGPRs)
+    K_LRMB = 10,   // LRMULT, FP64, fused, ranks <= 128  params: RI, RJ, -, KG (8 waves, 128 KB LDS)
 };
 
 // Kernel families: each family of variants is compiled into its own kernel
@@ -52,15 +53,18 @@ enum Family : int32_t {
     F_GROUPED = 0,   // lrbg_grouped_kernel / lrbg_persistent_kernel
     F_LRM = 1,       // lrbg_lrmult_kernel: 64 KB LDS, 2 workgroups per CU
     F_LRM4 = 2,      // lrbg_lrmult4_kernel: 32 KB LDS, 4 workgroups per CU
+    F_LRMB = 3,      // lrbg_lrmultb_kernel: 8 waves, 128 KB LDS, 1 workgroup per CU
 };
-constexpr int kFamilies = 3;
+constexpr int kFamilies = 4;
 constexpr int kLdsBytes4 = 32768;
+constexpr int kThreadsB = 512;
+constexpr int kLdsBytesB = 131072;
 
 constexpr int kThreads = 256;       // 4 wavefronts of 64
 constexpr int kWaves = 4;
 constexpr int kLdsBytes = 65536;    // static LDS per workgroup (2 workgroups per CU)
 constexpr int kMaxRank = 128;
-constexpr int kMaxLrRank = 64;     // LRMULT: C and E both staged in LDS
+constexpr int kMaxLrRank = 128;    // LRMULT: the rank x rank core staged in LDS
 constexpr int kMaxBlock = 65536;
 constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies
 
@@ -120,9 +124,15 @@ constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies
     X(44, K_LRM4, 1, 2, 2, 4)         \
     X(45, K_LRM4, 2, 2, 4, 2)
 
-#define LRBG_ALL_VARIANTS(X) LRBG_VARIANTS(X) LRBG_LRM_VARIANTS(X) LRBG_LRM4_VARIANTS(X)
+#define LRBG_LRMB_VARIANTS(X)         \
+    X(46, K_LRMB, 4, 2, 0, 4)         \
+    X(47, K_LRMB, 2, 4, 0, 4)         \
+    X(48, K_LRMB, 4, 2, 0, 2)
 
-constexpr int kNumVariants = 46;   // ids 0..45 (0 = no-op tile)
+#define LRBG_ALL_VARIANTS(X) \
+    LRBG_VARIANTS(X) LRBG_LRM_VARIANTS(X) LRBG_LRM4_VARIANTS(X) LRBG_LRMB_VARIANTS(X)
+
+constexpr int kNumVariants = 49;   // ids 0..48 (0 = no-op tile)
 
 struct VariantInfo {
     int32_t kind, p1, p2, p3, p4;

@@ -146,14 +146,145 @@ __device__ __forceinline__ void lrm_tile(const DevDesc &d, int i0, double *lds)
     __syncthreads();   // LDS is reused by the next tile of a persistent workgroup
 }
 
+// ---------------------------------------------------------------------------
+// LRMULT for ranks up to 128, fused: one workgroup of 8 waves per CU, the
+// rank x rank intermediates in 128 KB of LDS (C, then E over it).
+//   C phase: wave (wr, wc) of a WR x WC grid accumulates C rows
+//            [16 RI wr, +16 RI) x columns [16 RJ wc, +16 RJ) over all of k
+//            (the INNER stream, k not split); C -> LDS row-major.
+//   E phase: wave w forms E rows [16 w, 16 w + 16) x all columns: its strip
+//            X_A(16 w + rho(c), 32 g + s), s < 32, sits in registers (lane
+//            group g takes 32 consecutive k), C(32 g + s, 16 J + c) comes
+//            from LDS (consecutive lanes, consecutive banks); E -> LDS
+//            column-major over C.
+//   G phase: wave w forms G rows [16 w, 16 w + 16): its E strip comes from
+//            LDS into registers, the X_B column strips X_B(32 g + s, 16 J + c)
+//            stream from L2 (32 contiguous doubles per lane), one column
+//            block ahead, and G is stored block by block.
+// Rows and columns beyond the ranks hold finite filler or zeros: X_A columns
+// >= ra and X_B rows >= rb read as 0, so they never reach an output, and
+// output rows/columns beyond the ranks are not stored.
+template <int RI, int RJ, int KG, bool GUARD>
+__device__ __forceinline__ void lrmb_tile(const DevDesc &d, double *lds)
+{
+    constexpr int R = 128;
+    constexpr int WR = R / (16 * RI), WC = R / (16 * RJ);
+    static_assert(WR * WC == kThreadsB / 64, "one C block per wave");
+    static_assert(R * R * 8 <= kLdsBytesB, "LRMULT core exceeds LDS");
+    constexpr int NBJ = R / 16;
+    const int tid = threadIdx.x, lane = tid & 63, c = lane & 15, g = lane >> 4, w = tid >> 6;
+    const int ra = d.m, rb = d.n;
+    const int wr = w / WC, wc = w % WC;
+    const int row0 = 16 * RI * wr, col0 = 16 * RJ * wc;
+
+    d4 acc[RI][RJ];
+    if (row0 < ra && col0 < rb) {
+        inner_stream<RI, RJ, KG, GUARD>(d, row0, col0, 0, 4 * KG, acc, [] {});
+    } else {
+#pragma unroll
+        for (int bi = 0; bi < RI; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < RJ; ++bj) acc[bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+
+    // X_A strip of the E phase, issued before the C store
+    const int erow = 16 * w + rho(c);
+    double xa[32];
+    {
+        gcp p = gin(d.s) + (erow < ra ? erow : 0);
+        const size_t ldx = (size_t)d.lds;
+#pragma unroll
+        for (int s = 0; s < 32; ++s) {
+            const int kk = 32 * g + s;
+            xa[s] = kk < ra ? p[kk * ldx] : 0.0;
+        }
+    }
+
+#pragma unroll
+    for (int bi = 0; bi < RI; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < RJ; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) lds[(row0 + 16 * bi + 4 * g + v) * R + col0 + 16 * bj + c] = acc[bi][bj][v];
+    __syncthreads();
+
+    // E = X_A C
+    const int nbj = (rb + 15) / 16;
+    const bool rows_live = 16 * w < ra;
+    d4 e[NBJ];
+#pragma unroll
+    for (int J = 0; J < NBJ; ++J) e[J] = d4{0.0, 0.0, 0.0, 0.0};
+    if (rows_live) {
+#pragma unroll
+        for (int s = 0; s < 32; ++s) {
+            const double *crow = lds + (32 * g + s) * R + c;
+#pragma unroll
+            for (int J = 0; J < NBJ; ++J)
+                if (J < nbj) e[J] = mfma64(xa[s], crow[16 * J], e[J]);
+        }
+    }
+
+    auto fetch_xb = [&](int J, double (&xb)[32]) {
+        const int col = 16 * J + c;
+        gcp p = gin(d.e) + (size_t)(col < rb ? col : 0) * d.lde + 32 * g;
+        load_run<32, true>(xb, p, rb - 32 * g);   // rows >= rb read 0
+    };
+    double xb0[32], xb1[32];
+    fetch_xb(0, xb0);
+    __syncthreads();   // C is dead
+
+#pragma unroll
+    for (int J = 0; J < NBJ; ++J)
+        if (J < nbj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) lds[(16 * w + 4 * g + v) + (16 * J + c) * R] = e[J][v];
+    __syncthreads();
+
+    // G = E X_B
+    if (!rows_live) return;
+    double ea[32];
+#pragma unroll
+    for (int s = 0; s < 32; ++s) ea[s] = lds[erow + (32 * g + s) * R];
+    const size_t ldg = (size_t)d.ldc;
+    const int orow = 16 * w + 4 * g;
+    auto block = [&](int J, const double (&xb)[32]) {
+        d4 o = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 32; ++s) o = mfma64(ea[s], xb[s], o);
+        const int col = 16 * J + c;
+        if (orow < ra && col < rb) {
+            double out[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) out[v] = o[v];
+            store_run<4, true>(gout(d.c) + orow + (size_t)col * ldg, out, ra - orow, false);
+        }
+    };
+#pragma unroll
+    for (int J = 0; J < NBJ; J += 2) {
+        if (J >= nbj) break;
+        if (J + 1 < nbj) fetch_xb(J + 1, xb1);
+        block(J, xb0);
+        if (J + 1 >= nbj) break;
+        if (J + 2 < nbj) fetch_xb(J + 2, xb0);
+        block(J + 1, xb1);
+    }
+}
+
 template <int KIND, int P1, int P2, int P3, int P4>
 __device__ __forceinline__ void run_lrm_variant(const DevDesc &d, int p0, bool edge, double *lds)
 {
-    constexpr int LDSD = (KIND == K_LRM ? kLdsBytes : kLdsBytes4) / 8;
-    if (edge)
-        lrm_tile<P1, P2, P3, P4, true, LDSD>(d, p0, lds);
-    else
-        lrm_tile<P1, P2, P3, P4, false, LDSD>(d, p0, lds);
+    if constexpr (KIND == K_LRMB) {
+        if (edge)
+            lrmb_tile<P1, P2, P4, true>(d, lds);
+        else
+            lrmb_tile<P1, P2, P4, false>(d, lds);
+    } else {
+        constexpr int LDSD = (KIND == K_LRM ? kLdsBytes : kLdsBytes4) / 8;
+        if (edge)
+            lrm_tile<P1, P2, P3, P4, true, LDSD>(d, p0, lds);
+        else
+            lrm_tile<P1, P2, P3, P4, false, LDSD>(d, p0, lds);
+    }
 }
 
 template <int FAMILY>
@@ -168,6 +299,12 @@ __device__ __forceinline__ void run_lrm_tile(const DevDesc *__restrict__ descs, 
     if constexpr (FAMILY == F_LRM) {
         switch (t.variant) {
             LRBG_LRM_VARIANTS(LRBG_CASE)
+        default:
+            break;
+        }
+    } else if constexpr (FAMILY == F_LRMB) {
+        switch (t.variant) {
+            LRBG_LRMB_VARIANTS(LRBG_CASE)
         default:
             break;
         }
@@ -206,6 +343,17 @@ lrbg_lrmult4_kernel(const DevDesc *__restrict__ descs, const Tile *__restrict__ 
     run_lrm_tile<F_LRM4>(descs, tl, lds);
 }
 
+// Ranks up to 128: 8 waves and 128 KB of LDS, one workgroup per CU.
+__global__ void __launch_bounds__(kThreadsB) __attribute__((amdgpu_waves_per_eu(2, 2)))
+lrbg_lrmultb_kernel(const DevDesc *__restrict__ descs, const Tile *__restrict__ tiles, int ntiles)
+{
+    __shared__ double lds[kLdsBytesB / 8];
+    const int t = blockIdx.x;
+    if (t >= ntiles) return;
+    const Tile tl = tiles[t];
+    run_lrm_tile<F_LRMB>(descs, tl, lds);
+}
+
 int launch_lrm_family(int family, const DevDesc *descs, const Tile *tiles, int ntiles, void *stream)
 {
     if (ntiles <= 0) return 0;
@@ -215,6 +363,8 @@ int launch_lrm_family(int family, const DevDesc *descs, const Tile *tiles, int n
         hipLaunchKernelGGL(lrbg_lrmult_kernel, grid, block, 0, s, descs, tiles, ntiles);
     else if (family == F_LRM4)
         hipLaunchKernelGGL(lrbg_lrmult4_kernel, grid, block, 0, s, descs, tiles, ntiles);
+    else if (family == F_LRMB)
+        hipLaunchKernelGGL(lrbg_lrmultb_kernel, grid, dim3(kThreadsB), 0, s, descs, tiles, ntiles);
     else
         return (int)hipErrorInvalidValue;
     return (int)hipGetLastError();

@@ -385,33 +385,29 @@ __device__ __forceinline__ void dtsl_tile(const DevDesc &d, int i0, double *lds)
 // sums meet in LDS and are added in a fixed order: deterministic, no atomics.
 // Workgroup tile: T rows [i0, i0 + 16 RI NG) x all n columns.
 //
-// inn64_accumulate leaves the finished sums in the ks == 0 waves: lane
-// (c, g) of output group og holds T(rowbase + 16 bi + 4 g + v, 16 bj + c) in
-// acc[bi][bj][v], rowbase = i0 + 16 RI og.  Rows >= m and columns >= n hold
-// finite filler (clamped operand columns), never an output.  LDS is free
-// again when it returns.  `after_first` runs once the first chunk's loads
-// are in flight (before any LDS use of the reduction).
-template <int RI, int RJ, int KS, int KG, bool GUARD, typename Hook>
-__device__ __forceinline__ void inn64_accumulate(const DevDesc &d, int i0, double *lds, d4 (&acc)[RI][RJ],
-                                                 Hook after_first)
+// One wave's share of an INNER contraction: T(row0 + [0, 16 RI), col0 +
+// [0, 16 RJ)) summed over the k chunks kb, kb + kstride, ... (chunks of
+// 4 KG), into acc (zeroed here).  Lane (c, g) ends with
+// T(row0 + 16 bi + 4 g + v, col0 + 16 bj + c) in acc[bi][bj][v]; rows >= m
+// and columns >= n hold finite filler (clamped operand columns), never an
+// output.  `after_first` runs once the first chunk's loads are in flight.
+template <int RI, int RJ, int KG, bool GUARD, typename Hook>
+__device__ __forceinline__ void inner_stream(const DevDesc &d, int row0, int col0, int kb0, int kstride,
+                                             d4 (&acc)[RI][RJ], Hook after_first)
 {
-    constexpr int NG = 4 / KS;
-    constexpr int KSTEP = 4 * KG;
-    const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
-    const int og = w / KS, ks = w % KS;
+    const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
     const int M = d.m, N = d.n, K = d.k;
     const size_t ldv = (size_t)d.lda, ldu = (size_t)d.ldb;
 
-    const int rowbase = i0 + og * 16 * RI;
     gcp Vp[RI], Up[RJ];
 #pragma unroll
     for (int bi = 0; bi < RI; ++bi) {
-        const int col = rowbase + bi * 16 + rho(c);   // V1 column = T row
+        const int col = row0 + bi * 16 + rho(c);   // V1 column = T row
         Vp[bi] = gin(d.a) + (size_t)(col < M ? col : 0) * ldv;
     }
 #pragma unroll
     for (int bj = 0; bj < RJ; ++bj) {
-        const int col = bj * 16 + c;
+        const int col = col0 + bj * 16 + c;
         Up[bj] = gin(d.b) + (size_t)(col < N ? col : 0) * ldu;
     }
 
@@ -438,19 +434,35 @@ __device__ __forceinline__ void inn64_accumulate(const DevDesc &d, int i0, doubl
     };
 
     double a0[RI][KG], u0[RJ][KG], a1[RI][KG], u1[RJ][KG];
-    constexpr int STRIDE = KS * KSTEP;
-    int k0 = ks * KSTEP;
+    int k0 = kb0;
     if (k0 < K) load(k0, a0, u0);
     after_first();
     while (k0 < K) {
-        if (k0 + STRIDE < K) load(k0 + STRIDE, a1, u1);
+        if (k0 + kstride < K) load(k0 + kstride, a1, u1);
         compute(a0, u0);
-        k0 += STRIDE;
+        k0 += kstride;
         if (k0 >= K) break;
-        if (k0 + STRIDE < K) load(k0 + STRIDE, a0, u0);
+        if (k0 + kstride < K) load(k0 + kstride, a0, u0);
         compute(a1, u1);
-        k0 += STRIDE;
+        k0 += kstride;
     }
+}
+
+// inn64_accumulate leaves the finished sums in the ks == 0 waves: lane
+// (c, g) of output group og holds T(rowbase + 16 bi + 4 g + v, 16 bj + c) in
+// acc[bi][bj][v], rowbase = i0 + 16 RI og.  Rows >= m and columns >= n hold
+// finite filler, never an output.  LDS is free again when it returns.
+// `after_first` runs once the first chunk's loads are in flight (before any
+// LDS use of the reduction).
+template <int RI, int RJ, int KS, int KG, bool GUARD, typename Hook>
+__device__ __forceinline__ void inn64_accumulate(const DevDesc &d, int i0, double *lds, d4 (&acc)[RI][RJ],
+                                                 Hook after_first)
+{
+    constexpr int NG = 4 / KS;
+    constexpr int KSTEP = 4 * KG;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int og = w / KS, ks = w % KS;
+    inner_stream<RI, RJ, KG, GUARD>(d, i0 + og * 16 * RI, 0, ks * KSTEP, KS * KSTEP, acc, after_first);
 
     if constexpr (KS > 1) {
         // slot (og, ks-1): RI*RJ*4 doubles per lane, lane-fastest

@@ -104,6 +104,8 @@ def load(path: Optional[str] = None):
     lib.lrbg_plan_get_stats.restype = ctypes.c_int
     lib.lrbg_schedule_stats.argtypes = [P(lrbg_desc), i64, ctypes.c_char_p, u32, P(lrbg_plan_stats)]
     lib.lrbg_schedule_stats.restype = ctypes.c_int
+    lib.lrbg_schedule_variants.argtypes = [P(lrbg_desc), i64, ctypes.c_char_p, u32, P(i32)]
+    lib.lrbg_schedule_variants.restype = ctypes.c_int
     lib.lrbg_plan_last_ms.argtypes = [vp]
     lib.lrbg_plan_last_ms.restype = ctypes.c_double
     lib.lrbg_autotune.argtypes = [P(lrbg_desc), i64, ctypes.c_char_p, i32]
@@ -212,6 +214,16 @@ def lrbg_schedule_stats(descs: Sequence[lrbg_desc], tune_cache: Optional[str] = 
     cache = tune_cache.encode() if tune_cache else None
     _check(load().lrbg_schedule_stats(arr, len(descs), cache, flags, ctypes.byref(s)), "lrbg_schedule_stats")
     return {f: getattr(s, f) for f, _ in lrbg_plan_stats._fields_}
+
+
+def lrbg_schedule_variants(descs: Sequence[lrbg_desc], tune_cache: Optional[str] = None, flags: int = 0) -> List[str]:
+    """Names of the tile variants a plan over `descs` would run ("nop" for no-op products)."""
+    arr = (lrbg_desc * max(len(descs), 1))(*descs)
+    out = (ctypes.c_int32 * max(len(descs), 1))()
+    cache = tune_cache.encode() if tune_cache else None
+    lib = load()
+    _check(lib.lrbg_schedule_variants(arr, len(descs), cache, flags, out), "lrbg_schedule_variants")
+    return [lib.lrbg_variant_name(out[i]).decode() for i in range(len(descs))]
 
 
 def lrbg_plan_last_ms(plan: int) -> float:

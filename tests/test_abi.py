@@ -112,7 +112,8 @@ def test_lrmult_validation_and_accounting():
     b, r = 1024, 32
     assert status([mk("lrmult", m=r, n=r, k=b)]) == 0
     assert status([mk("lrmult", m=r, n=17, k=b)]) == 0
-    assert status([mk("lrmult", m=65, n=16, k=b)]) == lrbg.LRBG_EUNSUPPORTED     # rank > 64
+    assert status([mk("lrmult", m=96, n=128, k=b)]) == 0
+    assert status([mk("lrmult", m=129, n=16, k=b)]) == lrbg.LRBG_EUNSUPPORTED    # rank > 128
     assert status([mk("lrmult", m=r, n=r, k=b, prec=1)]) == lrbg.LRBG_EUNSUPPORTED
     assert status([mk("lrmult", m=r, n=r, k=b, e=0)]) == lrbg.LRBG_EINVAL
     assert status([mk("lrmult", m=r, n=r, k=b, s=0)]) == lrbg.LRBG_EINVAL
@@ -125,6 +126,12 @@ def test_lrmult_validation_and_accounting():
     # e is ignored (may be anything) for the other ops
     d = mk(); d.e = 12345; d.lde = 0
     assert status([d]) == 0
+    names = lrbg.lrbg_schedule_variants([mk("lrmult", m=8, n=8, k=b), mk("lrmult", m=32, n=20, k=b, base=BASE * 2),
+                                         mk("lrmult", m=64, n=64, k=b, base=BASE * 3),
+                                         mk("lrmult", m=100, n=128, k=b, base=BASE * 4),
+                                         mk("lrmult", m=0, n=8, k=b, base=BASE * 5, c=0, lds=1, ldc=1)])
+    assert names[0].startswith("lrm4_") and names[1].startswith("lrm_") and names[2].startswith("lrm_")
+    assert names[3].startswith("lrmb_") and names[4] == "nop"
     st = lrbg.lrbg_schedule_stats([mk("lrmult", m=r, n=r, k=b)])
     assert st["useful_flops"] == pytest.approx(4 * r ** 3 + 2 * r * r * b)   # the paper's Alg. 1 count
     assert st["hbm_bytes"] == pytest.approx(8 * (2 * b * r + 3 * r * r))
@@ -148,10 +155,10 @@ def test_lrmult_entry_validates_before_launch():
     assert lib.lr_batched_lrmult(0, *([None] * 13), None) == 0
     i32 = lambda v: (ctypes.c_int32 * 1)(v)
     p = lambda v: (ctypes.c_void_p * 1)(v)
-    # rank 65 is rejected by validation (nothing launched, no device touched)
-    st = lib.lr_batched_lrmult(1, i32(512), i32(65), i32(8), p(BASE), i32(512), p(BASE + (1 << 30)), i32(512),
-                               p(BASE + (2 << 30)), i32(65), p(BASE + (3 << 30)), i32(8), p(BASE + (4 << 30)),
-                               i32(65), None)
+    # rank 129 is rejected by validation (nothing launched, no device touched)
+    st = lib.lr_batched_lrmult(1, i32(512), i32(129), i32(8), p(BASE), i32(512), p(BASE + (1 << 30)), i32(512),
+                               p(BASE + (2 << 30)), i32(129), p(BASE + (3 << 30)), i32(8), p(BASE + (4 << 30)),
+                               i32(129), None)
     assert st == lrbg.LRBG_EUNSUPPORTED
 
 

@@ -55,10 +55,13 @@ def _dev(AV, BU, AX, BX, pad):
             DevMat(ra, rb, ld=ra + pad[4]))
 
 
-def _plan_case(k, ra, rb, integer, seed, pad=(0, 0, 0, 0, 0), tune=None):
+def _plan_case(k, ra, rb, integer, seed, pad=(0, 0, 0, 0, 0), tune=None, expect=None):
     ops = _operands(k, ra, rb, integer, seed)
     dAV, dBU, dAX, dBX, dG = _dev(*ops, pad)
-    p = lrbg.Plan([lrbg.desc("lrmult", dAV.view, dBU.view, dG.view, s=dAX.view, e=dBX.view)], tune_cache=tune)
+    d = lrbg.desc("lrmult", dAV.view, dBU.view, dG.view, s=dAX.view, e=dBX.view)
+    if expect is not None:   # the forced variant is the one scheduled
+        assert lrbg.lrbg_schedule_variants([d], tune_cache=tune) == [expect]
+    p = lrbg.Plan([d], tune_cache=tune)
     p.execute(stream())
     sync()
     p.close()
@@ -70,7 +73,8 @@ def _plan_case(k, ra, rb, integer, seed, pad=(0, 0, 0, 0, 0), tune=None):
 # (k = b, ra, rb): square paper shapes, ragged ranks, tails of every tile
 SHAPES = [(512, 8, 8), (512, 16, 16), (512, 32, 32), (1024, 32, 32), (2048, 16, 16), (512, 64, 64),
           (100, 7, 9), (333, 17, 31), (65, 33, 12), (1000, 64, 47), (3, 5, 5), (1, 1, 1), (37, 2, 64),
-          (600, 48, 48), (129, 20, 3)]
+          (600, 48, 48), (129, 20, 3), (512, 128, 128), (1024, 96, 96), (1000, 100, 77), (300, 65, 128),
+          (129, 128, 1), (77, 70, 120)]
 
 
 @pytest.mark.parametrize("k,ra,rb", SHAPES)
@@ -109,14 +113,14 @@ def _lrm_variants():
 def test_every_lrmult_variant_forced(name):
     """Each fused tile at a rank below its limit (ragged), with a k tail."""
     rj = int(name.split("_rj")[1].split("_")[0])
-    r = 16 * rj
+    r = 128 if name.startswith("lrmb") else 16 * rj
     for ra, rb in ((r - 1, r - 3), (max(r // 2 - 1, 1), r)):
         k = 301
         tune = _forced_cache(name, k, max(ra, rb))
         try:
-            G, Gref, _ = _plan_case(k, ra, rb, True, 900 + r + ra, pad=(1, 0, 2, 0, 1), tune=tune)
+            G, Gref, _ = _plan_case(k, ra, rb, True, 900 + r + ra, pad=(1, 0, 2, 0, 1), tune=tune, expect=name)
             assert np.array_equal(G, Gref)
-            G, Gref, D = _plan_case(k, ra, rb, False, 950 + r + ra, tune=tune)
+            G, Gref, D = _plan_case(k, ra, rb, False, 950 + r + ra, tune=tune, expect=name)
             assert oracle.normalized_error(G, Gref, D) <= TOL
         finally:
             os.unlink(tune)
@@ -124,7 +128,8 @@ def test_every_lrmult_variant_forced(name):
 
 def test_lr_batched_lrmult_entry_mixed_sizes():
     """The Alg. 2-style entry point over arrays: uneven (b, ra, rb) per instance."""
-    rng_shapes = [(512, 8, 8), (77, 13, 5), (1024, 32, 16), (200, 64, 64), (0, 4, 4), (5, 0, 3)]
+    rng_shapes = [(512, 8, 8), (77, 13, 5), (1024, 32, 16), (200, 64, 64), (0, 4, 4), (5, 0, 3), (300, 128, 90),
+                  (0, 100, 100)]
     ops, devs = [], []
     for t, (k, ra, rb) in enumerate(rng_shapes):
         o = _operands(k, ra, rb, False, 1000 + t)
