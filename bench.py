@@ -189,6 +189,39 @@ def run_chain(count=4096, b=512, r=32, steps=20, warmup=3, prec="fp64"):
             "frac_of_roofline_time": round(roof / ms, 4), "bound": "hbm"}
 
 
+def run_lrmult_config(args):
+    """One (b, r) of the paper's fused low-rank product as the timed workload
+    (``--config lrmult``): batch ``--count`` of G = X_A (V_A^T U_B) X_B."""
+    import torch
+    from paper_2311_07602_amd import lrbg, workloads
+    stream = torch.cuda.current_stream()
+    b, r = args.lr_b, args.lr_r
+    w = workloads.lrmult(args.count, b, r)
+    plan = lrbg.Plan(w.descs, tune_cache=args.tune_cache)
+    st = plan.stats()
+    kernel = {"lrm_": "lrbg_lrmult_kernel", "lrm4": "lrbg_lrmult4_kernel",
+              "lrmb": "lrbg_lrmultb_kernel"}[lrbg.lrbg_schedule_variants(w.descs[:1], args.tune_cache)[0][:4]]
+    ms, per = time_plan(plan, args.steps, args.warmup, stream)
+    plan.close()
+    f, by = st["useful_flops"], st["hbm_bytes"]
+    t_f, t_b = f / (PEAK_FP64_TFLOPS * 1e12), by / (PEAK_HBM_GBS * 1e9)
+    if t_f >= t_b:
+        roof = {"bound": "mfma", "achieved": round(f / ms / 1e9, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(f / ms / 1e9 / PEAK_FP64_TFLOPS, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(by / ms / 1e6, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(by / ms / 1e6 / PEAK_HBM_GBS, 4)}
+    roof.update({"traffic": None, "kernel": kernel, "algorithmic_flops": f, "algorithmic_bytes": by,
+                 "roofline_ms": round(max(t_f, t_b) * 1e3, 4), "frac_of_roofline_time": round(max(t_f, t_b) * 1e3 / ms, 4)})
+    return {"metric": METRIC, "value": round(f / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"{args.count} x G = X_A (V_A^T U_B) X_B, b={b}, r={r}, FP64, N(0,1) "
+                                   f"(the paper's fused low-rank product)", "instances": args.count,
+                       "tiles": st["tiles"], "launch": "hipGraph replay, one fused kernel"},
+            "roofline": roof, "step_ms_min": round(min(per), 4), "step_ms_max": round(max(per), 4)}
+
+
 def run_lrmult_paper(count=20000, bs=(512, 1024, 2048), rs=(8, 16, 32, 96, 128), steps=10, warmup=2):
     """The paper's batched low-rank product G = X_A (V_A^T U_B) X_B at its
     measured shapes (batch 20 000 per (b, r)); GFLOP/s by the paper's count
@@ -255,8 +288,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="grouped", choices=["grouped"])
+    ap.add_argument("--config", default="grouped", choices=["grouped", "lrmult"],
+                    help="grouped: the uneven batch (default); lrmult: one (b, r) of the paper's fused product")
     ap.add_argument("--count", type=int, default=20000)
+    ap.add_argument("--lr-b", type=int, default=2048)
+    ap.add_argument("--lr-r", type=int, default=32)
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2311_07602_amd", "tune", "mi355x.tune"))
     ap.add_argument("--persistent", action="store_true")
     ap.add_argument("--lpt", action="store_true", help="longest-first tile order instead of the mixed "
@@ -278,6 +314,9 @@ def main():
     lrbg.load()
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.config == "lrmult":
+        print(json.dumps(run_lrmult_config(args)), flush=True)
         return
     line = run_grouped(args)
     if not args.no_extras:

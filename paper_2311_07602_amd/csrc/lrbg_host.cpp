@@ -47,12 +47,28 @@ static lrbg_status fail(lrbg_status st, const char *fmt, ...)
 
 // ------------------------------------------------------------- variants
 
-static const VariantInfo kVariants[kNumVariants] = {
-    {K_NOP, 0, 0, 0, 0},
-#define LRBG_INFO(id, kind, p1, p2, p3, p4) {kind, p1, p2, p3, p4},
-    LRBG_ALL_VARIANTS(LRBG_INFO)
+// Variant table indexed by id (the per-kernel lists are not in id order).
+struct VariantTable {
+    VariantInfo v[kNumVariants];
+    int listed = 0;
+    constexpr VariantTable() : v()
+    {
+#define LRBG_INFO(id, kind, p1, p2, p3, p4) \
+    v[id] = VariantInfo{kind, p1, p2, p3, p4};  \
+    ++listed;
+        LRBG_ALL_VARIANTS(LRBG_INFO)
 #undef LRBG_INFO
+    }
+    constexpr bool dense() const
+    {
+        for (int i = 1; i < kNumVariants; ++i)
+            if (v[i].kind == K_NOP) return false;
+        return v[0].kind == K_NOP && listed == kNumVariants - 1;
+    }
 };
+static constexpr VariantTable kVariantTable;
+static_assert(kVariantTable.dense(), "variant ids must be 1..kNumVariants-1, each listed once");
+static constexpr const VariantInfo *kVariants = kVariantTable.v;
 
 static std::string variant_name(int v)
 {
@@ -229,7 +245,7 @@ static int default_variant(const lrbg_desc &d)
         if (rr <= 16) return pick({42, 39});   // 4 workgroups per CU: memory-bound, latency-limited
         if (rr <= 32) return pick({40, 44});
         if (rr <= 64) return pick({41});
-        return pick({46});
+        return pick({47});
     }
     if (kind == K_REC64) {
         if (d.k <= 16) return pick({13});
@@ -593,11 +609,16 @@ static void lay_tiles(const std::vector<int64_t> &prods, const lrbg_desc *ds, co
 static int family_of(int v)
 {
     const int kind = kVariants[v].kind;
-    return kind == K_LRM ? F_LRM : kind == K_LRM4 ? F_LRM4 : kind == K_LRMB ? F_LRMB : F_GROUPED;
+    switch (kind) {
+    case K_LRM: return F_LRM;
+    case K_LRM4: return F_LRM4;
+    case K_LRMB: return F_LRMB;
+    default: return F_GROUPED;
+    }
 }
 
 // A level's products go to one kernel per family: the grouped kernel (or
-// its persistent form) and the two fused low-rank product kernels.
+// its persistent form) and the fused low-rank product kernels.
 static void layout_level(const std::vector<int64_t> &prods, const lrbg_desc *ds, const std::vector<int> &variant,
                          uint32_t flags, Schedule &sch, Level &lv)
 {

@@ -73,44 +73,44 @@ constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies
 // LRBG_VARIANTS run in the grouped kernel; LRBG_LRM_VARIANTS (the fused
 // low-rank product) in a kernel of their own, so that their code and
 // register pressure stay out of the grouped kernel.
-#define LRBG_VARIANTS(X)              \
-    X(1, K_DTS64, 1, 1, 8, 0)         \
-    X(2, K_DTS64, 2, 1, 8, 0)         \
-    X(3, K_DTS64, 4, 1, 8, 0)         \
-    X(4, K_DTS64, 1, 2, 8, 0)         \
-    X(5, K_DTS64, 2, 2, 8, 0)         \
-    X(6, K_DTS64, 1, 4, 4, 0)         \
-    X(7, K_DTS64, 2, 4, 4, 0)         \
-    X(8, K_INN64, 1, 1, 4, 8)         \
-    X(9, K_INN64, 2, 2, 4, 8)         \
-    X(10, K_INN64, 2, 2, 2, 8)        \
-    X(11, K_INN64, 2, 4, 2, 4)        \
-    X(12, K_INN64, 1, 4, 4, 4)        \
-    X(13, K_REC64, 1, 4, 2, 0)        \
-    X(14, K_REC64, 1, 4, 8, 0)        \
-    X(15, K_REC64, 2, 4, 4, 0)        \
-    X(16, K_REC64, 1, 2, 8, 0)        \
-    X(17, K_REC64, 1, 8, 4, 0)        \
-    X(18, K_REC64, 2, 2, 8, 0)        \
-    X(19, K_DTSL, 2, 2, 8, 0)         \
-    X(20, K_DTSL, 4, 2, 4, 0)         \
-    X(21, K_DTSL, 2, 4, 4, 0)         \
-    X(22, K_DTSL, 4, 4, 4, 0)         \
-    X(23, K_DTSL, 2, 8, 4, 0)         \
-    X(24, K_DTSL, 1, 8, 4, 0)         \
-    X(25, K_INNL, 4, 4, 2, 2)         \
-    X(26, K_INNL, 2, 2, 2, 4)         \
-    X(27, K_INNL, 2, 4, 4, 4)         \
-    X(28, K_INNL, 4, 4, 2, 3)         \
-    X(29, K_DTS3, 4, 1, 0, 0)         \
-    X(30, K_DTS3, 2, 2, 1, 0)         \
-    X(31, K_DTS3, 2, 4, 0, 0)         \
-    X(32, K_DTS3, 1, 8, 0, 0)         \
-    X(33, K_DTS3, 1, 2, 1, 0)         \
-    X(34, K_INN3, 1, 1, 4, 1)         \
-    X(35, K_INN3, 2, 2, 4, 1)         \
-    X(36, K_INN3, 1, 4, 4, 1)         \
-    X(37, K_INN3, 1, 8, 4, 0)         \
+#define LRBG_VARIANTS(X)           \
+    X(1, K_DTS64, 1, 1, 8, 0)      \
+    X(2, K_DTS64, 2, 1, 8, 0)      \
+    X(3, K_DTS64, 4, 1, 8, 0)      \
+    X(4, K_DTS64, 1, 2, 8, 0)      \
+    X(5, K_DTS64, 2, 2, 8, 0)      \
+    X(6, K_DTS64, 1, 4, 4, 0)      \
+    X(7, K_DTS64, 2, 4, 4, 0)      \
+    X(8, K_INN64, 1, 1, 4, 8)      \
+    X(9, K_INN64, 2, 2, 4, 8)      \
+    X(10, K_INN64, 2, 2, 2, 8)     \
+    X(11, K_INN64, 2, 4, 2, 4)     \
+    X(12, K_INN64, 1, 4, 4, 4)     \
+    X(13, K_REC64, 1, 4, 2, 0)     \
+    X(14, K_REC64, 1, 4, 8, 0)     \
+    X(15, K_REC64, 2, 4, 4, 0)     \
+    X(16, K_REC64, 1, 2, 8, 0)     \
+    X(17, K_REC64, 1, 8, 4, 0)     \
+    X(18, K_REC64, 2, 2, 8, 0)     \
+    X(19, K_DTSL, 2, 2, 8, 0)      \
+    X(20, K_DTSL, 4, 2, 4, 0)      \
+    X(21, K_DTSL, 2, 4, 4, 0)      \
+    X(22, K_DTSL, 4, 4, 4, 0)      \
+    X(23, K_DTSL, 2, 8, 4, 0)      \
+    X(24, K_DTSL, 1, 8, 4, 0)      \
+    X(25, K_INNL, 4, 4, 2, 2)      \
+    X(26, K_INNL, 2, 2, 2, 4)      \
+    X(27, K_INNL, 2, 4, 4, 4)      \
+    X(28, K_INNL, 4, 4, 2, 3)      \
+    X(29, K_DTS3, 4, 1, 0, 0)      \
+    X(30, K_DTS3, 2, 2, 1, 0)      \
+    X(31, K_DTS3, 2, 4, 0, 0)      \
+    X(32, K_DTS3, 1, 8, 0, 0)      \
+    X(33, K_DTS3, 1, 2, 1, 0)      \
+    X(34, K_INN3, 1, 1, 4, 1)      \
+    X(35, K_INN3, 2, 2, 4, 1)      \
+    X(36, K_INN3, 1, 4, 4, 1)      \
+    X(37, K_INN3, 1, 8, 4, 0)      \
     X(38, K_INN3, 2, 2, 2, 1)
 
 #define LRBG_LRM_VARIANTS(X)          \
@@ -138,7 +138,7 @@ struct VariantInfo {
     int32_t kind, p1, p2, p3, p4;
 };
 
-// Kernel launch helpers (defined in lrbg_kernels.hip and lrbg_lrmult.hip).
+// Kernel launch helpers (defined in the lrbg_*.hip kernel sources).
 int launch_persistent(const DevDesc *descs, const Tile *tiles, const int32_t *qinfo,
                       int32_t *counters, int grid, void *stream);
 int launch_reset(int32_t *counters, int n, void *stream);

@@ -1,24 +1,14 @@
 // The grouped kernel (one workgroup per tile over a heterogeneous tile list)
 // and its persistent form, for the DENSE_TS, INNER and RECOMP tiles of
-// lrbg_tiles.h; the fused low-rank product kernels live in lrbg_lrmult.hip.
+// lrbg_tiles.h (FP64 and BF16x3); the fused low-rank product kernels live
+// in lrbg_lrmult.hip.
 #include "lrbg_tiles.h"
 
 namespace lrbg {
 
 __device__ __forceinline__ void run_tile(const DevDesc *__restrict__ descs, const Tile &t, double *lds)
 {
-    if (t.variant <= 0) return;
-    const DevDesc d = descs[t.desc];
-    const bool edge = (t.flags & kTileEdge) != 0;
-    switch (t.variant) {
-#define LRBG_CASE(id, kind, p1, p2, p3, p4) \
-    case id:                                \
-        run_variant<kind, p1, p2, p3, p4>(d, t.p0, edge, lds); break;
-        LRBG_VARIANTS(LRBG_CASE)
-#undef LRBG_CASE
-    default:
-        break;
-    }
+    LRBG_RUN_TILE(LRBG_VARIANTS, descs, t, lds);
 }
 
 // Out-of-line tile call for the persistent kernel: keeps each variant's

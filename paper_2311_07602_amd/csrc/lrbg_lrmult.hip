@@ -150,8 +150,9 @@ __device__ __forceinline__ void lrm_tile(const DevDesc &d, int i0, double *lds)
 // LRMULT for ranks up to 128, fused: one workgroup of 8 waves per CU, the
 // rank x rank intermediates in 128 KB of LDS (C, then E over it).
 //   C phase: wave (wr, wc) of a WR x WC grid accumulates C rows
-//            [16 RI wr, +16 RI) x columns [16 RJ wc, +16 RJ) over all of k
-//            (the INNER stream, k not split); C -> LDS row-major.
+//            [16 RI wr, +16 RI) x columns [16 RJ wc, +16 RJ) over all of k,
+//            each k chunk of V_A and U_B staged once in LDS for all 8 waves
+//            (inner_staged); C -> LDS row-major.
 //   E phase: wave w forms E rows [16 w, 16 w + 16) x all columns: its strip
 //            X_A(16 w + rho(c), 32 g + s), s < 32, sits in registers (lane
 //            group g takes 32 consecutive k), C(32 g + s, 16 J + c) comes
@@ -178,14 +179,7 @@ __device__ __forceinline__ void lrmb_tile(const DevDesc &d, double *lds)
     const int row0 = 16 * RI * wr, col0 = 16 * RJ * wc;
 
     d4 acc[RI][RJ];
-    if (row0 < ra && col0 < rb) {
-        inner_stream<RI, RJ, KG, GUARD>(d, row0, col0, 0, 4 * KG, acc, [] {});
-    } else {
-#pragma unroll
-        for (int bi = 0; bi < RI; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < RJ; ++bj) acc[bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
-    }
+    inner_staged<RI, RJ, WR, WC, KG, GUARD, kThreadsB, kLdsBytesB>(d, 0, lds, acc);
 
     // X_A strip of the E phase, issued before the C store
     const int erow = 16 * w + rho(c);
@@ -293,29 +287,29 @@ __device__ __forceinline__ void run_lrm_tile(const DevDesc *__restrict__ descs, 
     if (t.variant <= 0) return;
     const DevDesc d = descs[t.desc];
     const bool edge = (t.flags & kTileEdge) != 0;
-#define LRBG_CASE(id, kind, p1, p2, p3, p4) \
+#define LRBG_LRM_CASE(id, kind, p1, p2, p3, p4) \
     case id:                                \
         run_lrm_variant<kind, p1, p2, p3, p4>(d, t.p0, edge, lds); break;
     if constexpr (FAMILY == F_LRM) {
         switch (t.variant) {
-            LRBG_LRM_VARIANTS(LRBG_CASE)
+            LRBG_LRM_VARIANTS(LRBG_LRM_CASE)
         default:
             break;
         }
     } else if constexpr (FAMILY == F_LRMB) {
         switch (t.variant) {
-            LRBG_LRMB_VARIANTS(LRBG_CASE)
+            LRBG_LRMB_VARIANTS(LRBG_LRM_CASE)
         default:
             break;
         }
     } else {
         switch (t.variant) {
-            LRBG_LRM4_VARIANTS(LRBG_CASE)
+            LRBG_LRM4_VARIANTS(LRBG_LRM_CASE)
         default:
             break;
         }
     }
-#undef LRBG_CASE
+#undef LRBG_LRM_CASE
 }
 
 // The fused low-rank products, one workgroup per tile (same tile layout and

@@ -172,18 +172,18 @@ __device__ __forceinline__ void store_rows(gp col, const d4 (&acc)[RM], int g, i
 // lane group) are conflict-free.  Columns at or beyond `nvalid` hold
 // clamped (valid) data, used only for outputs that are never stored; with
 // GUARD, rows at or beyond `kvalid` are stored as 0.
-template <int NCOL, int KC, bool GUARD>
+template <int NCOL, int KC, bool GUARD, int NTHR = kThreads>
 struct StageK {
     static_assert(KC % 2 == 0, "row pairs");
     static constexpr int NPAIR = NCOL * (KC / 2);
-    static constexpr int PPT = (NPAIR + kThreads - 1) / kThreads;
+    static constexpr int PPT = (NPAIR + NTHR - 1) / NTHR;
     double r[PPT][2];
 
     __device__ __forceinline__ void fetch(gcp base, size_t ld, int kvalid, int nvalid)
     {
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
-            const int idx = threadIdx.x + kThreads * p;
+            const int idx = threadIdx.x + NTHR * p;
             const int j = idx / (KC / 2), kk = 2 * (idx % (KC / 2));
             const int jc = (idx < NPAIR && j < nvalid) ? j : 0;
             load_run<2, GUARD>(r[p], base + kk + (size_t)jc * ld, kvalid - kk);
@@ -193,7 +193,7 @@ struct StageK {
     {
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
-            const int idx = threadIdx.x + kThreads * p;
+            const int idx = threadIdx.x + NTHR * p;
             if (idx < NPAIR) {
                 const int j = idx / (KC / 2), kk = 2 * (idx % (KC / 2));
                 buf[kk * P + j] = r[p][0];
@@ -524,27 +524,29 @@ __device__ __forceinline__ void inn64_tile(const DevDesc &d, int i0, double *lds
 // ---------------------------------------------------------------------------
 // INNER, FP64, both operands staged in LDS (ranks >= 64, matrix-core-bound):
 // each k chunk of V1 (tile rows) and U2 (all columns) crosses HBM -> LDS
-// once, and the 4 waves, arranged WR x WC over the output, each own a
+// once, and the waves, arranged WR x WC over the output, each own a
 // 16 RI x 16 RJ block group for the whole contraction (no reduction).
-// Tile: T rows [i0, i0 + 16 RI WR) x columns [0, 16 RJ WC).
-template <int RI, int RJ, int WR, int KG, bool GUARD>
-__device__ __forceinline__ void innl_tile(const DevDesc &d, int i0, double *lds)
+// inner_staged accumulates T rows [i0, i0 + 16 RI WR) x columns
+// [0, 16 RJ WC) with NTHR threads and LDSB bytes of LDS: wave (wr, wc) ends
+// with T(i0 + 16 RI wr + 16 bi + 4 g + v, 16 RJ wc + 16 bj + c) in
+// acc[bi][bj][v].  It ends with a barrier, so LDS is free on return.
+template <int RI, int RJ, int WR, int WC, int KG, bool GUARD, int NTHR, int LDSB>
+__device__ __forceinline__ void inner_staged(const DevDesc &d, int i0, double *lds, d4 (&acc)[RI][RJ])
 {
-    constexpr int WC = 4 / WR;
+    static_assert(WR * WC * 64 == NTHR, "one block group per wave");
     constexpr int KC = 4 * KG;
     constexpr int MT = 16 * RI * WR, NT = 16 * RJ * WC;
     constexpr int PV = MT + 1, PU = NT + 1;
     constexpr int BUF = KC * (PV + PU);
-    static_assert(2 * BUF * 8 <= kLdsBytes, "INNER staging exceeds LDS");
+    static_assert(2 * BUF * 8 <= LDSB, "INNER staging exceeds LDS");
     const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
     const int wr = w / WC, wc = w % WC;
     const int M = d.m, N = d.n, K = d.k;
-    const size_t ldv = (size_t)d.lda, ldu = (size_t)d.ldb, ldt = (size_t)d.ldc;
+    const size_t ldv = (size_t)d.lda, ldu = (size_t)d.ldb;
     const gcp V1t = gin(d.a) + (size_t)i0 * ldv;   // column i0 of V1 = T row i0
     const gcp U2 = gin(d.b);
     const int mvalid = M - i0;
 
-    d4 acc[RI][RJ];
 #pragma unroll
     for (int bi = 0; bi < RI; ++bi)
 #pragma unroll
@@ -567,8 +569,8 @@ __device__ __forceinline__ void innl_tile(const DevDesc &d, int i0, double *lds)
                 for (int bj = 0; bj < RJ; ++bj) acc[bi][bj] = mfma64(a[bi], b[bj], acc[bi][bj]);
         }
     };
-    StageK<MT, KC, GUARD> sv;
-    StageK<NT, KC, GUARD> su;
+    StageK<MT, KC, GUARD, NTHR> sv;
+    StageK<NT, KC, GUARD, NTHR> su;
     if (K > 0) {
         sv.fetch(V1t, ldv, K, mvalid);
         su.fetch(U2, ldu, K, N);
@@ -591,6 +593,20 @@ __device__ __forceinline__ void innl_tile(const DevDesc &d, int i0, double *lds)
         }
         __syncthreads();
     }
+}
+
+// Tile: T rows [i0, i0 + 16 RI WR) x columns [0, 16 RJ WC), 4 waves.
+template <int RI, int RJ, int WR, int KG, bool GUARD>
+__device__ __forceinline__ void innl_tile(const DevDesc &d, int i0, double *lds)
+{
+    constexpr int WC = 4 / WR;
+    const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4, w = threadIdx.x >> 6;
+    const int wr = w / WC, wc = w % WC;
+    const int M = d.m, N = d.n;
+    const size_t ldt = (size_t)d.ldc;
+    const int arow = wr * 16 * RI, bcol = wc * 16 * RJ;
+    d4 acc[RI][RJ];
+    inner_staged<RI, RJ, WR, WC, KG, GUARD, kThreads, kLdsBytes>(d, i0, lds, acc);
 
 #pragma unroll
     for (int bi = 0; bi < RI; ++bi) {
@@ -1097,6 +1113,24 @@ __device__ __forceinline__ void run_variant(const DevDesc &d, int p0, bool edge,
     else
         run_variant_g<KIND, P1, P2, P3, P4, false>(d, p0, lds);
 }
+
+// Run tile t with the variants of one kernel (LIST: an X-macro variant list).
+#define LRBG_CASE(id, kind, p1, p2, p3, p4) \
+    case id:                                \
+        run_variant<kind, p1, p2, p3, p4>(lrbg_d_, lrbg_t_.p0, lrbg_edge_, lrbg_lds_); break;
+#define LRBG_RUN_TILE(LIST, descs, t, lds)                        \
+    do {                                                          \
+        const Tile &lrbg_t_ = (t);                                \
+        double *lrbg_lds_ = (lds);                                \
+        if (lrbg_t_.variant <= 0) break;                          \
+        const DevDesc lrbg_d_ = (descs)[lrbg_t_.desc];            \
+        const bool lrbg_edge_ = (lrbg_t_.flags & kTileEdge) != 0; \
+        switch (lrbg_t_.variant) {                                \
+            LIST(LRBG_CASE)                                       \
+        default:                                                  \
+            break;                                                \
+        }                                                         \
+    } while (0)
 
 }  // namespace lrbg
 

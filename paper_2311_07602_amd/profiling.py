@@ -25,9 +25,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ["csrc/lrbg_kernels.hip", "csrc/lrbg_tiles.h", "csrc/lrbg_internal.h", "tune/mi355x.tune"]
 
 
-def source_digest() -> str:
+def source_digest(sources=None) -> str:
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in sources or KERNEL_SOURCES:
         with open(os.path.join(HERE, rel), "rb") as f:
             h.update(rel.encode())
             h.update(f.read())
@@ -73,7 +73,7 @@ def summarize(args) -> str:
     lines = [
         f"# {args.kernel}: {args.workload}",
         "",
-        "rocprofv3 summaries of the benchmark's grouped kernel (one launch per step).",
+        f"rocprofv3 summaries of {args.kernel} in the benchmark command below (one launch per step).",
         "",
         "## Commands",
         "",
@@ -90,7 +90,7 @@ def summarize(args) -> str:
         "",
         "## HBM traffic (--pmc FETCH_SIZE, then --pmc WRITE_SIZE; KiB per dispatch)",
         "",
-        f"| counter | grouped kernel (median of {len(fetch)}) | copy of {args.cal_bytes / 2**30:.0f} GiB | scale |",
+        f"| counter | kernel (median of {len(fetch)}) | copy of {args.cal_bytes / 2**30:.0f} GiB | scale |",
         f"|---|---|---|---|",
         f"| FETCH_SIZE | {statistics.median(fetch):.0f} | {cal_f:.0f} | {fs:.4f} |",
         f"| WRITE_SIZE | {statistics.median(write):.0f} | {cal_w:.0f} | {ws:.4f} |",
@@ -100,13 +100,14 @@ def summarize(args) -> str:
         f"(ratio {(f_b + w_b) / args.bytes:.3f}).",
         f"Achieved: {args.flops / (avg_ms * 1e-3) / 1e12:.2f} TFLOP/s useful "
         f"({args.flops / (avg_ms * 1e-3) / 78.6e12 * 100:.1f}% of 78.6), "
-        f"{args.bytes / (avg_ms * 1e-3) / 1e9:.0f} GB/s algorithmic.",
+        f"{args.bytes / (avg_ms * 1e-3) / 1e9:.0f} GB/s algorithmic "
+        f"({args.bytes / (avg_ms * 1e-3) / 8.0e12 * 100:.1f}% of 8000).",
         "",
         "## Machine-readable",
         "",
         "```",
         f"kernel: {args.kernel}",
-        f"source_digest: {args.digest or source_digest()}",
+        f"source_digest: {args.digest or source_digest(args.sources.split(',') if args.sources else None)}",
         f"avg_duration_ms: {avg_ms:.6f}",
         f"algorithmic_flops: {args.flops:.6g}",
         f"algorithmic_bytes: {args.bytes:.6g}",
@@ -162,6 +163,7 @@ def main():
     sm.add_argument("--flops", type=float, required=True)
     sm.add_argument("--bytes", type=float, required=True)
     sm.add_argument("--digest", default=None)
+    sm.add_argument("--sources", default=None, help="comma list of sources (relative to the package) the digest covers")
     sm.add_argument("--cmd", action="append", default=[])
     sm.add_argument("--out", required=True)
     sub.add_parser("digest")
