@@ -14,8 +14,8 @@ skinny batch (64 x 256x256 . 256x16, buffer sets rotated so the 38 MB batch
 does not sit in the 256 MB last-level cache) and the low-rank x low-rank
 chain (4096 instances, b = 512, r = 32: inner products, then recompression),
 the paper's fused low-rank product G = X_A (V_A^T U_B) X_B at batch 20 000
-for b in {512, 1024, 2048} and r in {8, 16, 32, 96, 128}, and the serving
-loop.
+for b in {512, 1024, 2048} and r in {8, 16, 32, 96, 128}, a weakly admissible
+BLR matrix times 8 right-hand sides, and the serving loop.
 
   python bench.py [--steps K] [--warmup W] [--extras/--no-extras]
   python bench.py --calibrate-copy      # plain 1 GiB device copy (counter scaling)
@@ -248,6 +248,31 @@ def run_lrmult_paper(count=20000, bs=(512, 1024, 2048), rs=(8, 16, 32, 96, 128),
                         f"instance)", "flops_per_instance": "4 r^3 + 2 r^2 b", "bound": "hbm for r <= 32, mfma for r >= 96", "shapes": out}
 
 
+def run_blr(nbs=(32, 64, 128), b=512, r=8, nrhs=8, steps=20, warmup=3):
+    """Weakly admissible BLR matrix times 8 right-hand sides (rank 8), the
+    application of the paper's evaluation; one captured two-level plan per
+    size (INNER products into the stacked right-hand sides, then one
+    DENSE_TS per block row over [A_ii | U_i])."""
+    import torch
+    from paper_2311_07602_amd import workloads
+    stream = torch.cuda.current_stream()
+    out = []
+    for nb in nbs:
+        m = workloads.blr(nb, b, r, nrhs)
+        f, by = m.work()
+        plan = m.plan()
+        ms, _ = time_plan(plan, steps, warmup, stream)
+        m.close()
+        del m
+        torch.cuda.empty_cache()
+        roof = max(f / (PEAK_FP64_TFLOPS * 1e12), by / (PEAK_HBM_GBS * 1e9)) * 1e3
+        out.append({"N": nb * b, "blocks": nb, "ms_per_step": round(ms, 4), "GFLOP/s": round(f / ms / 1e6, 1),
+                    "GB/s": round(by / ms / 1e6, 1), "frac_of_roofline_time": round(roof / ms, 4)})
+        log(f"[bench] blr N={nb * b}: {ms:.4f} ms, {by / ms / 1e6:.0f} GB/s")
+    return {"workload": f"Y = A X, A weakly admissible BLR (blocks of {b}, rank {r}, dense diagonal), X with "
+                        f"{nrhs} columns, FP64, N(0,1) blocks", "bound": "hbm", "sizes": out}
+
+
 def run_serving(budget=64e9, slots=8, sat_requests=300, warm=200, measured=1000, rho=0.7):
     """Continuous-batching loop: saturated request rate first (all requests
     queued at t=0), then Poisson arrivals at rho x that rate; latency is
@@ -325,6 +350,8 @@ def main():
                          "chain_bf16x3": run_chain(prec="bf16x3")}
         log("[bench] paper-shape low-rank products ...")
         line["extra"]["lrmult_paper_shapes"] = run_lrmult_paper()
+        log("[bench] BLR matrix x 8 right-hand sides ...")
+        line["extra"]["blr_matvec"] = run_blr()
         log("[bench] serving ...")
         line["extra"]["serving"] = run_serving()
     print(json.dumps(line), flush=True)

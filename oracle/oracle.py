@@ -25,7 +25,7 @@ _LIB_PATH = os.path.join(_HERE, "liblrbg_oracle.so")
 _lib = None
 
 __all__ = [
-    "load", "dense_ts", "inner", "recomp", "chain", "lr_mult", "dot2",
+    "load", "dense_ts", "inner", "recomp", "chain", "lr_mult", "blr_matvec", "dot2",
     "max_threads", "normalized_error", "normwise_error", "col_major",
 ]
 
@@ -162,6 +162,25 @@ def lr_mult(AVs, BUs, AXs, BXs, nthreads: int = 0):
     if rc:
         raise MemoryError("oracle lr_mult: allocation failed")
     return Gs
+
+
+def blr_matvec(diag, U, V, X, nthreads: int = 0):
+    """Block low-rank matrix times multiple right-hand sides (the application
+    of Sec. 7): Y_i = A_ii X_i + sum over j != i of U_ij (V_ij^T X_j), each
+    low-rank block applied as the paper's low-rank product does, rank-sized
+    factor first.  diag[i]: b x b; U[i][j], V[i][j]: b x r (None on the
+    diagonal); X[j]: b x nrhs.  The terms of a block row are added in order
+    of j, after the diagonal term.  Returns the list of Y_i."""
+    nb = len(diag)
+    Ys = dense_ts(list(diag), list(X), nthreads=nthreads)
+    pairs = [(i, j) for i in range(nb) for j in range(nb) if i != j]
+    if not pairs:
+        return Ys
+    Ps = inner([V[i][j] for i, j in pairs], [X[j] for i, j in pairs], nthreads=nthreads)
+    Zs = dense_ts([U[i][j] for i, j in pairs], Ps, nthreads=nthreads)
+    for (i, j), Z in zip(pairs, Zs):
+        Ys[i] += Z
+    return Ys
 
 
 def dot2(x: np.ndarray, y: np.ndarray) -> float:

@@ -267,15 +267,52 @@ struct Range {
     int64_t idx;
 };
 
-static Range span(const void *p, int rows, int cols, int ld, size_t es, int64_t idx)
+static bool overlaps(const Range &a, const Range &b) { return a.lo < b.hi && b.lo < a.hi && a.hi > a.lo && b.hi > b.lo; }
+
+// A column-major operand as the bytes it occupies: `cols` runs of
+// `row_bytes` bytes, `ld_bytes` apart (row_bytes <= ld_bytes, validated).
+struct Mat {
+    uintptr_t p = 0;
+    int64_t cols = 0;
+    uintptr_t ld_bytes = 0, row_bytes = 0;
+    int64_t idx = -1;
+    bool empty() const { return !p || cols <= 0 || row_bytes == 0; }
+    Range range() const
+    {
+        if (empty()) return Range{0, 0, idx};
+        return Range{p, p + (uintptr_t)(cols - 1) * ld_bytes + row_bytes, idx};
+    }
+};
+
+static Mat mat_of(const void *p, int rows, int cols, int ld, size_t es, int64_t idx)
 {
-    if (!p || rows <= 0 || cols <= 0) return Range{0, 0, idx};
-    uintptr_t lo = (uintptr_t)p;
-    uintptr_t hi = lo + ((size_t)(cols - 1) * (size_t)ld + (size_t)rows) * es;
-    return Range{lo, hi, idx};
+    Mat m;
+    if (!p || rows <= 0 || cols <= 0) return m;
+    m.p = (uintptr_t)p;
+    m.cols = cols;
+    m.ld_bytes = (uintptr_t)ld * es;
+    m.row_bytes = (uintptr_t)rows * es;
+    m.idx = idx;
+    return m;
 }
 
-static bool overlaps(const Range &a, const Range &b) { return a.lo < b.hi && b.lo < a.hi && a.hi > a.lo && b.hi > b.lo; }
+// Element-exact overlap: do some bytes of x and y coincide?  Two operands
+// whose byte spans interleave (row blocks of one larger matrix) do not
+// overlap unless one of their columns meets one of the other's.
+static bool mats_overlap(const Mat &x, const Mat &y)
+{
+    if (x.empty() || y.empty() || !overlaps(x.range(), y.range())) return false;
+    const Mat &a = x.cols <= y.cols ? x : y;
+    const Mat &b = x.cols <= y.cols ? y : x;
+    for (int64_t j = 0; j < a.cols; ++j) {
+        const uintptr_t s = a.p + (uintptr_t)j * a.ld_bytes, e = s + a.row_bytes;   // column j of a
+        // first column jb of b that ends after s; columns of b are disjoint and ascending
+        int64_t jb = 0;
+        if (b.p + b.row_bytes <= s) jb = (int64_t)((s - b.p - b.row_bytes) / b.ld_bytes) + 1;
+        if (jb < b.cols && b.p + (uintptr_t)jb * b.ld_bytes < e) return true;
+    }
+    return false;
+}
 
 // Operand shapes (rows, cols) of a product: a, b, s, c, e (0 x 0 when unused).
 static void shapes(const lrbg_desc &d, int sh[5][2])
@@ -339,10 +376,10 @@ static lrbg_status validate_one(const lrbg_desc &d, int64_t i)
                 return fail(LRBG_EINVAL, "product %lld: %s not %zu-byte aligned", (long long)i, nm[t], es[t]);
         }
     }
-    const Range out = span(d.c, sh[3][0], sh[3][1], d.ldc, 8, i);
+    const Mat out = mat_of(d.c, sh[3][0], sh[3][1], d.ldc, 8, i);
     for (int t = 0; t < 5; ++t) {
         if (t == 3 || (t == 2 && !uses_s) || (t == 4 && !uses_e)) continue;
-        if (overlaps(out, span(ptr[t], sh[t][0], sh[t][1], ld[t], es[t], i)))
+        if (mats_overlap(out, mat_of(ptr[t], sh[t][0], sh[t][1], ld[t], es[t], i)))
             return fail(LRBG_EINVAL, "product %lld: output overlaps input %s", (long long)i, nm[t]);
     }
     return LRBG_OK;
@@ -459,26 +496,72 @@ struct Schedule {
 };
 
 // Dependency level of every product: a product reading (a, b, s or e)
-// memory written by another product runs one level after it.
+// memory written by another product runs one level after it.  Overlaps are
+// element-exact: outputs may interleave inside one larger matrix (row blocks
+// of a stacked vector, for instance) as long as no element is shared.
+//
+// Outputs are grouped into clusters of intersecting byte spans; within a
+// cluster of several outputs the columns of all members are sorted and must
+// be disjoint.  An input is then tested against the members of the clusters
+// its span meets: one exact test for a single-output cluster, a binary
+// search over the sorted columns otherwise.
 static lrbg_status compute_levels(const lrbg_desc *ds, int64_t n, std::vector<int> &level)
 {
     level.assign((size_t)n, 0);
-    std::vector<Range> outs;
+    std::vector<Mat> outs;
     outs.reserve((size_t)n);
     for (int64_t i = 0; i < n; ++i) {
         int sh[5][2];
         shapes(ds[i], sh);
-        Range r = span(ds[i].c, sh[3][0], sh[3][1], ds[i].ldc, 8, i);
-        if (r.hi > r.lo) outs.push_back(r);
+        Mat m = mat_of(ds[i].c, sh[3][0], sh[3][1], ds[i].ldc, 8, i);
+        if (!m.empty()) outs.push_back(m);
     }
-    std::sort(outs.begin(), outs.end(), [](const Range &x, const Range &y) { return x.lo < y.lo; });
-    for (size_t t = 1; t < outs.size(); ++t)
-        if (outs[t].lo < outs[t - 1].hi)
-            return fail(LRBG_EINVAL, "outputs of products %lld and %lld overlap", (long long)outs[t - 1].idx,
-                        (long long)outs[t].idx);
+    std::sort(outs.begin(), outs.end(), [](const Mat &x, const Mat &y) { return x.p < y.p; });
+
+    struct Seg {
+        uintptr_t lo, hi;
+        int64_t idx;
+    };
+    struct Cluster {
+        uintptr_t lo, hi;
+        size_t first, count;      // members: outs[first, first + count)
+        std::vector<Seg> segs;    // sorted columns of all members (count > 1)
+    };
+    std::vector<Cluster> cl;
+    for (size_t t = 0; t < outs.size(); ++t) {
+        const Range r = outs[t].range();
+        if (!cl.empty() && r.lo < cl.back().hi) {
+            cl.back().hi = std::max(cl.back().hi, r.hi);
+            ++cl.back().count;
+        } else {
+            cl.push_back(Cluster{r.lo, r.hi, t, 1, {}});
+        }
+    }
+    for (Cluster &c : cl) {
+        if (c.count < 2) continue;
+        for (size_t t = c.first; t < c.first + c.count; ++t) {
+            const Mat &m = outs[t];
+            for (int64_t j = 0; j < m.cols; ++j) {
+                const uintptr_t lo = m.p + (uintptr_t)j * m.ld_bytes;
+                c.segs.push_back(Seg{lo, lo + m.row_bytes, m.idx});
+            }
+        }
+        std::sort(c.segs.begin(), c.segs.end(), [](const Seg &x, const Seg &y) { return x.lo < y.lo; });
+        for (size_t t = 1; t < c.segs.size(); ++t)
+            if (c.segs[t].lo < c.segs[t - 1].hi)
+                return fail(LRBG_EINVAL, "outputs of products %lld and %lld overlap", (long long)c.segs[t - 1].idx,
+                            (long long)c.segs[t].idx);
+    }
+
     // deps[i]: products whose output product i reads
     std::vector<std::vector<int64_t>> deps((size_t)n);
     bool any = false;
+    auto add_dep = [&](int64_t i, int64_t j) {
+        if (j == i) return;
+        std::vector<int64_t> &v = deps[(size_t)i];
+        if (std::find(v.begin(), v.end(), j) == v.end()) v.push_back(j);
+        any = true;
+    };
     for (int64_t i = 0; i < n; ++i) {
         const lrbg_desc &d = ds[i];
         int sh[5][2];
@@ -490,17 +573,29 @@ static lrbg_status compute_levels(const lrbg_desc *ds, int64_t n, std::vector<in
         for (int t = 0; t < 4; ++t) {
             if (t == 2 && d.op != LRBG_OP_RECOMP && d.op != LRBG_OP_LRMULT) continue;
             if (t == 3 && d.op != LRBG_OP_LRMULT) continue;
-            Range in = span(ptr[t], sh[si[t]][0], sh[si[t]][1], ld[t], es[t], i);
-            if (in.hi <= in.lo) continue;
-            // outputs starting before in.hi; walk back while they may overlap
-            auto it = std::lower_bound(outs.begin(), outs.end(), in.hi,
-                                       [](const Range &x, uintptr_t v) { return x.lo < v; });
-            while (it != outs.begin()) {
+            const Mat in = mat_of(ptr[t], sh[si[t]][0], sh[si[t]][1], ld[t], es[t], i);
+            if (in.empty()) continue;
+            const Range ir = in.range();
+            // clusters starting before ir.hi; walk back while they may meet it (clusters are disjoint)
+            auto it = std::lower_bound(cl.begin(), cl.end(), ir.hi,
+                                       [](const Cluster &c, uintptr_t v) { return c.lo < v; });
+            while (it != cl.begin()) {
                 --it;
-                if (it->hi <= in.lo) break;   // outputs are disjoint and sorted
-                if (it->idx != i) {
-                    deps[(size_t)i].push_back(it->idx);
-                    any = true;
+                if (it->hi <= ir.lo) break;
+                if (it->count == 1) {
+                    const Mat &m = outs[it->first];
+                    if (mats_overlap(in, m)) add_dep(i, m.idx);
+                    continue;
+                }
+                for (int64_t j = 0; j < in.cols; ++j) {
+                    const uintptr_t lo = in.p + (uintptr_t)j * in.ld_bytes, hi = lo + in.row_bytes;
+                    auto sg = std::lower_bound(it->segs.begin(), it->segs.end(), hi,
+                                               [](const Seg &x, uintptr_t v) { return x.lo < v; });
+                    while (sg != it->segs.begin()) {
+                        --sg;
+                        if (sg->hi <= lo) break;   // segments are disjoint and sorted
+                        add_dep(i, sg->idx);
+                    }
                 }
             }
         }

@@ -13,6 +13,10 @@ arithmetic happens here.
                    folded into V (generated on the host per instance).
   lrmult(count)    the paper's batched low-rank product at one (b, r):
                    G = X_A (V_A^T U_B) X_B, all four operands N(0,1).
+  blr(nb, b)       a weakly admissible BLR matrix (dense diagonal blocks,
+                   rank-r off-diagonal blocks U V^T with the log-spaced
+                   scalings of the chain folded into V) and nrhs N(0,1)
+                   right-hand sides, in the device layout of blr.BlrMatvec.
 """
 from __future__ import annotations
 
@@ -165,6 +169,19 @@ def lrmult_operands(w: Workload, i: int):
         return np.asfortranarray(_cm(pool, off, rows, cols).cpu().numpy())
     return dict(AV=host(pin, oV, b, r), BU=host(pin, oU, b, r), AX=host(pin, oXA, r, r),
                 BX=host(pin, oXB, r, r), G=host(pout, oG, r, r))
+
+
+def blr(nb: int = 64, b: int = 512, r: int = 8, nrhs: int = 8, seed: int = 9, device="cuda"):
+    """A BlrMatvec filled with seeded synthetic blocks (all on the device)."""
+    import torch
+    from .blr import BlrMatvec
+    m = BlrMatvec(nb, b, r, nrhs, device=device)
+    m.rows.copy_(inputs.device_normal(m.rows.numel(), seed=seed, device=device).view_as(m.rows))
+    sig = torch.from_numpy(inputs.sigma_profile(r)).to(device)
+    m.vs.copy_(inputs.device_normal(m.vs.numel(), seed=seed + 1, device=device).view_as(m.vs))
+    m.vs.mul_(sig.view(1, 1, r, 1))
+    m.xs[:, :, :b].copy_(inputs.device_normal(nb * nrhs * b, seed=seed + 2, device=device).view(nb, nrhs, b))
+    return m
 
 
 def work_totals(descs) -> Tuple[float, float]:

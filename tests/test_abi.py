@@ -227,3 +227,75 @@ def test_null_host_arrays_rejected():
     assert st == lrbg.LRBG_EINVAL
     assert lib.lr_batched_gemm(0, 0, 0, None, None, None, None, None, None, None, None, None, None, None, None) == 0
     assert b"NULL" in lib.lrbg_last_error() or lib.lrbg_last_error() != b""
+
+
+# ------------------------------------------------ element-exact overlaps
+
+def _inner_at(c, ldc, m=8, n=8, k=64, a=BASE, b=BASE + (1 << 30)):
+    return mk("inner", m=m, n=n, k=k, a=a, b=b, c=c, ldc=ldc, lda=k, ldb=k)
+
+
+def test_interleaved_outputs_accepted_and_exact_overlap_rejected():
+    X = BASE + (40 << 30)
+    # two 8 x 8 outputs in rows [0, 8) and [8, 16) of one 16 x 8 matrix: spans interleave, no element shared
+    d1 = _inner_at(X, 16); d2 = _inner_at(X + 8 * 8, 16, a=BASE + (2 << 30))
+    assert status([d1, d2]) == 0
+    assert lrbg.lrbg_schedule_stats([d1, d2])["levels"] == 1
+    # shifted by one row: element (7, j) of the first is element (0, j) of the second
+    d3 = _inner_at(X + 7 * 8, 16, a=BASE + (2 << 30))
+    assert status([d1, d3]) == lrbg.LRBG_EINVAL
+
+
+def test_stacked_vector_dependencies_are_exact():
+    """Products writing row blocks of a stacked vector and a product reading
+    another row block of it: no dependency; reading all of it: one."""
+    b, r, nrhs = 64, 8, 8
+    L = b + 2 * r
+    Xs = BASE + (50 << 30)
+    w1 = mk("inner", m=r, n=nrhs, k=b, a=BASE, b=BASE + (1 << 30), c=Xs + 8 * b, ldc=L, lda=b, ldb=b)
+    w2 = mk("inner", m=r, n=nrhs, k=b, a=BASE + (2 << 30), b=BASE + (3 << 30), c=Xs + 8 * (b + r), ldc=L,
+            lda=b, ldb=b)
+    # reads rows [0, b) of Xs only
+    rd_top = mk("inner", m=r, n=nrhs, k=b, a=BASE + (4 << 30), b=Xs, c=BASE + (5 << 30), ldc=r, lda=b, ldb=L)
+    assert lrbg.lrbg_schedule_stats([w1, w2, rd_top])["levels"] == 1
+    # reads all L rows of Xs (the stacked DENSE_TS of a BLR row): after both writers
+    rd_all = mk(m=b, n=nrhs, k=L, a=BASE + (6 << 30), b=Xs, c=BASE + (7 << 30), ldc=b, lda=b, ldb=L)
+    assert lrbg.lrbg_schedule_stats([w1, w2, rd_all, rd_top])["levels"] == 2
+    # a product whose output interleaves with its own input is fine; one sharing an element is not
+    own = mk("inner", m=r, n=nrhs, k=b, a=BASE + (8 << 30), b=Xs, c=Xs + 8 * b, ldc=L, lda=b, ldb=L)
+    assert status([own]) == 0
+    bad = mk("inner", m=r, n=nrhs, k=b, a=BASE + (8 << 30), b=Xs, c=Xs + 8 * (b - 1), ldc=L, lda=b, ldb=L)
+    assert status([bad]) == lrbg.LRBG_EINVAL
+
+
+def test_overlap_decisions_match_brute_force():
+    """Random small column-major operands in one buffer: the scheduler's
+    overlap (rejection) and dependency (levels) decisions equal those of
+    explicit element sets."""
+    import random
+    rnd = random.Random(7)
+    base = BASE + (60 << 30)
+
+    def elems(off, rows, cols, ld):
+        return {off + i + j * ld for j in range(cols) for i in range(rows)}
+
+    for trial in range(300):
+        ld1, ld2 = rnd.randint(8, 24), rnd.randint(8, 24)
+        r1, c1 = rnd.randint(1, 8), rnd.randint(1, 6)       # output of product 1 (inner: m x n)
+        r2, c2 = rnd.randint(1, 8), rnd.randint(1, 6)       # output of product 2
+        o1, o2 = rnd.randint(0, 200), rnd.randint(0, 200)
+        e1, e2 = elems(o1, r1, c1, ld1), elems(o2, r2, c2, ld2)
+        p1 = mk("inner", m=r1, n=c1, k=64, a=BASE, b=BASE + (1 << 30), c=base + 8 * o1, ldc=ld1, lda=64, ldb=64)
+        p2 = mk("inner", m=r2, n=c2, k=64, a=BASE + (2 << 30), b=BASE + (3 << 30), c=base + 8 * o2, ldc=ld2,
+                lda=64, ldb=64)
+        st = status([p1, p2])
+        assert (st == lrbg.LRBG_EINVAL) == bool(e1 & e2), (trial, st)
+        # product 3 reads a k x n operand B at a random place: depends on whichever output it meets
+        kr, kc, ldr, orr = rnd.randint(1, 8), rnd.randint(1, 6), rnd.randint(8, 24), rnd.randint(0, 200)
+        er = elems(orr, kr, kc, ldr)
+        p3 = mk("inner", m=8, n=kc, k=kr, a=BASE + (4 << 30), b=base + 8 * orr, ldb=ldr, lda=kr,
+                c=BASE + (5 << 30), ldc=8)
+        if e1 & e2:
+            continue
+        levels = lrbg.lrbg_schedule_stats([p1, p2, p3])["levels"]
+        assert levels == (2 if (er & (e1 | e2)) else 1), trial

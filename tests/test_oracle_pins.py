@@ -305,3 +305,49 @@ def test_dot2_ill_conditioned_exact(orc):
         small = float(rng.standard_normal())
         x = np.array([big, small, -big]); y = np.ones(3)
         assert orc.dot2(x, y) == small
+
+
+# ------------------------------------------------------ BLR matrix x RHS
+
+def _blr_host(rng, nb, b, r, nrhs, f):
+    D = [f(rng, b, b) for _ in range(nb)]
+    U = [[None if i == j else f(rng, b, r) for j in range(nb)] for i in range(nb)]
+    V = [[None if i == j else f(rng, b, r) for j in range(nb)] for i in range(nb)]
+    X = [f(rng, b, nrhs) for _ in range(nb)]
+    return D, U, V, X
+
+
+def _assembled(D, U, V):
+    nb, b = len(D), D[0].shape[0]
+    A = np.zeros((nb * b, nb * b))
+    for i in range(nb):
+        for j in range(nb):
+            A[i * b:(i + 1) * b, j * b:(j + 1) * b] = D[i] if i == j else U[i][j] @ V[i][j].T
+    return A
+
+
+@pytest.mark.parametrize("nb,b,r,nrhs", [(3, 5, 2, 4), (4, 8, 3, 1), (1, 6, 2, 3), (5, 7, 1, 2)])
+def test_blr_matvec_equals_assembled_product_integer(orc, nb, b, r, nrhs):
+    """On integer blocks every partial sum is exact, so the BLR evaluation
+    U_ij (V_ij^T X_j) must equal the assembled dense matrix times X exactly
+    (numpy's product of the assembled matrix, not the oracle's loops)."""
+    rng = np.random.default_rng(20 + nb + b)
+    D, U, V, X = _blr_host(rng, nb, b, r, nrhs, inputs.integer_f)
+    Y = np.vstack(orc.blr_matvec(D, U, V, X))
+    assert np.array_equal(Y, _assembled(D, U, V) @ np.vstack(X))
+
+
+def test_blr_matvec_within_bound_of_assembled_product(orc):
+    """N(0,1) blocks: the two evaluation orders differ only by rounding,
+    within gamma_n of the sum of absolute terms."""
+    rng = np.random.default_rng(31)
+    nb, b, r, nrhs = 4, 16, 3, 2
+    D, U, V, X = _blr_host(rng, nb, b, r, nrhs, inputs.normal_f)
+    Y = np.vstack(orc.blr_matvec(D, U, V, X))
+    Yd = _assembled(D, U, V) @ np.vstack(X)
+    ab = lambda m: None if m is None else np.asfortranarray(np.abs(m))
+    Dabs = np.vstack(orc.blr_matvec([ab(d) for d in D], [[ab(u) for u in row] for row in U],
+                                    [[ab(v) for v in row] for row in V], [ab(x) for x in X]))
+    n = nb * b + r
+    assert np.all(np.abs(Y - Yd) <= 2 * gamma(n) * Dabs)
+    assert np.max(np.abs(Y - Yd) / Dabs) < 1e-14
