@@ -222,10 +222,51 @@ def run_lrmult_config(args):
             "roofline": roof, "step_ms_min": round(min(per), 4), "step_ms_max": round(max(per), 4)}
 
 
+def time_calls(fn, steps, warmup, stream):
+    """Average time of fn() (device work enqueued on `stream`), HIP events."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def vendor_lrmult(w, steps, warmup, stream):
+    """The same batch as three vendor strided-batched DGEMMs (torch.bmm on
+    ROCm: rocBLAS / hipBLASLt), C and E through HBM, on the operands in place.
+    Returns (ms, max |G_vendor - G| / max |G|) on the first instances."""
+    import torch
+    pin, pout = w.pools
+    n, b, r, per, per_g = w.meta["count"], w.meta["b"], w.meta["r"], w.meta["per"], w.meta["per_g"]
+    oV, oU, oXA, oXB = w.meta["offs"]
+    VAt = pin.as_strided((n, r, b), (per, b, 1), oV)     # V_A^T (V_A stored b x r column-major)
+    UB = pin.as_strided((n, b, r), (per, 1, b), oU)
+    XA = pin.as_strided((n, r, r), (per, 1, r), oXA)
+    XB = pin.as_strided((n, r, r), (per, 1, r), oXB)
+    C = torch.empty(n, r, r, dtype=torch.float64, device=pin.device)
+    E, G = torch.empty_like(C), torch.empty_like(C)
+
+    def chain():
+        torch.bmm(VAt, UB, out=C)
+        torch.bmm(XA, C, out=E)
+        torch.bmm(E, XB, out=G)
+    ms = time_calls(chain, steps, warmup, stream)
+    ours = pout.as_strided((min(n, 64), r, r), (per_g, 1, r), 0)
+    diff = float((G[:ours.shape[0]] - ours).abs().max() / ours.abs().max())
+    return ms, diff
+
+
 def run_lrmult_paper(count=20000, bs=(512, 1024, 2048), rs=(8, 16, 32, 96, 128), steps=10, warmup=2):
     """The paper's batched low-rank product G = X_A (V_A^T U_B) X_B at its
     measured shapes (batch 20 000 per (b, r)); GFLOP/s by the paper's count
-    4 r^3 + 2 r^2 b per instance."""
+    4 r^3 + 2 r^2 b per instance.  Beside each: the vendor library's
+    batched DGEMM on the same operands (three calls), as context."""
     import torch
     from paper_2311_07602_amd import lrbg, workloads
     stream = torch.cuda.current_stream()
@@ -237,15 +278,58 @@ def run_lrmult_paper(count=20000, bs=(512, 1024, 2048), rs=(8, 16, 32, 96, 128),
             st = plan.stats()
             ms, _ = time_plan(plan, steps, warmup, stream)
             plan.close()
+            vms, vdiff = vendor_lrmult(w, steps, warmup, stream)
             del w
             torch.cuda.empty_cache()
             f, by = st["useful_flops"], st["hbm_bytes"]
             roof = max(f / (PEAK_FP64_TFLOPS * 1e12), by / (PEAK_HBM_GBS * 1e9)) * 1e3
             out.append({"b": b, "r": r, "ms_per_step": round(ms, 4), "GFLOP/s": round(f / ms / 1e6, 1),
-                        "GB/s": round(by / ms / 1e6, 1), "frac_of_roofline_time": round(roof / ms, 4)})
-            log(f"[bench] lrmult b={b} r={r}: {ms:.4f} ms, {f / ms / 1e6:.0f} GFLOP/s, {by / ms / 1e6:.0f} GB/s")
+                        "GB/s": round(by / ms / 1e6, 1), "frac_of_roofline_time": round(roof / ms, 4),
+                        "vendor_ms": round(vms, 4), "speedup_vs_vendor": round(vms / ms, 2),
+                        "vendor_rel_diff": vdiff})
+            log(f"[bench] lrmult b={b} r={r}: {ms:.4f} ms, {f / ms / 1e6:.0f} GFLOP/s, {by / ms / 1e6:.0f} GB/s; "
+                f"vendor {vms:.4f} ms")
     return {"workload": f"{count} x G = X_A (V_A^T U_B) X_B per (b, r), FP64, N(0,1), fused (one tile per "
-                        f"instance)", "flops_per_instance": "4 r^3 + 2 r^2 b", "bound": "hbm for r <= 32, mfma for r >= 96", "shapes": out}
+                        f"instance)", "flops_per_instance": "4 r^3 + 2 r^2 b",
+            "bound": "hbm for r <= 32, mfma for r >= 96",
+            "vendor": "torch.bmm (rocBLAS/hipBLASLt strided-batched DGEMM), three calls per step, C and E in HBM",
+            "shapes": out}
+
+
+def run_vendor_grouped(w, steps=5, warmup=2):
+    """The uneven batch through the vendor library: one strided-batched DGEMM
+    per (op, b, r) bucket (torch.bmm), on contiguous per-bucket copies of the
+    operands made before timing (the copies are not timed)."""
+    import torch
+    from collections import defaultdict
+    from paper_2311_07602_amd import workloads
+    stream = torch.cuda.current_stream()
+    pin = w.pools[0]
+    groups = defaultdict(list)
+    for i, (b, r) in enumerate(w.meta["shapes"]):
+        groups[(b, r)].append(i)
+    calls = []
+    for (b, r), ids in sorted(groups.items()):
+        cm = lambda off, rows, cols: pin[off:off + rows * cols].view(cols, rows)   # [col, row]
+        A = torch.stack([cm(w.index[i][2], b, b) for i in ids]).transpose(1, 2)     # n x b x b
+        U = torch.stack([cm(w.index[i][3], b, r) for i in ids]).transpose(1, 2)     # n x b x r
+        V1t = torch.stack([cm(w.index[i][4], b, r) for i in ids])                   # n x r x b = V1^T
+        U2 = torch.stack([cm(w.index[i][5], b, r) for i in ids]).transpose(1, 2)    # n x b x r
+        C = torch.empty(len(ids), b, r, dtype=torch.float64, device=pin.device)
+        T = torch.empty(len(ids), r, r, dtype=torch.float64, device=pin.device)
+        calls.append((A, U, C, V1t, U2, T))
+    torch.cuda.synchronize()
+
+    def all_calls():
+        for A, U, C, V1t, U2, T in calls:
+            torch.bmm(A, U, out=C)
+            torch.bmm(V1t, U2, out=T)
+    ms = time_calls(all_calls, steps, warmup, stream)
+    del calls
+    torch.cuda.empty_cache()
+    return {"workload": "the uneven batch, one torch.bmm (rocBLAS/hipBLASLt strided-batched DGEMM) per (op, b, r) "
+                        f"bucket, {2 * len(groups)} calls per step on contiguous per-bucket copies",
+            "ms_per_step": round(ms, 4)}
 
 
 def run_blr(nbs=(32, 64, 128), b=512, r=8, nrhs=8, steps=20, warmup=3):
@@ -348,6 +432,18 @@ def main():
         log("[bench] extra workloads ...")
         line["extra"] = {"dense_uniform": run_dense_uniform(), "chain_fp64": run_chain(),
                          "chain_bf16x3": run_chain(prec="bf16x3")}
+        log("[bench] vendor batched DGEMM on the uneven batch ...")
+        wv = None
+        try:
+            from paper_2311_07602_amd import workloads
+            wv = workloads.grouped(args.count, seed=3)
+            vg = run_vendor_grouped(wv)
+            vg["speedup_of_grouped_kernel"] = round(vg["ms_per_step"] / line["ms_per_step"], 2)
+            line["extra"]["vendor_uneven_batch"] = vg
+        finally:
+            del wv
+            import torch
+            torch.cuda.empty_cache()
         log("[bench] paper-shape low-rank products ...")
         line["extra"]["lrmult_paper_shapes"] = run_lrmult_paper()
         log("[bench] BLR matrix x 8 right-hand sides ...")

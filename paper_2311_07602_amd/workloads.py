@@ -157,7 +157,8 @@ def lrmult(count: int = 20000, b: int = 1024, r: int = 16, seed: int = 5, device
         descs.append(lrbg.desc("lrmult", _cm(pin, oV, b, r), _cm(pin, oU, b, r), _cm(pout, oG, r, r),
                                s=_cm(pin, oXA, r, r), e=_cm(pin, oXB, r, r)))
         index.append((oV, oU, oXA, oXB, oG))
-    return Workload("lrmult", descs, [pin, pout], {"count": count, "b": b, "r": r, "seed": seed}, index)
+    return Workload("lrmult", descs, [pin, pout], {"count": count, "b": b, "r": r, "seed": seed, "per": per,
+                                                  "offs": [int(o) for o in off1], "per_g": per_g}, index)
 
 
 def lrmult_operands(w: Workload, i: int):
