@@ -98,6 +98,8 @@ def run_grouped(args):
     flags = 0
     if args.persistent:
         flags |= lrbg.LRBG_PLAN_PERSISTENT
+    if args.dual:
+        flags |= lrbg.LRBG_PLAN_DUAL
     if not args.lpt:
         flags |= lrbg.LRBG_PLAN_SCHED_MIX
     plan = lrbg.Plan(w.descs, tune_cache=args.tune_cache, flags=flags)
@@ -404,6 +406,8 @@ def main():
     ap.add_argument("--lr-r", type=int, default=32)
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2311_07602_amd", "tune", "mi355x.tune"))
     ap.add_argument("--persistent", action="store_true")
+    ap.add_argument("--dual", action="store_true", help="dual-role persistent workgroups (one matrix-core-bound "
+                    "and one memory-bound workgroup per CU)")
     ap.add_argument("--lpt", action="store_true", help="longest-first tile order instead of the mixed "
                     "compute-/memory-bound order")
     ap.add_argument("--no-cpu-baseline", action="store_true")

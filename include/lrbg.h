@@ -174,6 +174,12 @@ typedef struct lrbg_plan lrbg_plan;
                                       per tile, hardware-dispatched) */
 #define LRBG_PLAN_NO_GRAPH   0x2u  /* replay by direct launches instead of a
                                       captured hipGraph */
+#define LRBG_PLAN_DUAL       0x8u  /* role-steered dispatch: a starting
+                                      workgroup takes a matrix-core-bound tile
+                                      if none runs on its CU, else a
+                                      memory-bound one, so both kinds share
+                                      every CU (takes precedence over
+                                      PERSISTENT) */
 #define LRBG_PLAN_SCHED_MIX  0x4u  /* interleave compute-bound and memory-bound
                                       tiles instead of longest-first order */
 

@@ -460,6 +460,8 @@ static bool compute_bound(const lrbg_desc &d)
 
 // ------------------------------------------------------------- plans
 
+constexpr uint32_t kPlanFlags = LRBG_PLAN_PERSISTENT | LRBG_PLAN_NO_GRAPH | LRBG_PLAN_SCHED_MIX | LRBG_PLAN_DUAL;
+
 struct Level {
     int64_t off[kFamilies] = {};   // per kernel family: first tile in the plan's tile array
     int32_t n[kFamilies] = {};     // and the grid of its one-workgroup-per-tile launch
@@ -476,6 +478,7 @@ struct lrbg_plan {
     lrbg::Tile *d_tiles = nullptr;
     int32_t *d_qinfo = nullptr;
     int32_t *d_counters = nullptr;
+    int32_t *d_cu = nullptr;      // per-CU role flags (LRBG_PLAN_DUAL)
     std::vector<lrbg::Level> levels;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -632,6 +635,38 @@ static void lay_tiles(const std::vector<int64_t> &prods, const lrbg_desc *ds, co
     ps.reserve(prods.size());
     for (int64_t i : prods) ps.push_back(P{i, est_time(ds[i])});
     std::stable_sort(ps.begin(), ps.end(), [](const P &x, const P &y) { return x.t > y.t; });
+    std::vector<int32_t> p0s, edge;
+    if ((flags & LRBG_PLAN_DUAL) && queues) {
+        // 16 queues, role-major: q = role * 8 + xcd; role 0 = matrix-core-bound
+        // products, role 1 = memory-bound; each role LPT-balanced over the 8
+        // XCD queues, longest first within a queue, a product's tiles adjacent.
+        std::vector<std::vector<int64_t>> qs(2 * kXcds);
+        std::vector<double> load(2 * kXcds, 0.0);
+        for (const P &p : ps) {
+            const int role = compute_bound(ds[p.i]) ? 0 : 1;
+            int qmin = role * kXcds;
+            for (int x = 1; x < kXcds; ++x)
+                if (load[role * kXcds + x] < load[qmin]) qmin = role * kXcds + x;
+            qs[qmin].push_back(p.i);
+            load[qmin] += p.t;
+        }
+        tile_off = (int64_t)sch.tiles.size();
+        int32_t off = 0;
+        for (auto &q : qs) {
+            sch.qinfo.push_back(off);
+            for (int64_t i : q) {
+                p0s.clear();
+                edge.clear();
+                tiles_of(variant[(size_t)i], ds[i], p0s, edge);
+                for (size_t t = 0; t < p0s.size(); ++t)
+                    sch.tiles.push_back(Tile{(int32_t)i, variant[(size_t)i], p0s[t], edge[t]});
+                off += (int32_t)p0s.size();
+            }
+        }
+        sch.qinfo.push_back(off);
+        ntiles = off;
+        return;
+    }
     std::vector<std::vector<int64_t>> bins(kXcds);
     std::vector<double> load(kXcds, 0.0);
     for (const P &p : ps) {
@@ -665,7 +700,6 @@ static void lay_tiles(const std::vector<int64_t> &prods, const lrbg_desc *ds, co
         }
     }
     std::vector<std::vector<Tile>> bt(kXcds);
-    std::vector<int32_t> p0s, edge;
     for (int b = 0; b < kXcds; ++b)
         for (int64_t i : bins[b]) {
             p0s.clear();
@@ -721,8 +755,8 @@ static void layout_level(const std::vector<int64_t> &prods, const lrbg_desc *ds,
     for (int64_t i : prods) fam[family_of(variant[(size_t)i])].push_back(i);
     lv.qinfo_off = (int32_t)sch.qinfo.size();
     for (int f = 0; f < kFamilies; ++f)
-        lay_tiles(fam[f], ds, variant, f == F_GROUPED ? flags : flags & ~LRBG_PLAN_PERSISTENT, sch, lv.off[f],
-                  lv.n[f], f == F_GROUPED);
+        lay_tiles(fam[f], ds, variant, f == F_GROUPED ? flags : flags & ~(LRBG_PLAN_PERSISTENT | LRBG_PLAN_DUAL),
+                  sch, lv.off[f], lv.n[f], f == F_GROUPED);
 }
 
 static lrbg_status build_schedule(const lrbg_desc *ds, int64_t n, const TuneTable &tt, uint32_t flags,
@@ -827,7 +861,13 @@ static lrbg_status enqueue_levels(lrbg_plan *p, hipStream_t stream)
         }
         if (lv.n[F_GROUPED] <= 0) continue;
         int rc;
-        if (p->flags & LRBG_PLAN_PERSISTENT) {
+        if (p->flags & LRBG_PLAN_DUAL) {
+            rc = launch_reset(p->d_counters + lv.qinfo_off, 2 * kXcds, stream);
+            if (!rc) rc = launch_reset(p->d_cu, cu_key_count(), stream);
+            if (rc) return fail(LRBG_EDEVICE, "reset launch failed: %s", hipGetErrorString((hipError_t)rc));
+            rc = launch_steered(p->d_descs, p->d_tiles + lv.off[F_GROUPED], p->d_qinfo + lv.qinfo_off,
+                                p->d_counters + lv.qinfo_off, p->d_cu, lv.n[F_GROUPED], stream);
+        } else if (p->flags & LRBG_PLAN_PERSISTENT) {
             rc = launch_reset(p->d_counters + lv.qinfo_off, kXcds, stream);
             if (rc) return fail(LRBG_EDEVICE, "reset launch failed: %s", hipGetErrorString((hipError_t)rc));
             rc = launch_persistent(p->d_descs, p->d_tiles + lv.off[F_GROUPED], p->d_qinfo + lv.qinfo_off,
@@ -856,6 +896,8 @@ static lrbg_status plan_from_schedule(Schedule &sch, uint32_t flags, lrbg_plan *
     const size_t nq = std::max<size_t>(sch.qinfo.size(), 1) * sizeof(int32_t);
     if (hipMalloc(&p->d_descs, nd) != hipSuccess || hipMalloc(&p->d_tiles, nt) != hipSuccess ||
         hipMalloc(&p->d_qinfo, nq) != hipSuccess || hipMalloc(&p->d_counters, nq) != hipSuccess)
+        return cleanup(fail(LRBG_ENOMEM, "device allocation for the plan failed"));
+    if ((flags & LRBG_PLAN_DUAL) && hipMalloc(&p->d_cu, (size_t)cu_key_count() * sizeof(int32_t)) != hipSuccess)
         return cleanup(fail(LRBG_ENOMEM, "device allocation for the plan failed"));
     if (hipMemcpy(p->d_descs, sch.descs.data(), nd, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(p->d_tiles, sch.tiles.data(), nt, hipMemcpyHostToDevice) != hipSuccess ||
@@ -1065,7 +1107,7 @@ lrbg_status lrbg_plan_create(lrbg_plan **out, const lrbg_desc *descs, int64_t co
 {
     if (!out) return fail(LRBG_EINVAL, "out is NULL");
     *out = nullptr;
-    if (flags & ~(uint32_t)(LRBG_PLAN_PERSISTENT | LRBG_PLAN_NO_GRAPH | LRBG_PLAN_SCHED_MIX))
+    if (flags & ~kPlanFlags)
         return fail(LRBG_EINVAL, "unknown plan flags 0x%x", flags);
     TuneTable tt;
     load_tune_cache(tune_cache ? tune_cache : getenv("LRBG_TUNE_CACHE"), tt);
@@ -1079,7 +1121,7 @@ lrbg_status lrbg_schedule_stats(const lrbg_desc *descs, int64_t count, const cha
                                 lrbg_plan_stats *out)
 {
     if (!out) return fail(LRBG_EINVAL, "out is NULL");
-    if (flags & ~(uint32_t)(LRBG_PLAN_PERSISTENT | LRBG_PLAN_NO_GRAPH | LRBG_PLAN_SCHED_MIX))
+    if (flags & ~kPlanFlags)
         return fail(LRBG_EINVAL, "unknown plan flags 0x%x", flags);
     TuneTable tt;
     load_tune_cache(tune_cache, tt);
@@ -1094,7 +1136,7 @@ lrbg_status lrbg_schedule_variants(const lrbg_desc *descs, int64_t count, const 
                                    int32_t *variant_out)
 {
     if (count > 0 && !variant_out) return fail(LRBG_EINVAL, "variant_out is NULL");
-    if (flags & ~(uint32_t)(LRBG_PLAN_PERSISTENT | LRBG_PLAN_NO_GRAPH | LRBG_PLAN_SCHED_MIX))
+    if (flags & ~kPlanFlags)
         return fail(LRBG_EINVAL, "unknown plan flags 0x%x", flags);
     TuneTable tt;
     load_tune_cache(tune_cache, tt);
@@ -1143,6 +1185,7 @@ lrbg_status lrbg_plan_destroy(lrbg_plan *p)
     if (p->d_tiles) (void)hipFree(p->d_tiles);
     if (p->d_qinfo) (void)hipFree(p->d_qinfo);
     if (p->d_counters) (void)hipFree(p->d_counters);
+    if (p->d_cu) (void)hipFree(p->d_cu);
     delete p;
     return LRBG_OK;
 }

@@ -142,6 +142,9 @@ struct VariantInfo {
 int launch_persistent(const DevDesc *descs, const Tile *tiles, const int32_t *qinfo,
                       int32_t *counters, int grid, void *stream);
 int launch_reset(int32_t *counters, int n, void *stream);
+int launch_steered(const DevDesc *descs, const Tile *tiles, const int32_t *qinfo, int32_t *counters,
+                   int32_t *cu_busy, int ntiles, void *stream);
+int cu_key_count();
 int launch_family(int family, const DevDesc *descs, const Tile *tiles, int ntiles, void *stream);
 int launch_lrm_family(int family, const DevDesc *descs, const Tile *tiles, int ntiles, void *stream);
 int persistent_blocks_per_cu();

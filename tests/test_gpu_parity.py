@@ -280,7 +280,8 @@ def _check_cases(cases, outs, bitwise_to=None):
 
 
 @pytest.mark.parametrize("flags", [0, lrbg.LRBG_PLAN_NO_GRAPH, lrbg.LRBG_PLAN_SCHED_MIX,
-                                   lrbg.LRBG_PLAN_PERSISTENT])
+                                   lrbg.LRBG_PLAN_PERSISTENT, lrbg.LRBG_PLAN_DUAL,
+                                   lrbg.LRBG_PLAN_DUAL | lrbg.LRBG_PLAN_NO_GRAPH])
 def test_grouped_mixed_plan(flags):
     cases = _mixed_batch(7)
     descs, outs, keep = _descs_for(cases)
