@@ -334,6 +334,54 @@ def run_vendor_grouped(w, steps=5, warmup=2):
             "ms_per_step": round(ms, 4)}
 
 
+def run_round(count=20000, b=1024, rs=(8, 16, 32), tol=1e-8, steps=10, warmup=2):
+    """The product of two low-rank blocks recompressed to rank <= r / 2 (fused
+    core, batched truncated SVD, new bases), one-shot calls on device-resident
+    N(0,1) operands."""
+    import torch
+    from paper_2311_07602_amd import inputs, lrbg
+    stream = torch.cuda.current_stream()
+    out = []
+    for r in rs:
+        kmax = max(r // 2, 1)
+        per = 4 * b * r + 2 * r * r
+        pin = inputs.device_normal(count * per, seed=17 + r)
+        U = torch.empty(count, kmax, b, dtype=torch.float64, device="cuda")
+        V = torch.empty_like(U)
+        sigma = torch.empty(count * kmax, dtype=torch.float64, device="cuda")
+        kout = torch.empty(count, dtype=torch.int32, device="cuda")
+        base = pin.data_ptr()
+        off = lambda t, j: base + 8 * (t * per + j * b * r)
+        offs = lambda t, j: base + 8 * (t * per + 4 * b * r + j * r * r)
+        ts = range(count)
+        args = ([b] * count, [r] * count, [r] * count,
+                [off(t, 0) for t in ts], [b] * count, [off(t, 1) for t in ts], [b] * count,
+                [offs(t, 0) for t in ts], [r] * count, [off(t, 2) for t in ts], [b] * count,
+                [offs(t, 1) for t in ts], [r] * count, [off(t, 3) for t in ts], [b] * count,
+                kmax, tol, [U[t].data_ptr() for t in ts], [b] * count, [V[t].data_ptr() for t in ts], [b] * count,
+                sigma.data_ptr(), kout.data_ptr())
+        call = lambda: lrbg.lr_batched_lrmult_round(*args, stream=stream)
+        ms = time_calls(call, steps, warmup, stream)        # host-inclusive: schedules built per call
+        # device time: hold the stream in a device-side sleep while the host enqueues, then
+        # bracket only the enqueued work with events
+        dev = []
+        for _ in range(3):
+            torch.cuda._sleep(int(2e8))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            call()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            dev.append(e0.elapsed_time(e1))
+        out.append({"b": b, "r": r, "kmax": kmax, "ms_per_call": round(ms, 4), "device_ms": round(min(dev), 4)})
+        log(f"[bench] recompressed product b={b} r={r}: {ms:.4f} ms per call, {min(dev):.4f} ms on the device")
+        del pin, U, V
+        torch.cuda.empty_cache()
+    return {"workload": f"{count} x (A_U A_X A_V^T)(B_U B_X B_V^T) recompressed to rank <= r/2 (tol {tol}), FP64, "
+                        f"one lr_batched_lrmult_round call (fused core, batched SVD, two DENSE_TS)",
+            "sizes": out}
+
+
 def run_blr(nbs=(32, 64, 128), b=512, r=8, nrhs=8, steps=20, warmup=3):
     """Weakly admissible BLR matrix times 8 right-hand sides (rank 8), the
     application of the paper's evaluation; one captured two-level plan per
@@ -436,6 +484,10 @@ def main():
         log("[bench] extra workloads ...")
         line["extra"] = {"dense_uniform": run_dense_uniform(), "chain_fp64": run_chain(),
                          "chain_bf16x3": run_chain(prec="bf16x3")}
+        # the serving loop allocates per request: run it before the large workloads below
+        # so that the allocator's cache, not fresh device allocations, serves its requests
+        log("[bench] serving ...")
+        line["extra"]["serving"] = run_serving()
         log("[bench] vendor batched DGEMM on the uneven batch ...")
         wv = None
         try:
@@ -450,10 +502,10 @@ def main():
             torch.cuda.empty_cache()
         log("[bench] paper-shape low-rank products ...")
         line["extra"]["lrmult_paper_shapes"] = run_lrmult_paper()
+        log("[bench] recompressed low-rank products ...")
+        line["extra"]["lrmult_round"] = run_round()
         log("[bench] BLR matrix x 8 right-hand sides ...")
         line["extra"]["blr_matvec"] = run_blr()
-        log("[bench] serving ...")
-        line["extra"]["serving"] = run_serving()
     print(json.dumps(line), flush=True)
 
 

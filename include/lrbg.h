@@ -155,6 +155,40 @@ lrbg_status lr_batched_lrmult(int64_t count, const int32_t *b,
                               void *stream);
 
 /*
+ * lr_batched_lrmult_round -- `count` products of two low-rank blocks,
+ * recompressed: A = A_U A_X A_V^T and B = B_U B_X B_V^T (b x b blocks, ranks
+ * ra and rb, orthonormal outer bases A_U, B_V) give A B = A_U G B_V^T with
+ * the core G = A_X (A_V^T B_U) B_X of Alg. 1; G = X S Y^T (singular value
+ * decomposition) is truncated to the k largest singular values with
+ * sigma_i > tol * sigma_1, k <= kmax, and the result is returned as
+ * U diag(sigma) V^T with U = A_U X_k, V = B_V Y_k.  FP64.
+ *   b, ra, rb     : host arrays [count]; ra, rb <= 64.
+ *   AU, AV        : device b x ra (A_U, and A_V: the stored A_{V^T} transposed).
+ *   AX            : device ra x ra.
+ *   BU, BV        : device b x rb.   BX: device rb x rb.
+ *   kmax, tol     : 1 <= kmax <= 64; relative truncation threshold tol >= 0.
+ *   U, V          : device b x kmax outputs (columns beyond the kept rank
+ *                   are zero).
+ *   sigma         : device array [count * kmax], instance t at t * kmax,
+ *                   descending, zero beyond the kept rank.
+ *   kout          : device array [count]: the rank kept.
+ * The singular vectors (columns of U, V) are unique up to sign; U diag(sigma)
+ * V^T is unique when sigma_k > sigma_{k+1}.  Scratch for G, X, Y is
+ * allocated by the library (pooled, reused once the call's work has run).
+ */
+lrbg_status lr_batched_lrmult_round(int64_t count, const int32_t *b, const int32_t *ra, const int32_t *rb,
+                                    const double *const *AU, const int32_t *ldau,
+                                    const double *const *AV, const int32_t *ldav,
+                                    const double *const *AX, const int32_t *ldax,
+                                    const double *const *BU, const int32_t *ldbu,
+                                    const double *const *BX, const int32_t *ldbx,
+                                    const double *const *BV, const int32_t *ldbv,
+                                    int32_t kmax, double tol,
+                                    double *const *U, const int32_t *ldu,
+                                    double *const *V, const int32_t *ldv,
+                                    double *sigma, int32_t *kout, void *stream);
+
+/*
  * lrbg_grouped -- one launch sequence over `count` heterogeneous products
  * (any mix of ops, precisions, sizes).  Products whose input is exactly the
  * output buffer of another product of the same call (e.g. a RECOMP whose

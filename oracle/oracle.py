@@ -25,7 +25,7 @@ _LIB_PATH = os.path.join(_HERE, "liblrbg_oracle.so")
 _lib = None
 
 __all__ = [
-    "load", "dense_ts", "inner", "recomp", "chain", "lr_mult", "blr_matvec", "dot2",
+    "load", "dense_ts", "inner", "recomp", "chain", "lr_mult", "lr_mult_round", "blr_matvec", "dot2",
     "max_threads", "normalized_error", "normwise_error", "col_major",
 ]
 
@@ -162,6 +162,30 @@ def lr_mult(AVs, BUs, AXs, BXs, nthreads: int = 0):
     if rc:
         raise MemoryError("oracle lr_mult: allocation failed")
     return Gs
+
+
+def lr_mult_round(AU, AV, AX, BU, BX, BV, kmax: int, tol: float):
+    """The product of two low-rank blocks recompressed to rank <= kmax:
+    G = A_X (A_V^T B_U) B_X (Alg. 1, the oracle's loops), its singular value
+    decomposition (LAPACK through numpy, a library step), truncation to the
+    k largest singular values above tol * sigma_1, and the new bases A_U X_k,
+    B_V Y_k (the oracle's loops).  Returns (U, sigma, V, k) with U, V
+    b x kmax and sigma of length kmax, zero beyond k."""
+    G = lr_mult([AV], [BU], [AX], [BX])[0]
+    ra, rb = G.shape
+    if G.size == 0:
+        s = np.zeros(0); X = np.zeros((ra, 0)); Yt = np.zeros((0, rb))
+    else:
+        X, s, Yt = np.linalg.svd(G, full_matrices=False)
+    k = 0
+    while k < len(s) and k < kmax and s[0] > 0 and s[k] > tol * s[0]:
+        k += 1
+    Xk = col_major(ra, kmax, fill=0.0); Yk = col_major(rb, kmax, fill=0.0)
+    Xk[:, :k] = X[:, :k]; Yk[:, :k] = Yt[:k, :].T
+    sig = np.zeros(kmax); sig[:k] = s[:k]
+    U = dense_ts([AU], [Xk])[0]
+    V = dense_ts([BV], [Yk])[0]
+    return U, sig, V, k
 
 
 def blr_matvec(diag, U, V, X, nthreads: int = 0):

@@ -946,20 +946,28 @@ struct Staging {
     size_t cap = 0;
     hipEvent_t ev = nullptr;
     bool in_use = false;
+    bool recorded = false;   // ev marks the end of the current use (set under g_mu)
 };
 static std::mutex g_mu;
 static std::vector<Staging *> g_staging;
 
-static Staging *acquire_staging(size_t bytes)
+// with_host: also a pinned host buffer of the same size (for uploads);
+// without: device scratch only.
+static Staging *acquire_staging(size_t bytes, bool with_host = true)
 {
     std::lock_guard<std::mutex> lk(g_mu);
     Staging *best = nullptr;
     for (Staging *st : g_staging) {
-        if (st->in_use && hipEventQuery(st->ev) == hipSuccess) st->in_use = false;
-        if (!st->in_use && st->cap >= bytes && (!best || st->cap < best->cap)) best = st;
+        // a buffer in use is free again only once the event recorded after
+        // its last enqueued use has completed (an event not yet recorded for
+        // this use reads as complete)
+        if (st->in_use && st->recorded && hipEventQuery(st->ev) == hipSuccess) st->in_use = false;
+        if (!st->in_use && st->cap >= bytes && (st->host != nullptr) == with_host && (!best || st->cap < best->cap))
+            best = st;
     }
     if (best) {
         best->in_use = true;
+        best->recorded = false;
         return best;
     }
     size_t cap = 4096;
@@ -970,7 +978,7 @@ static Staging *acquire_staging(size_t bytes)
         delete st;
         return nullptr;
     }
-    if (hipHostMalloc(&st->host, cap, hipHostMallocDefault) != hipSuccess ||
+    if ((with_host && hipHostMalloc(&st->host, cap, hipHostMallocDefault) != hipSuccess) ||
         hipEventCreateWithFlags(&st->ev, hipEventDisableTiming) != hipSuccess) {
         (void)hipFree(st->dev);
         if (st->host) (void)hipHostFree(st->host);
@@ -979,18 +987,32 @@ static Staging *acquire_staging(size_t bytes)
     }
     st->cap = cap;
     st->in_use = true;
+    st->recorded = false;
     g_staging.push_back(st);
     return st;
 }
 
-static lrbg_status run_once(const lrbg_desc *ds, int64_t n, hipStream_t stream)
+static void release_staging(Staging *sg)
 {
-    if (n == 0) return LRBG_OK;
-    Schedule sch;
-    TuneTable tt;
-    load_tune_cache(getenv("LRBG_TUNE_CACHE"), tt);
-    lrbg_status st = build_schedule(ds, n, tt, 0, nullptr, sch);
-    if (st != LRBG_OK) return st;
+    std::lock_guard<std::mutex> lk(g_mu);
+    sg->in_use = false;
+}
+
+// Record sg's release event on `stream` (after everything that uses sg).
+static hipError_t record_release(Staging *sg, hipStream_t stream)
+{
+    const hipError_t e = hipEventRecord(sg->ev, stream);
+    if (e == hipSuccess) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        sg->recorded = true;
+    }
+    return e;
+}
+
+// Enqueue a built schedule on `stream` through pooled staging buffers.
+static lrbg_status enqueue_once(const Schedule &sch, hipStream_t stream)
+{
+    lrbg_status st = LRBG_OK;
     const size_t nd = sch.descs.size() * sizeof(DevDesc), nt = sch.tiles.size() * sizeof(Tile);
     const size_t toff = (nd + 255) / 256 * 256;
     Staging *sg = acquire_staging(toff + nt);
@@ -1014,12 +1036,184 @@ static lrbg_status run_once(const lrbg_desc *ds, int64_t n, hipStream_t stream)
         }
     }
     // the buffers are released only after everything enqueued above has run
-    e = hipEventRecord(sg->ev, stream);
+    e = record_release(sg, stream);
     if (e != hipSuccess) {
         (void)hipStreamSynchronize(stream);
-        std::lock_guard<std::mutex> lk(g_mu);
-        sg->in_use = false;
+        release_staging(sg);
         return st != LRBG_OK ? st : fail(LRBG_EDEVICE, "hipEventRecord: %s", hipGetErrorString(e));
+    }
+    return st;
+}
+
+static lrbg_status run_once(const lrbg_desc *ds, int64_t n, hipStream_t stream)
+{
+    if (n == 0) return LRBG_OK;
+    Schedule sch;
+    TuneTable tt;
+    load_tune_cache(getenv("LRBG_TUNE_CACHE"), tt);
+    lrbg_status st = build_schedule(ds, n, tt, 0, nullptr, sch);
+    if (st != LRBG_OK) return st;
+    return enqueue_once(sch, stream);
+}
+
+// ------------------------------------------------- recompressed product
+
+// Product of two low-rank blocks recompressed to rank <= kmax (see
+// lr_batched_lrmult_round): G = A_X (A_V^T B_U) B_X by the fused product,
+// G = X S Y^T truncated by the batched SVD, U = A_U X_k and V = B_V Y_k by
+// DENSE_TS.  Both product schedules are built (and so every argument is
+// validated) before anything is launched; G, X, Y live in pooled device
+// scratch released by an event after the last launch.
+struct RoundArgs {
+    int64_t count;
+    const int32_t *b, *ra, *rb;
+    const double *const *AU, *const *AV, *const *AX, *const *BU, *const *BX, *const *BV;
+    const int32_t *ldau, *ldav, *ldax, *ldbu, *ldbx, *ldbv;
+    int32_t kmax;
+    double tol;
+    double *const *U, *const *V;
+    const int32_t *ldu, *ldv;
+    double *sigma;
+    int32_t *kout;
+};
+
+static lrbg_status lrmult_round(const RoundArgs &a, hipStream_t stream)
+{
+    const int64_t n = a.count;
+    if (n < 0) return fail(LRBG_EINVAL, "negative count");
+    if (n == 0) return LRBG_OK;
+    if (!a.b || !a.ra || !a.rb || !a.AU || !a.AV || !a.AX || !a.BU || !a.BX || !a.BV || !a.ldau || !a.ldav ||
+        !a.ldax || !a.ldbu || !a.ldbx || !a.ldbv || !a.U || !a.V || !a.ldu || !a.ldv)
+        return fail(LRBG_EINVAL, "a required host array is NULL");
+    if (!a.sigma || !a.kout) return fail(LRBG_EINVAL, "sigma and kout must be device arrays");
+    if ((uintptr_t)a.sigma % 8 || (uintptr_t)a.kout % 4) return fail(LRBG_EINVAL, "sigma or kout misaligned");
+    if (a.kmax < 1 || a.kmax > svd_max_dim())
+        return fail(LRBG_EUNSUPPORTED, "kmax must be in [1, %d]", svd_max_dim());
+    if (!(a.tol >= 0.0) || !std::isfinite(a.tol)) return fail(LRBG_EINVAL, "tol must be finite and >= 0");
+    // scratch: G (ra x rb), X (ra x kmax), Y (rb x kmax) per product, 256-byte aligned
+    std::vector<size_t> og((size_t)n), ox((size_t)n), oy((size_t)n);
+    size_t total = 0;
+    auto take = [&](size_t elems) {
+        const size_t o = total;
+        total += (elems * 8 + 255) / 256 * 256;
+        return o;
+    };
+    for (int64_t t = 0; t < n; ++t) {
+        if (a.ra[t] < 0 || a.rb[t] < 0 || a.b[t] < 0)
+            return fail(LRBG_EINVAL, "product %lld: negative size", (long long)t);
+        if (a.ra[t] > svd_max_dim() || a.rb[t] > svd_max_dim())
+            return fail(LRBG_EUNSUPPORTED, "product %lld: ranks above %d", (long long)t, svd_max_dim());
+        og[(size_t)t] = take((size_t)a.ra[t] * a.rb[t]);
+        ox[(size_t)t] = take((size_t)a.ra[t] * a.kmax);
+        oy[(size_t)t] = take((size_t)a.rb[t] * a.kmax);
+    }
+    Staging *scr = acquire_staging(std::max<size_t>(total, 256), false);
+    if (!scr) return fail(LRBG_ENOMEM, "scratch allocation failed");
+    char *base = (char *)scr->dev;
+    std::vector<lrbg_desc> d1((size_t)n), d2((size_t)(2 * n));
+    std::vector<SvdDesc> sv((size_t)n);
+    for (int64_t t = 0; t < n; ++t) {
+        const int ra = a.ra[t], rb = a.rb[t], bb = a.b[t], km = a.kmax;
+        double *G = (double *)(base + og[(size_t)t]), *X = (double *)(base + ox[(size_t)t]),
+               *Y = (double *)(base + oy[(size_t)t]);
+        lrbg_desc &m = d1[(size_t)t];
+        m.op = LRBG_OP_LRMULT;
+        m.prec = LRBG_FP64;
+        m.m = ra;
+        m.n = rb;
+        m.k = bb;
+        m.a = a.AV[t];
+        m.lda = a.ldav[t];
+        m.b = a.BU[t];
+        m.ldb = a.ldbu[t];
+        m.s = a.AX[t];
+        m.lds = a.ldax[t];
+        m.e = a.BX[t];
+        m.lde = a.ldbx[t];
+        m.c = G;
+        m.ldc = std::max(ra, 1);
+        lrbg_desc &u = d2[(size_t)(2 * t)], &v = d2[(size_t)(2 * t + 1)];
+        u.op = v.op = LRBG_OP_DENSE_TS;
+        u.prec = v.prec = LRBG_FP64;
+        u.m = bb;
+        u.k = ra;
+        u.n = km;
+        u.a = a.AU[t];
+        u.lda = a.ldau[t];
+        u.b = X;
+        u.ldb = std::max(ra, 1);
+        u.c = a.U[t];
+        u.ldc = a.ldu[t];
+        u.lds = 1;
+        v.m = bb;
+        v.k = rb;
+        v.n = km;
+        v.a = a.BV[t];
+        v.lda = a.ldbv[t];
+        v.b = Y;
+        v.ldb = std::max(rb, 1);
+        v.c = a.V[t];
+        v.ldc = a.ldv[t];
+        v.lds = 1;
+        SvdDesc &s = sv[(size_t)t];
+        s.g = G;
+        s.x = X;
+        s.y = Y;
+        s.sigma = a.sigma + t * km;
+        s.kout = a.kout + t;
+        s.tol = a.tol;
+        s.m = ra;
+        s.n = rb;
+        s.ldg = std::max(ra, 1);
+        s.ldx = std::max(ra, 1);
+        s.ldy = std::max(rb, 1);
+        s.kmax = km;
+    }
+    TuneTable tt;
+    load_tune_cache(getenv("LRBG_TUNE_CACHE"), tt);
+    Schedule s1, s2;
+    lrbg_status st = build_schedule(d1.data(), n, tt, 0, nullptr, s1);
+    if (st == LRBG_OK) st = build_schedule(d2.data(), 2 * n, tt, 0, nullptr, s2);
+    Staging *sd = st == LRBG_OK ? acquire_staging(sv.size() * sizeof(SvdDesc)) : nullptr;
+    if (st == LRBG_OK && !sd) st = fail(LRBG_ENOMEM, "staging allocation failed");
+    if (st != LRBG_OK) {
+        release_staging(scr);
+        if (sd) release_staging(sd);
+        return st;
+    }
+    // group the cores by size class (one SVD launch per class)
+    const int classes[3] = {16, 32, 64};
+    std::vector<SvdDesc> byc;
+    byc.reserve(sv.size());
+    int ccount[3] = {0, 0, 0};
+    for (int c = 0; c < 3; ++c)
+        for (const SvdDesc &x : sv) {
+            const int dim = std::max(x.m, x.n);
+            const int cls = dim <= 16 ? 0 : dim <= 32 ? 1 : 2;
+            if (cls == c) {
+                byc.push_back(x);
+                ++ccount[c];
+            }
+        }
+    sv.swap(byc);
+    memcpy(sd->host, sv.data(), sv.size() * sizeof(SvdDesc));
+    hipError_t e = hipMemcpyAsync(sd->dev, sd->host, sv.size() * sizeof(SvdDesc), hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) st = fail(LRBG_EDEVICE, "hipMemcpyAsync: %s", hipGetErrorString(e));
+    if (st == LRBG_OK) st = enqueue_once(s1, stream);
+    if (st == LRBG_OK) {
+        int off = 0;
+        for (int c = 0; c < 3 && st == LRBG_OK; ++c) {
+            const int rc = launch_core_svd(classes[c], (const SvdDesc *)sd->dev + off, ccount[c], stream);
+            if (rc) st = fail(LRBG_EDEVICE, "svd launch failed: %s", hipGetErrorString((hipError_t)rc));
+            off += ccount[c];
+        }
+    }
+    if (st == LRBG_OK) st = enqueue_once(s2, stream);
+    // scratch and descriptors are released once everything above has run
+    if (record_release(scr, stream) != hipSuccess || record_release(sd, stream) != hipSuccess) {
+        (void)hipStreamSynchronize(stream);
+        release_staging(scr);
+        release_staging(sd);
     }
     return st;
 }
@@ -1094,6 +1288,19 @@ lrbg_status lr_batched_lrmult(int64_t count, const int32_t *b, const int32_t *ra
         d.ldc = ldg[i];
     }
     return run_once(ds.data(), count, (hipStream_t)stream);
+}
+
+lrbg_status lr_batched_lrmult_round(int64_t count, const int32_t *b, const int32_t *ra, const int32_t *rb,
+                                    const double *const *AU, const int32_t *ldau, const double *const *AV,
+                                    const int32_t *ldav, const double *const *AX, const int32_t *ldax,
+                                    const double *const *BU, const int32_t *ldbu, const double *const *BX,
+                                    const int32_t *ldbx, const double *const *BV, const int32_t *ldbv, int32_t kmax,
+                                    double tol, double *const *U, const int32_t *ldu, double *const *V,
+                                    const int32_t *ldv, double *sigma, int32_t *kout, void *stream)
+{
+    RoundArgs a{count, b, ra, rb, AU, AV, AX, BU, BX, BV, ldau, ldav, ldax, ldbu, ldbx, ldbv,
+                kmax, tol, U, V, ldu, ldv, sigma, kout};
+    return lrmult_round(a, (hipStream_t)stream);
 }
 
 lrbg_status lrbg_grouped(const lrbg_desc *descs, int64_t count, void *stream)

@@ -138,6 +138,17 @@ struct VariantInfo {
     int32_t kind, p1, p2, p3, p4;
 };
 
+// One small truncated SVD (recompression of a low-rank product's core).
+struct SvdDesc {
+    const double *g;    // m x n core, column-major, ld ldg
+    double *x;          // m x kmax left singular vectors (zero beyond the rank kept)
+    double *y;          // n x kmax right singular vectors
+    double *sigma;      // kmax singular values, descending (zero beyond the rank kept)
+    int32_t *kout;      // the rank kept
+    double tol;         // keep sigma_i > tol * sigma_max
+    int32_t m, n, ldg, ldx, ldy, kmax;
+};
+
 // Kernel launch helpers (defined in the lrbg_*.hip kernel sources).
 int launch_persistent(const DevDesc *descs, const Tile *tiles, const int32_t *qinfo,
                       int32_t *counters, int grid, void *stream);
@@ -148,5 +159,7 @@ int cu_key_count();
 int launch_family(int family, const DevDesc *descs, const Tile *tiles, int ntiles, void *stream);
 int launch_lrm_family(int family, const DevDesc *descs, const Tile *tiles, int ntiles, void *stream);
 int persistent_blocks_per_cu();
+int launch_core_svd(int nmax, const SvdDesc *descs, int count, void *stream);
+int svd_max_dim();
 
 }  // namespace lrbg

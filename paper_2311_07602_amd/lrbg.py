@@ -92,6 +92,8 @@ def load(path: Optional[str] = None):
     lib.lr_batched_gemm.restype = ctypes.c_int
     lib.lr_batched_lrmult.argtypes = [i64] + [vp] * 13 + [vp]
     lib.lr_batched_lrmult.restype = ctypes.c_int
+    lib.lr_batched_lrmult_round.argtypes = [i64] + [vp] * 15 + [i32, ctypes.c_double] + [vp] * 6 + [vp]
+    lib.lr_batched_lrmult_round.restype = ctypes.c_int
     lib.lrbg_grouped.argtypes = [P(lrbg_desc), i64, vp]
     lib.lrbg_grouped.restype = ctypes.c_int
     lib.lrbg_plan_create.argtypes = [P(vp), P(lrbg_desc), i64, ctypes.c_char_p, u32]
@@ -171,6 +173,21 @@ def lr_batched_lrmult(b: Sequence[int], ra: Sequence[int], rb: Sequence[int],
     ptrs = [ctypes.cast(a, vp) for a in args]
     st = load().lr_batched_lrmult(count, *ptrs, _stream_ptr(stream))
     return _check(st, "lr_batched_lrmult")
+
+
+def lr_batched_lrmult_round(b: Sequence[int], ra: Sequence[int], rb: Sequence[int],
+                            AU, ldau, AV, ldav, AX, ldax, BU, ldbu, BX, ldbx, BV, ldbv,
+                            kmax: int, tol: float, U, ldu, V, ldv, sigma: int, kout: int, stream=None) -> int:
+    """Pointer-array form of the recompressed low-rank product (see include/lrbg.h);
+    sigma and kout are device pointers."""
+    i32, vp = ctypes.c_int32, ctypes.c_void_p
+    arrs = [_arr(i32, b), _arr(i32, ra), _arr(i32, rb), _arr(vp, AU), _arr(i32, ldau), _arr(vp, AV),
+            _arr(i32, ldav), _arr(vp, AX), _arr(i32, ldax), _arr(vp, BU), _arr(i32, ldbu), _arr(vp, BX),
+            _arr(i32, ldbx), _arr(vp, BV), _arr(i32, ldbv)]
+    outs = [_arr(vp, U), _arr(i32, ldu), _arr(vp, V), _arr(i32, ldv)]
+    st = load().lr_batched_lrmult_round(len(b), *[ctypes.cast(x, vp) for x in arrs], int(kmax), float(tol),
+                                        *[ctypes.cast(x, vp) for x in outs], sigma, kout, _stream_ptr(stream))
+    return _check(st, "lr_batched_lrmult_round")
 
 
 def lrbg_grouped(descs: Sequence[lrbg_desc], stream=None) -> int:

@@ -351,3 +351,31 @@ def test_blr_matvec_within_bound_of_assembled_product(orc):
     n = nb * b + r
     assert np.all(np.abs(Y - Yd) <= 2 * gamma(n) * Dabs)
     assert np.max(np.abs(Y - Yd) / Dabs) < 1e-14
+
+
+# ------------------------------------------ recompressed low-rank product
+
+def test_lr_mult_round_recovers_a_planted_spectrum(orc):
+    """A core with known singular values: A_X = P diag(s) Q^T with A_V^T B_U
+    = I and B_X = I (orthonormal P, Q); the recompressed product keeps exactly
+    the singular values above tol * s_1, in order, and U diag(sigma) V^T is
+    the truncated product."""
+    rng = np.random.default_rng(41)
+    b, r = 40, 6
+    s = np.array([3.0, 2.0, 1.0, 1e-3, 1e-9, 1e-14])
+    P = inputs.orthonormal_f(rng, r, r); Q = inputs.orthonormal_f(rng, r, r)
+    AX = np.asfortranarray(P @ np.diag(s) @ Q.T)
+    W = inputs.orthonormal_f(rng, b, r)                 # A_V = B_U = W: A_V^T B_U = I
+    AU = inputs.orthonormal_f(rng, b, r); BV = inputs.orthonormal_f(rng, b, r)
+    BX = np.asfortranarray(np.eye(r))
+    for tol, kmax, want in ((1e-6, 6, 4), (1e-12, 6, 5), (0.0, 3, 3), (0.9, 6, 1)):
+        U, sig, V, k = orc.lr_mult_round(AU, W, AX, W, BX, BV, kmax, tol)
+        assert k == want
+        assert np.allclose(sig[:k], s[:k], rtol=1e-13, atol=1e-15)
+        assert np.all(sig[k:] == 0) and np.all(U[:, k:] == 0) and np.all(V[:, k:] == 0)
+        full = AU @ AX @ BV.T                            # the exact product (A_V^T B_U = I)
+        trunc = AU @ P[:, :k] @ np.diag(s[:k]) @ Q[:, :k].T @ BV.T
+        got = U[:, :k] @ np.diag(sig[:k]) @ V[:, :k].T
+        assert np.max(np.abs(got - trunc)) < 1e-13
+        assert np.max(np.abs(got - full)) <= (s[k] if k < r else 0) + 1e-13
+        assert np.allclose(U[:, :k].T @ U[:, :k], np.eye(k), atol=1e-13)
