@@ -188,22 +188,26 @@ def lr_mult_round(AU, AV, AX, BU, BX, BV, kmax: int, tol: float):
     return U, sig, V, k
 
 
-def blr_matvec(diag, U, V, X, nthreads: int = 0):
+def blr_matvec(diag, U, V, X, nthreads: int = 0, rows=None):
     """Block low-rank matrix times multiple right-hand sides (the application
     of Sec. 7): Y_i = A_ii X_i + sum over j != i of U_ij (V_ij^T X_j), each
     low-rank block applied as the paper's low-rank product does, rank-sized
     factor first.  diag[i]: b x b; U[i][j], V[i][j]: b x r (None on the
     diagonal); X[j]: b x nrhs.  The terms of a block row are added in order
-    of j, after the diagonal term.  Returns the list of Y_i."""
-    nb = len(diag)
-    Ys = dense_ts(list(diag), list(X), nthreads=nthreads)
-    pairs = [(i, j) for i in range(nb) for j in range(nb) if i != j]
+    of j, after the diagonal term.  Returns the list of Y_i (only the block
+    rows listed in `rows`, in that order, when given; blocks of other rows
+    are not read)."""
+    nb = len(X)
+    rows = list(range(nb)) if rows is None else list(rows)
+    Ys = dense_ts([diag[i] for i in rows], [X[i] for i in rows], nthreads=nthreads)
+    pos = {i: t for t, i in enumerate(rows)}
+    pairs = [(i, j) for i in rows for j in range(nb) if i != j]
     if not pairs:
         return Ys
     Ps = inner([V[i][j] for i, j in pairs], [X[j] for i, j in pairs], nthreads=nthreads)
     Zs = dense_ts([U[i][j] for i, j in pairs], Ps, nthreads=nthreads)
     for (i, j), Z in zip(pairs, Zs):
-        Ys[i] += Z
+        Ys[pos[i]] += Z
     return Ys
 
 

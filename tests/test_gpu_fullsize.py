@@ -88,3 +88,97 @@ def test_dense_uniform_every_instance():
         Cref, D = ref_dense_ts(A, U)
         assert oracle.normalized_error(C, Cref, D) <= 1e-13, i
     plan.close()
+
+
+@pytest.mark.parametrize("b,r", [(2048, 32), (2048, 128), (512, 8)])
+def test_lrmult_paper_shape_sampled(b, r):
+    """The paper's fused product at its batch of 20 000 (the bench's
+    lrmult_paper_shapes configuration): sampled instances against Alg. 1 in
+    the oracle, replays bitwise identical."""
+    import torch
+    from gpu_util import ref_lrmult
+    w = workloads.lrmult(20000, b, r)
+    plan = lrbg.Plan(w.descs)
+    _replay(plan)
+    g = w.pools[1].clone()
+    worst = 0.0
+    for i in (0, 1, 4999, 10001, 19999):
+        o = workloads.lrmult_operands(w, i)
+        Gref, D = ref_lrmult(o["AV"], o["BU"], o["AX"], o["BX"])
+        worst = max(worst, oracle.normalized_error(o["G"], Gref, D))
+    assert worst <= 1e-13, worst
+    w.pools[1].fill_(float("nan"))
+    _replay(plan, 1)
+    assert torch.equal(g.view(torch.int64), w.pools[1].view(torch.int64)), "replays differ"
+    plan.close()
+
+
+def test_blr_large_sampled_rows():
+    """BLR matrix x 8 right-hand sides at N = 65 536 (128 block rows of 512,
+    rank 8): sampled block rows against the oracle's BLR evaluation."""
+    from paper_2311_07602_amd import blr as _blr  # noqa: F401
+    m = workloads.blr(128, 512)
+    _replay(m.plan())
+    nb = m.nb
+    X = [np.asfortranarray(m.x(j).cpu().numpy()) for j in range(nb)]
+    worst = 0.0
+    for i in (0, 63, 127):
+        D = np.asfortranarray(m.diag(i).cpu().numpy())
+        U = [[None] * nb for _ in range(nb)]
+        V = [[None] * nb for _ in range(nb)]
+        for j in range(nb):
+            if j != i:
+                U[i][j] = np.asfortranarray(m.u(i, j).cpu().numpy())
+                V[i][j] = np.asfortranarray(m.v(i, j).cpu().numpy())
+        Dl = [None] * nb
+        Dl[i] = D
+        Y = oracle.blr_matvec(Dl, U, V, X, rows=[i])[0]
+        ab = lambda a: None if a is None else np.asfortranarray(np.abs(a))
+        Dy = oracle.blr_matvec([ab(d) for d in Dl], [[ab(u) for u in row] for row in U],
+                               [[ab(v) for v in row] for row in V], [ab(x) for x in X], rows=[i])[0]
+        worst = max(worst, oracle.normalized_error(m.y(i).cpu().numpy(), Y, Dy))
+    m.close()
+    assert worst <= 1e-13, worst
+
+
+def test_round_at_scale_sampled():
+    """The recompressed product over 2000 instances (b = 1024, r = 32, rank
+    <= 16): sampled instances' singular values against the oracle (within
+    1e-12 sigma_1) and orthonormal kept bases."""
+    import torch
+    from paper_2311_07602_amd import inputs
+    count, b, r, kmax, tol = 2000, 1024, 32, 16, 1e-8
+    per = 4 * b * r + 2 * r * r
+    pin = inputs.device_normal(count * per, seed=71)
+    U = torch.empty(count, kmax, b, dtype=torch.float64, device="cuda")
+    V = torch.empty_like(U)
+    sigma = torch.empty(count * kmax, dtype=torch.float64, device="cuda")
+    kout = torch.empty(count, dtype=torch.int32, device="cuda")
+    base = pin.data_ptr()
+    off = lambda t, j: base + 8 * (t * per + j * b * r)
+    offs = lambda t, j: base + 8 * (t * per + 4 * b * r + j * r * r)
+    ts = range(count)
+    lrbg.lr_batched_lrmult_round([b] * count, [r] * count, [r] * count,
+                                 [off(t, 0) for t in ts], [b] * count, [off(t, 1) for t in ts], [b] * count,
+                                 [offs(t, 0) for t in ts], [r] * count, [off(t, 2) for t in ts], [b] * count,
+                                 [offs(t, 1) for t in ts], [r] * count, [off(t, 3) for t in ts], [b] * count,
+                                 kmax, tol, [U[t].data_ptr() for t in ts], [b] * count,
+                                 [V[t].data_ptr() for t in ts], [b] * count, sigma.data_ptr(), kout.data_ptr(),
+                                 torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    host = pin.cpu().numpy()
+    sig = sigma.cpu().numpy().reshape(count, kmax)
+    ks = kout.cpu().numpy()
+    cm = lambda o, rows, cols: np.asfortranarray(host[o:o + rows * cols].reshape(cols, rows).T)
+    for t in (0, 777, 1999):
+        o = t * per
+        AU, AV, BU, BV = (cm(o + j * b * r, b, r) for j in range(4))
+        AX, BX = cm(o + 4 * b * r, r, r), cm(o + 4 * b * r + r * r, r, r)
+        Uo, so, Vo, ko = oracle.lr_mult_round(AU, AV, AX, BU, BX, BV, kmax, tol)
+        assert ks[t] == ko
+        assert np.all(np.abs(sig[t] - so) <= 1e-12 * so[0])
+        # kept columns equal the oracle's up to sign (the random cores have distinct singular values)
+        Ut = U[t].cpu().numpy().T
+        for j in range(ko):
+            d = min(np.max(np.abs(Ut[:, j] - Uo[:, j])), np.max(np.abs(Ut[:, j] + Uo[:, j])))
+            assert d <= 1e-8 * np.max(np.abs(Uo[:, j])), (t, j, d)

@@ -379,3 +379,11 @@ def test_lr_mult_round_recovers_a_planted_spectrum(orc):
         assert np.max(np.abs(got - trunc)) < 1e-13
         assert np.max(np.abs(got - full)) <= (s[k] if k < r else 0) + 1e-13
         assert np.allclose(U[:, :k].T @ U[:, :k], np.eye(k), atol=1e-13)
+
+
+def test_blr_matvec_selected_rows_equal_full_evaluation(orc):
+    rng = np.random.default_rng(32)
+    D, U, V, X = _blr_host(rng, 5, 6, 2, 3, inputs.normal_f)
+    full = orc.blr_matvec(D, U, V, X)
+    part = orc.blr_matvec(D, U, V, X, rows=[3, 0])
+    assert np.array_equal(part[0], full[3]) and np.array_equal(part[1], full[0])
