@@ -166,7 +166,10 @@ __device__ __forceinline__ void store_rows(gp col, const d4 (&acc)[RM], int g, i
 
 // ---------------------------------------------------------------------------
 // Staging of a k-contiguous operand chunk (KC rows of NCOL columns of a
-// column-major matrix) into LDS as buf[kk * P + j]: threads read 16-byte row
+// column-major matrix) into LDS as buf[kk * P + j] (the thread-count test is
+// resolved at compile time when NPAIR is a multiple of NTHR: a per-thread
+// branch around the store lets the compiler sink a load into it, right
+// before its use, which exposes that load's whole latency): threads read 16-byte row
 // pairs, consecutive threads walking down a column, and write them
 // transposed so that the matrix-core operand reads (16 consecutive j per
 // lane group) are conflict-free.  Columns at or beyond `nvalid` hold
@@ -185,7 +188,7 @@ struct StageK {
         for (int p = 0; p < PPT; ++p) {
             const int idx = threadIdx.x + NTHR * p;
             const int j = idx / (KC / 2), kk = 2 * (idx % (KC / 2));
-            const int jc = (idx < NPAIR && j < nvalid) ? j : 0;
+            const int jc = ((NPAIR % NTHR == 0 || idx < NPAIR) && j < nvalid) ? j : 0;
             load_run<2, GUARD>(r[p], base + kk + (size_t)jc * ld, kvalid - kk);
         }
     }
@@ -194,7 +197,7 @@ struct StageK {
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
             const int idx = threadIdx.x + NTHR * p;
-            if (idx < NPAIR) {
+            if (NPAIR % NTHR == 0 || idx < NPAIR) {   // decided at compile time when NPAIR divides
                 const int j = idx / (KC / 2), kk = 2 * (idx % (KC / 2));
                 buf[kk * P + j] = r[p][0];
                 buf[(kk + 1) * P + j] = r[p][1];
@@ -258,17 +261,28 @@ __device__ __forceinline__ void dts64_tile(const DevDesc &d, int i0)
                 for (int mm = 0; mm < RM; ++mm) acc[mm][jb] = mfma64(aa[s][mm], uu[jb][s], acc[mm][jb]);
     };
 
-    double a0[KG][RM], u0[RN][KG], a1[KG][RM], u1[RN][KG];
-    if (K > 0) load(0, a0, u0);
-    for (int k0 = 0; k0 < K;) {
-        if (k0 + KSTEP < K) load(k0 + KSTEP, a1, u1);
-        compute(a0, u0);
-        k0 += KSTEP;
-        if (k0 >= K) break;
-        if (k0 + KSTEP < K) load(k0 + KSTEP, a0, u0);
-        compute(a1, u1);
-        k0 += KSTEP;
+    // One chunk in flight while the previous one is multiplied.  Inside the
+    // loop the prefetch is unconditional and handed over by copy at the end
+    // of the step; the last chunk is peeled off.  A conditional prefetch, or
+    // a two-buffer loop with an exit between the halves, lets the compiler
+    // drain or sink the loads in front of the matrix-core work that should
+    // hide them.
+    double a[KG][RM], u[RN][KG];
+    if (K > 0) load(0, a, u);
+    for (int k0 = 0; k0 + KSTEP < K; k0 += KSTEP) {
+        double an[KG][RM], un[RN][KG];
+        load(k0 + KSTEP, an, un);
+        compute(a, u);
+        __builtin_amdgcn_sched_barrier(0);   // keep the hand-off behind the products
+#pragma unroll
+        for (int s = 0; s < KG; ++s) {
+#pragma unroll
+            for (int mm = 0; mm < RM; ++mm) a[s][mm] = an[s][mm];
+#pragma unroll
+            for (int nn = 0; nn < RN; ++nn) u[nn][s] = un[nn][s];
+        }
     }
+    if (K > 0) compute(a, u);
 
 #pragma unroll
     for (int jb = 0; jb < RN; ++jb) {
@@ -346,22 +360,25 @@ __device__ __forceinline__ void dtsl_tile(const DevDesc &d, int i0, double *lds)
         st.store(lds, P);
     }
     __syncthreads();
+    // The loop body is straight-line and the last chunk is peeled off: with
+    // the loads and stores inside `if (more)` the compiler's wait placement
+    // stalled each k step of a chunk on that chunk's own prefetch.
     int it = 0;
-    for (int k0 = 0; k0 < K; k0 += KC, ++it) {
-        const bool more = k0 + KC < K;
+    for (int k0 = 0; k0 + KC < K; k0 += KC, ++it) {
+        const int kn = k0 + KC;
         double an[KG][RM];
-        if (more) {
-            st.fetch(U + k0 + KC, ldu, K - (k0 + KC), N);
-            load_a(k0 + KC, an);
-        }
+        st.fetch(U + kn, ldu, K - kn, N);
+        load_a(kn, an);
         compute(lds + (it & 1) * BUF, a);
-        if (more) {
-            st.store(lds + ((it + 1) & 1) * BUF, P);
+        st.store(lds + ((it + 1) & 1) * BUF, P);
 #pragma unroll
-            for (int s = 0; s < KG; ++s)
+        for (int s = 0; s < KG; ++s)
 #pragma unroll
-                for (int mm = 0; mm < RM; ++mm) a[s][mm] = an[s][mm];
-        }
+            for (int mm = 0; mm < RM; ++mm) a[s][mm] = an[s][mm];
+        __syncthreads();
+    }
+    if (K > 0) {
+        compute(lds + (it & 1) * BUF, a);
         __syncthreads();
     }
 
@@ -433,18 +450,32 @@ __device__ __forceinline__ void inner_stream(const DevDesc &d, int row0, int col
                 for (int bj = 0; bj < RJ; ++bj) acc[bi][bj] = mfma64(aa[bi][s], uu[bj][s], acc[bi][bj]);
     };
 
+    // Two register buffers, chunks taken in pairs: every load in the loop is
+    // unconditional and no exit sits between a load and its use, so the
+    // compiler neither drains nor sinks the prefetch; the last one or two
+    // chunks are peeled off.  (With split k a wave sees only a few chunks,
+    // so a per-step register hand-off or a redundant last load shows.)
     double a0[RI][KG], u0[RJ][KG], a1[RI][KG], u1[RJ][KG];
-    int k0 = kb0;
-    if (k0 < K) load(k0, a0, u0);
+    if (kb0 < K) load(kb0, a0, u0);
     after_first();
-    while (k0 < K) {
-        if (k0 + kstride < K) load(k0 + kstride, a1, u1);
+    int k0 = kb0;
+    // The scheduling barriers keep each prefetch ahead of the products (and
+    // of the waits for their operands) that it is meant to overlap.
+    for (; k0 + 2 * kstride < K; k0 += 2 * kstride) {
+        load(k0 + kstride, a1, u1);
+        __builtin_amdgcn_sched_barrier(0);
         compute(a0, u0);
-        k0 += kstride;
-        if (k0 >= K) break;
-        if (k0 + kstride < K) load(k0 + kstride, a0, u0);
+        load(k0 + 2 * kstride, a0, u0);
+        __builtin_amdgcn_sched_barrier(0);
         compute(a1, u1);
-        k0 += kstride;
+    }
+    if (k0 + kstride < K) {
+        load(k0 + kstride, a1, u1);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(a0, u0);
+        compute(a1, u1);
+    } else if (k0 < K) {
+        compute(a0, u0);
     }
 }
 
@@ -579,18 +610,18 @@ __device__ __forceinline__ void inner_staged(const DevDesc &d, int i0, double *l
     }
     __syncthreads();
     int it = 0;
-    for (int k0 = 0; k0 < K; k0 += KC, ++it) {
-        const bool more = k0 + KC < K;
-        if (more) {
-            sv.fetch(V1t + k0 + KC, ldv, K - (k0 + KC), mvalid);
-            su.fetch(U2 + k0 + KC, ldu, K - (k0 + KC), N);
-        }
+    for (int k0 = 0; k0 + KC < K; k0 += KC, ++it) {   // loop shape as in dtsl_tile
+        const int kn = k0 + KC;
+        sv.fetch(V1t + kn, ldv, K - kn, mvalid);
+        su.fetch(U2 + kn, ldu, K - kn, N);
         compute(lds + (it & 1) * BUF);
-        if (more) {
-            double *nv = lds + ((it + 1) & 1) * BUF;
-            sv.store(nv, PV);
-            su.store(nv + KC * PV, PU);
-        }
+        double *nv = lds + ((it + 1) & 1) * BUF;
+        sv.store(nv, PV);
+        su.store(nv + KC * PV, PU);
+        __syncthreads();
+    }
+    if (K > 0) {
+        compute(lds + (it & 1) * BUF);
         __syncthreads();
     }
 }
@@ -716,7 +747,8 @@ __device__ __forceinline__ void rec64_tile(const DevDesc &d, int j0, double *lds
         }
         const bool has_next = nrg * RG < M;
         double un[RB][KG][2];
-        if (has_next) load_u(nrg * RG, nl0, un);
+        // unconditional prefetch (the last step re-reads its own chunk)
+        load_u(has_next ? nrg * RG : rg * RG, has_next ? nl0 : l0, un);
 #pragma unroll
         for (int s = 0; s < KG; ++s) {
             const int l = l0 + KG * g + s;
@@ -752,15 +784,13 @@ __device__ __forceinline__ void rec64_tile(const DevDesc &d, int j0, double *lds
         }
         rg = nrg;
         l0 = nl0;
-        if (has_next) {
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
+        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-                for (int s = 0; s < KG; ++s) {
-                    u[rb][s][0] = un[rb][s][0];
-                    u[rb][s][1] = un[rb][s][1];
-                }
-        }
+            for (int s = 0; s < KG; ++s) {
+                u[rb][s][0] = un[rb][s][0];
+                u[rb][s][1] = un[rb][s][1];
+            }
     }
     __syncthreads();   // P is reused by the next tile of a persistent workgroup
 }
@@ -902,13 +932,7 @@ __device__ __forceinline__ void inn3_tile(const DevDesc &d, int i0, double *lds)
 #pragma unroll
         for (int bj = 0; bj < RJ; ++bj) load8f<GUARD>(uu[bj], Up[bj] + kb, kv);
     };
-    int k0 = ks * 32;
-    if (PF && k0 < K) load(k0, a, u);
-    for (; k0 < K; k0 += KS * 32) {
-        float an[RI][8], un[RJ][8];
-        const bool more = PF && k0 + KS * 32 < K;
-        if (!PF) load(k0, a, u);
-        if (more) load(k0 + KS * 32, an, un);
+    auto compute = [&]() {
         Split3 sa[RI];
 #pragma unroll
         for (int bi = 0; bi < RI; ++bi) sa[bi] = split3(a[bi]);
@@ -918,7 +942,16 @@ __device__ __forceinline__ void inn3_tile(const DevDesc &d, int i0, double *lds)
 #pragma unroll
             for (int bi = 0; bi < RI; ++bi) mfma_x6(sa[bi], sb, acc[bi][bj]);
         }
-        if (more) {
+    };
+    constexpr int KSTEP = KS * 32;
+    const int kb0 = ks * 32;
+    if constexpr (PF) {   // loop shape as in dts64_tile: prefetch, last chunk peeled
+        if (kb0 < K) load(kb0, a, u);
+        for (int k0 = kb0; k0 + KSTEP < K; k0 += KSTEP) {
+            float an[RI][8], un[RJ][8];
+            load(k0 + KSTEP, an, un);
+            compute();
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
 #pragma unroll
@@ -926,6 +959,12 @@ __device__ __forceinline__ void inn3_tile(const DevDesc &d, int i0, double *lds)
 #pragma unroll
                 for (int bj = 0; bj < RJ; ++bj) u[bj][t] = un[bj][t];
             }
+        }
+        if (kb0 < K) compute();
+    } else {
+        for (int k0 = kb0; k0 < K; k0 += KSTEP) {
+            load(k0, a, u);
+            compute();
         }
     }
 
@@ -1042,12 +1081,7 @@ __device__ __forceinline__ void dts3_tile(const DevDesc &d, int i0)
 #pragma unroll
         for (int jb = 0; jb < RN; ++jb) load8f<GUARD>(uu[jb], Up[jb] + kb, kv);
     };
-    if (PF && K > 0) load(0, a, u);
-    for (int k0 = 0; k0 < K; k0 += 32) {
-        float an[RM][8], un[RN][8];
-        const bool more = PF && k0 + 32 < K;
-        if (!PF) load(k0, a, u);
-        if (more) load(k0 + 32, an, un);
+    auto compute = [&]() {
         Split3 sa[RM];
 #pragma unroll
         for (int mm = 0; mm < RM; ++mm) sa[mm] = split3(a[mm]);
@@ -1057,7 +1091,14 @@ __device__ __forceinline__ void dts3_tile(const DevDesc &d, int i0)
 #pragma unroll
             for (int mm = 0; mm < RM; ++mm) mfma_x6(sa[mm], sb, acc[mm][jb]);
         }
-        if (more) {
+    };
+    if constexpr (PF) {   // loop shape as in dts64_tile
+        if (K > 0) load(0, a, u);
+        for (int k0 = 0; k0 + 32 < K; k0 += 32) {
+            float an[RM][8], un[RN][8];
+            load(k0 + 32, an, un);
+            compute();
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
 #pragma unroll
@@ -1065,6 +1106,12 @@ __device__ __forceinline__ void dts3_tile(const DevDesc &d, int i0)
 #pragma unroll
                 for (int jb = 0; jb < RN; ++jb) u[jb][t] = un[jb][t];
             }
+        }
+        if (K > 0) compute();
+    } else {
+        for (int k0 = 0; k0 < K; k0 += 32) {
+            load(k0, a, u);
+            compute();
         }
     }
     // lane (c, g): MFMA row 4g + v of block mm is row wrow + RM (4g + v) + mm
