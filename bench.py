@@ -213,7 +213,10 @@ def run_lrmult_config(args):
     else:
         roof = {"bound": "hbm", "achieved": round(by / ms / 1e6, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(by / ms / 1e6 / PEAK_HBM_GBS, 4)}
-    roof.update({"traffic": None, "kernel": kernel, "algorithmic_flops": f, "algorithmic_bytes": by,
+    from paper_2311_07602_amd import profiling
+    prof = os.path.join(ROOT, "profiles", f"{kernel}.lrmult_b{b}_r{r}_{args.count}.md")
+    traffic = profiling.current_traffic(prof, profiling.LRMULT_SOURCES) if os.path.exists(prof) else None
+    roof.update({"traffic": traffic, "kernel": kernel, "algorithmic_flops": f, "algorithmic_bytes": by,
                  "roofline_ms": round(max(t_f, t_b) * 1e3, 4), "frac_of_roofline_time": round(max(t_f, t_b) * 1e3 / ms, 4)})
     return {"metric": METRIC, "value": round(f / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,

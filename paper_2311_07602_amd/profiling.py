@@ -138,11 +138,15 @@ def read_summary(path: str) -> Optional[dict]:
     return out or None
 
 
-def current_traffic(path: str) -> Optional[float]:
+# Sources behind the fused low-rank product kernels (their own translation unit).
+LRMULT_SOURCES = ["csrc/lrbg_lrmult.hip", "csrc/lrbg_tiles.h", "csrc/lrbg_internal.h", "tune/mi355x.tune"]
+
+
+def current_traffic(path: str, sources=None) -> Optional[float]:
     """Traffic per launch from a summary, or None once the kernel sources or
     tuning cache have changed since the counters were taken."""
     s = read_summary(path)
-    if not s or s.get("source_digest") != source_digest():
+    if not s or s.get("source_digest") != source_digest(sources):
         return None
     return float(s["traffic_bytes_per_launch"])
 
