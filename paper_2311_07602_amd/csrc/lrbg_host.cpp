@@ -215,6 +215,14 @@ static int default_variant(const lrbg_desc &d)
         return 0;
     };
     if (kind == K_DTS64) {
+        if (4 * d.k <= d.m) {
+            // short contraction (a basis update: b x r times r x k): a tile
+            // is little work, so take as many rows per tile as the
+            // registers allow
+            if (d.n <= 16) return pick({3, 1});
+            if (d.n <= 32) return pick({5, 4});
+            if (d.n <= 64) return pick({7, 6});
+        }
         if (d.n <= 16) return pick({1});
         if (d.n <= 32) return pick({4});
         if (d.n <= 64) return pick({d.m >= 512 ? 22 : 6});
