@@ -82,6 +82,7 @@ static std::string variant_name(int v)
     case K_DTS3: snprintf(buf, sizeof buf, "dts3_rm%d_rn%d_pf%d", vi.p1, vi.p2, vi.p3); break;
     case K_INN3: snprintf(buf, sizeof buf, "inn3_ri%d_rj%d_ks%d_pf%d", vi.p1, vi.p2, vi.p3, vi.p4); break;
     case K_DTSL: snprintf(buf, sizeof buf, "dtsl_rm%d_rn%d_kg%d", vi.p1, vi.p2, vi.p3); break;
+    case K_DTSS: snprintf(buf, sizeof buf, "dtss_rm%d_rn%d_kg%d", vi.p1, vi.p2, vi.p3); break;
     case K_INNL: snprintf(buf, sizeof buf, "innl_ri%d_rj%d_wr%d_kg%d", vi.p1, vi.p2, vi.p3, vi.p4); break;
     case K_LRM: snprintf(buf, sizeof buf, "lrm_ri%d_rj%d_ks%d_kg%d", vi.p1, vi.p2, vi.p3, vi.p4); break;
     case K_LRM4: snprintf(buf, sizeof buf, "lrm4_ri%d_rj%d_ks%d_kg%d", vi.p1, vi.p2, vi.p3, vi.p4); break;
@@ -110,7 +111,7 @@ static bool kind_matches(int kind, int op, int prec)
 {
     const int base = kind_of(op, prec);
     if (kind == base) return base != K_NOP;
-    if (prec == LRBG_FP64 && op == LRBG_OP_DENSE_TS) return kind == K_DTSL;
+    if (prec == LRBG_FP64 && op == LRBG_OP_DENSE_TS) return kind == K_DTSL || kind == K_DTSS;
     if (prec == LRBG_FP64 && op == LRBG_OP_INNER) return kind == K_INNL;
     if (prec == LRBG_FP64 && op == LRBG_OP_LRMULT) return kind == K_LRM4 || kind == K_LRMB;
     return false;
@@ -125,6 +126,7 @@ static bool variant_fits(int v, const lrbg_desc &d)
     switch (vi.kind) {
     case K_DTS64: return d.n <= 16 * vi.p2;
     case K_DTSL: return d.n <= 16 * vi.p2;
+    case K_DTSS: return d.n <= 16 * vi.p2 && d.k <= 64;
     case K_INNL: return d.n <= 16 * vi.p2 * (4 / vi.p3);
     case K_DTS3: return d.n <= 16 * vi.p2;
     case K_INN64: return d.n <= 16 * vi.p2;
@@ -147,7 +149,7 @@ static void tiles_of(int v, const lrbg_desc &d, std::vector<int32_t> &p0s, std::
     int step = 0, extent = 0, kc = 1;
     bool rows_full_needed = false;   // block-type rows must fill the tile
     switch (vi.kind) {
-    case K_DTS64: case K_DTSL:
+    case K_DTS64: case K_DTSL: case K_DTSS:
         step = 64 * vi.p1; extent = d.m; kc = 4 * vi.p3; rows_full_needed = true; break;
     case K_DTS3:
         step = 64 * vi.p1; extent = d.m; kc = 32; rows_full_needed = true; break;
@@ -218,10 +220,10 @@ static int default_variant(const lrbg_desc &d)
         if (4 * d.k <= d.m) {
             // short contraction (a basis update: b x r times r x k): a tile
             // is little work, so take as many rows per tile as the
-            // registers allow
-            if (d.n <= 16) return pick({3, 1});
-            if (d.n <= 32) return pick({5, 4});
-            if (d.n <= 64) return pick({7, 6});
+            // registers allow, and k per lane group to match the contraction
+            if (d.n <= 16) return d.k <= 8 ? pick({49, 3}) : d.k <= 16 ? pick({50, 3}) : pick({3, 1});
+            if (d.n <= 32) return d.k <= 32 ? pick({51, 5}) : pick({5, 4});
+            if (d.n <= 64) return d.k <= 32 ? pick({52, 7}) : pick({7, 6});
         }
         if (d.n <= 16) return pick({1});
         if (d.n <= 32) return pick({4});
@@ -750,6 +752,7 @@ static int family_of(int v)
     case K_LRM: return F_LRM;
     case K_LRM4: return F_LRM4;
     case K_LRMB: return F_LRMB;
+    case K_DTSS: return F_SHORT;
     default: return F_GROUPED;
     }
 }

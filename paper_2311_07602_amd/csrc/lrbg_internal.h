@@ -45,6 +45,7 @@ enum Kind : int32_t {
     K_LRM = 8,     // LRMULT, FP64, fused          params: RI, RJ, KS, KG (INNER phase)
     K_LRM4 = 9,    // as K_LRM in the high-occupancy fused kernel (32 KB LDS, <= 128 VGPRs)
     K_LRMB = 10,   // LRMULT, FP64, fused, ranks <= 128  params: RI, RJ, -, KG (8 waves, 128 KB LDS)
+    K_DTSS = 11,   // DENSE_TS, FP64, short contraction (k <= 64)  params: RM, RN, KG (no LDS)
 };
 
 // Kernel families: each family of variants is compiled into its own kernel
@@ -54,8 +55,9 @@ enum Family : int32_t {
     F_LRM = 1,       // lrbg_lrmult_kernel: 64 KB LDS, 2 workgroups per CU
     F_LRM4 = 2,      // lrbg_lrmult4_kernel: 32 KB LDS, 4 workgroups per CU
     F_LRMB = 3,      // lrbg_lrmultb_kernel: 8 waves, 128 KB LDS, 1 workgroup per CU
+    F_SHORT = 4,     // lrbg_short_kernel: no LDS, up to 4 workgroups per CU
 };
-constexpr int kFamilies = 4;
+constexpr int kFamilies = 5;
 constexpr int kLdsBytes4 = 32768;
 constexpr int kThreadsB = 512;
 constexpr int kLdsBytesB = 131072;
@@ -129,10 +131,18 @@ constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies
     X(47, K_LRMB, 2, 4, 0, 4)         \
     X(48, K_LRMB, 4, 2, 0, 2)
 
-#define LRBG_ALL_VARIANTS(X) \
-    LRBG_VARIANTS(X) LRBG_LRM_VARIANTS(X) LRBG_LRM4_VARIANTS(X) LRBG_LRMB_VARIANTS(X)
+// Dense products with a short contraction (the new bases of a recompressed
+// product, b x r times r x k): 1-4 k per lane group.
+#define LRBG_SHORT_VARIANTS(X)        \
+    X(49, K_DTSS, 4, 1, 2, 0)         \
+    X(50, K_DTSS, 2, 1, 4, 0)         \
+    X(51, K_DTSS, 2, 2, 2, 0)         \
+    X(52, K_DTSS, 2, 4, 1, 0)
 
-constexpr int kNumVariants = 49;   // ids 0..48 (0 = no-op tile)
+#define LRBG_ALL_VARIANTS(X) \
+    LRBG_VARIANTS(X) LRBG_LRM_VARIANTS(X) LRBG_LRM4_VARIANTS(X) LRBG_LRMB_VARIANTS(X) LRBG_SHORT_VARIANTS(X)
+
+constexpr int kNumVariants = 53;   // ids 0..52 (0 = no-op tile)
 
 struct VariantInfo {
     int32_t kind, p1, p2, p3, p4;
@@ -158,6 +168,7 @@ int launch_steered(const DevDesc *descs, const Tile *tiles, const int32_t *qinfo
 int cu_key_count();
 int launch_family(int family, const DevDesc *descs, const Tile *tiles, int ntiles, void *stream);
 int launch_lrm_family(int family, const DevDesc *descs, const Tile *tiles, int ntiles, void *stream);
+int launch_short_family(const DevDesc *descs, const Tile *tiles, int ntiles, void *stream);
 int persistent_blocks_per_cu();
 int launch_core_svd(int nmax, const SvdDesc *descs, int count, void *stream);
 int svd_max_dim();

@@ -141,6 +141,7 @@ int launch_family(int family, const DevDesc *descs, const Tile *tiles, int ntile
     if (ntiles <= 0) return 0;
     const dim3 grid(ntiles), block(kThreads);
     hipStream_t s = (hipStream_t)stream;
+    if (family == F_SHORT) return launch_short_family(descs, tiles, ntiles, stream);
     if (family != F_GROUPED) return launch_lrm_family(family, descs, tiles, ntiles, stream);
     hipLaunchKernelGGL(lrbg_grouped_kernel, grid, block, 0, s, descs, tiles, ntiles);
     return (int)hipGetLastError();

@@ -162,6 +162,22 @@ def test_lrmult_entry_validates_before_launch():
     assert st == lrbg.LRBG_EUNSUPPORTED
 
 
+def test_short_contraction_defaults():
+    # the new bases of a recompressed product (b x r times r x k) default to
+    # the short-contraction tiles; a square contraction keeps the long tiles
+    b = 1024
+    def pick(m, k, n, i):
+        return lrbg.lrbg_schedule_variants([mk(m=m, k=k, n=n, base=BASE * (i + 1))])[0]
+    assert pick(b, 8, 4, 0) == "dtss_rm4_rn1_kg2"
+    assert pick(b, 16, 8, 1) == "dtss_rm2_rn1_kg4"
+    assert pick(b, 32, 16, 2) == "dts64_rm4_rn1_kg8"
+    assert pick(b, 32, 32, 3) == "dtss_rm2_rn2_kg2"
+    assert pick(b, 64, 64, 4) == "dts64_rm2_rn4_kg4"
+    assert pick(b, 24, 64, 5) == "dtss_rm2_rn4_kg1"
+    assert not pick(b, b, 8, 6).startswith("dtss")
+    assert not pick(64, 64, 16, 7).startswith("dtss")
+
+
 def test_empty_and_zero_sizes():
     assert lrbg.lrbg_schedule_stats([])["products"] == 0
     st = lrbg.lrbg_schedule_stats([mk(m=0, lda=1, ldc=1, a=0, c=0), mk(n=0, b=0, c=0, base=BASE * 2)])

@@ -176,7 +176,18 @@ def _variant_params():
 
 @pytest.mark.parametrize("vid,name", _variant_params())
 def test_every_variant_forced(vid, name):
-    if name.startswith(("dts64", "dtsl")):
+    if name.startswith("dtss"):
+        # short contraction: one k chunk, a ragged one, several chunks
+        rn = int(name.split("_rn")[1].split("_")[0])
+        n = 16 * rn - 3
+        m = 300
+        for k in (8, 37, 64):
+            tune = cache_for(name, 0, 0, bucket(max(m, k), 64), bucket(n, 8))
+            C, Cref, _ = _dts_case(m, k, n, True, vid + k, lds_pad=(1, 2, 3), tune=tune)
+            assert np.array_equal(C, Cref)
+            C, Cref, D = _dts_case(m, k, n, False, vid + k, tune=tune)
+            assert oracle.normalized_error(C, Cref, D) <= TOL
+    elif name.startswith(("dts64", "dtsl")):
         rn = int(name.split("_rn")[1].split("_")[0])
         n = min(16 * rn, 128) - 3
         m = k = 300
