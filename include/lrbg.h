@@ -189,6 +189,35 @@ lrbg_status lr_batched_lrmult_round(int64_t count, const int32_t *b, const int32
                                     double *sigma, int32_t *kout, void *stream);
 
 /*
+ * lrbg_round_plan -- lr_batched_lrmult_round built once and replayed: the
+ * same arguments (without the stream), validated and scheduled at creation;
+ * the plan owns the scratch for G, X, Y, the schedules of the fused core
+ * and of the new bases, the SVD descriptors, and one captured hipGraph over
+ * the whole sequence.  The caller's buffers must stay valid (and at the
+ * same addresses) until the plan is destroyed; each execute recomputes U,
+ * V, sigma and kout from the current contents of the inputs.  Create
+ * allocates device memory and may block; execute only enqueues the graph on
+ * `stream`; destroy waits for the last execute to finish.  A plan is not
+ * thread-safe, and two executes of one plan must not overlap (they share
+ * the scratch).  Errors as lr_batched_lrmult_round; *out is NULL on error.
+ */
+typedef struct lrbg_round_plan lrbg_round_plan;
+lrbg_status lrbg_round_plan_create(lrbg_round_plan **out, int64_t count, const int32_t *b, const int32_t *ra,
+                                   const int32_t *rb,
+                                   const double *const *AU, const int32_t *ldau,
+                                   const double *const *AV, const int32_t *ldav,
+                                   const double *const *AX, const int32_t *ldax,
+                                   const double *const *BU, const int32_t *ldbu,
+                                   const double *const *BX, const int32_t *ldbx,
+                                   const double *const *BV, const int32_t *ldbv,
+                                   int32_t kmax, double tol,
+                                   double *const *U, const int32_t *ldu,
+                                   double *const *V, const int32_t *ldv,
+                                   double *sigma, int32_t *kout);
+lrbg_status lrbg_round_plan_execute(lrbg_round_plan *plan, void *stream);
+lrbg_status lrbg_round_plan_destroy(lrbg_round_plan *plan);
+
+/*
  * lrbg_grouped -- one launch sequence over `count` heterogeneous products
  * (any mix of ops, precisions, sizes).  Products whose input is exactly the
  * output buffer of another product of the same call (e.g. a RECOMP whose

@@ -1088,7 +1088,19 @@ struct RoundArgs {
     int32_t *kout;
 };
 
-static lrbg_status lrmult_round(const RoundArgs &a, hipStream_t stream)
+// The recompressed product's work, built once for a call or a plan: scratch
+// layout (G, X, Y per product), the fused-core and basis-update schedules,
+// and the SVD descriptors grouped by size class.
+struct RoundBuild {
+    size_t total = 0;                       // scratch bytes
+    std::vector<size_t> og, ox, oy;         // scratch offsets per product
+    Schedule s1, s2;                        // fused core; new bases
+    std::vector<SvdDesc> sv;                // by class 16, 32, 64
+    int ccount[3] = {0, 0, 0};
+};
+static const int kSvdClasses[3] = {16, 32, 64};
+
+static lrbg_status round_layout(const RoundArgs &a, RoundBuild &rb)
 {
     const int64_t n = a.count;
     if (n < 0) return fail(LRBG_EINVAL, "negative count");
@@ -1102,11 +1114,13 @@ static lrbg_status lrmult_round(const RoundArgs &a, hipStream_t stream)
         return fail(LRBG_EUNSUPPORTED, "kmax must be in [1, %d]", svd_max_dim());
     if (!(a.tol >= 0.0) || !std::isfinite(a.tol)) return fail(LRBG_EINVAL, "tol must be finite and >= 0");
     // scratch: G (ra x rb), X (ra x kmax), Y (rb x kmax) per product, 256-byte aligned
-    std::vector<size_t> og((size_t)n), ox((size_t)n), oy((size_t)n);
-    size_t total = 0;
+    rb.og.resize((size_t)n);
+    rb.ox.resize((size_t)n);
+    rb.oy.resize((size_t)n);
+    rb.total = 0;
     auto take = [&](size_t elems) {
-        const size_t o = total;
-        total += (elems * 8 + 255) / 256 * 256;
+        const size_t o = rb.total;
+        rb.total += (elems * 8 + 255) / 256 * 256;
         return o;
     };
     for (int64_t t = 0; t < n; ++t) {
@@ -1114,24 +1128,29 @@ static lrbg_status lrmult_round(const RoundArgs &a, hipStream_t stream)
             return fail(LRBG_EINVAL, "product %lld: negative size", (long long)t);
         if (a.ra[t] > svd_max_dim() || a.rb[t] > svd_max_dim())
             return fail(LRBG_EUNSUPPORTED, "product %lld: ranks above %d", (long long)t, svd_max_dim());
-        og[(size_t)t] = take((size_t)a.ra[t] * a.rb[t]);
-        ox[(size_t)t] = take((size_t)a.ra[t] * a.kmax);
-        oy[(size_t)t] = take((size_t)a.rb[t] * a.kmax);
+        rb.og[(size_t)t] = take((size_t)a.ra[t] * a.rb[t]);
+        rb.ox[(size_t)t] = take((size_t)a.ra[t] * a.kmax);
+        rb.oy[(size_t)t] = take((size_t)a.rb[t] * a.kmax);
     }
-    Staging *scr = acquire_staging(std::max<size_t>(total, 256), false);
-    if (!scr) return fail(LRBG_ENOMEM, "scratch allocation failed");
-    char *base = (char *)scr->dev;
+    rb.total = std::max<size_t>(rb.total, 256);
+    return LRBG_OK;
+}
+
+// Descriptors and schedules with the scratch at `base` (round_layout first).
+static lrbg_status round_build(const RoundArgs &a, char *base, RoundBuild &rb)
+{
+    const int64_t n = a.count;
     std::vector<lrbg_desc> d1((size_t)n), d2((size_t)(2 * n));
     std::vector<SvdDesc> sv((size_t)n);
     for (int64_t t = 0; t < n; ++t) {
-        const int ra = a.ra[t], rb = a.rb[t], bb = a.b[t], km = a.kmax;
-        double *G = (double *)(base + og[(size_t)t]), *X = (double *)(base + ox[(size_t)t]),
-               *Y = (double *)(base + oy[(size_t)t]);
+        const int ra = a.ra[t], rbk = a.rb[t], bb = a.b[t], km = a.kmax;
+        double *G = (double *)(base + rb.og[(size_t)t]), *X = (double *)(base + rb.ox[(size_t)t]),
+               *Y = (double *)(base + rb.oy[(size_t)t]);
         lrbg_desc &m = d1[(size_t)t];
         m.op = LRBG_OP_LRMULT;
         m.prec = LRBG_FP64;
         m.m = ra;
-        m.n = rb;
+        m.n = rbk;
         m.k = bb;
         m.a = a.AV[t];
         m.lda = a.ldav[t];
@@ -1157,69 +1176,83 @@ static lrbg_status lrmult_round(const RoundArgs &a, hipStream_t stream)
         u.ldc = a.ldu[t];
         u.lds = 1;
         v.m = bb;
-        v.k = rb;
+        v.k = rbk;
         v.n = km;
         v.a = a.BV[t];
         v.lda = a.ldbv[t];
         v.b = Y;
-        v.ldb = std::max(rb, 1);
+        v.ldb = std::max(rbk, 1);
         v.c = a.V[t];
         v.ldc = a.ldv[t];
         v.lds = 1;
-        SvdDesc &s = sv[(size_t)t];
-        s.g = G;
-        s.x = X;
-        s.y = Y;
-        s.sigma = a.sigma + t * km;
-        s.kout = a.kout + t;
-        s.tol = a.tol;
-        s.m = ra;
-        s.n = rb;
-        s.ldg = std::max(ra, 1);
-        s.ldx = std::max(ra, 1);
-        s.ldy = std::max(rb, 1);
-        s.kmax = km;
+        SvdDesc &sd = sv[(size_t)t];
+        sd.g = G;
+        sd.x = X;
+        sd.y = Y;
+        sd.sigma = a.sigma + t * km;
+        sd.kout = a.kout + t;
+        sd.tol = a.tol;
+        sd.m = ra;
+        sd.n = rbk;
+        sd.ldg = std::max(ra, 1);
+        sd.ldx = std::max(ra, 1);
+        sd.ldy = std::max(rbk, 1);
+        sd.kmax = km;
     }
     TuneTable tt;
     load_tune_cache(getenv("LRBG_TUNE_CACHE"), tt);
-    Schedule s1, s2;
-    lrbg_status st = build_schedule(d1.data(), n, tt, 0, nullptr, s1);
-    if (st == LRBG_OK) st = build_schedule(d2.data(), 2 * n, tt, 0, nullptr, s2);
-    Staging *sd = st == LRBG_OK ? acquire_staging(sv.size() * sizeof(SvdDesc)) : nullptr;
+    lrbg_status st = build_schedule(d1.data(), n, tt, 0, nullptr, rb.s1);
+    if (st == LRBG_OK) st = build_schedule(d2.data(), 2 * n, tt, 0, nullptr, rb.s2);
+    if (st != LRBG_OK) return st;
+    // group the cores by size class (one SVD launch per class)
+    rb.sv.clear();
+    rb.sv.reserve(sv.size());
+    for (int c = 0; c < 3; ++c) {
+        rb.ccount[c] = 0;
+        for (const SvdDesc &x : sv) {
+            const int dim = std::max(x.m, x.n);
+            const int cls = dim <= 16 ? 0 : dim <= 32 ? 1 : 2;
+            if (cls == c) {
+                rb.sv.push_back(x);
+                ++rb.ccount[c];
+            }
+        }
+    }
+    return LRBG_OK;
+}
+
+static lrbg_status round_svd_launches(const int (&ccount)[3], const SvdDesc *d_sv, hipStream_t stream)
+{
+    int off = 0;
+    for (int c = 0; c < 3; ++c) {
+        const int rc = launch_core_svd(kSvdClasses[c], d_sv + off, ccount[c], stream);
+        if (rc) return fail(LRBG_EDEVICE, "svd launch failed: %s", hipGetErrorString((hipError_t)rc));
+        off += ccount[c];
+    }
+    return LRBG_OK;
+}
+
+static lrbg_status lrmult_round(const RoundArgs &a, hipStream_t stream)
+{
+    RoundBuild rb;
+    lrbg_status st = round_layout(a, rb);
+    if (st != LRBG_OK || a.count == 0) return st;
+    Staging *scr = acquire_staging(rb.total, false);
+    if (!scr) return fail(LRBG_ENOMEM, "scratch allocation failed");
+    st = round_build(a, (char *)scr->dev, rb);
+    Staging *sd = st == LRBG_OK ? acquire_staging(rb.sv.size() * sizeof(SvdDesc)) : nullptr;
     if (st == LRBG_OK && !sd) st = fail(LRBG_ENOMEM, "staging allocation failed");
     if (st != LRBG_OK) {
         release_staging(scr);
         if (sd) release_staging(sd);
         return st;
     }
-    // group the cores by size class (one SVD launch per class)
-    const int classes[3] = {16, 32, 64};
-    std::vector<SvdDesc> byc;
-    byc.reserve(sv.size());
-    int ccount[3] = {0, 0, 0};
-    for (int c = 0; c < 3; ++c)
-        for (const SvdDesc &x : sv) {
-            const int dim = std::max(x.m, x.n);
-            const int cls = dim <= 16 ? 0 : dim <= 32 ? 1 : 2;
-            if (cls == c) {
-                byc.push_back(x);
-                ++ccount[c];
-            }
-        }
-    sv.swap(byc);
-    memcpy(sd->host, sv.data(), sv.size() * sizeof(SvdDesc));
-    hipError_t e = hipMemcpyAsync(sd->dev, sd->host, sv.size() * sizeof(SvdDesc), hipMemcpyHostToDevice, stream);
+    memcpy(sd->host, rb.sv.data(), rb.sv.size() * sizeof(SvdDesc));
+    hipError_t e = hipMemcpyAsync(sd->dev, sd->host, rb.sv.size() * sizeof(SvdDesc), hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) st = fail(LRBG_EDEVICE, "hipMemcpyAsync: %s", hipGetErrorString(e));
-    if (st == LRBG_OK) st = enqueue_once(s1, stream);
-    if (st == LRBG_OK) {
-        int off = 0;
-        for (int c = 0; c < 3 && st == LRBG_OK; ++c) {
-            const int rc = launch_core_svd(classes[c], (const SvdDesc *)sd->dev + off, ccount[c], stream);
-            if (rc) st = fail(LRBG_EDEVICE, "svd launch failed: %s", hipGetErrorString((hipError_t)rc));
-            off += ccount[c];
-        }
-    }
-    if (st == LRBG_OK) st = enqueue_once(s2, stream);
+    if (st == LRBG_OK) st = enqueue_once(rb.s1, stream);
+    if (st == LRBG_OK) st = round_svd_launches(rb.ccount, (const SvdDesc *)sd->dev, stream);
+    if (st == LRBG_OK) st = enqueue_once(rb.s2, stream);
     // scratch and descriptors are released once everything above has run
     if (record_release(scr, stream) != hipSuccess || record_release(sd, stream) != hipSuccess) {
         (void)hipStreamSynchronize(stream);
@@ -1230,6 +1263,20 @@ static lrbg_status lrmult_round(const RoundArgs &a, hipStream_t stream)
 }
 
 }  // namespace lrbg
+
+// A recompressed product built once: scratch, the two sub-plans (launched by
+// direct enqueue), the SVD descriptors, and one graph over all of it.
+struct lrbg_round_plan {
+    int64_t count = 0;
+    void *d_scratch = nullptr;
+    lrbg_plan *core = nullptr, *bases = nullptr;
+    lrbg::SvdDesc *d_svd = nullptr;
+    int ccount[3] = {0, 0, 0};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+    bool launched = false;
+};
 
 // =================================================================== C ABI
 
@@ -1312,6 +1359,95 @@ lrbg_status lr_batched_lrmult_round(int64_t count, const int32_t *b, const int32
     RoundArgs a{count, b, ra, rb, AU, AV, AX, BU, BX, BV, ldau, ldav, ldax, ldbu, ldbx, ldbv,
                 kmax, tol, U, V, ldu, ldv, sigma, kout};
     return lrmult_round(a, (hipStream_t)stream);
+}
+
+lrbg_status lrbg_round_plan_create(lrbg_round_plan **out, int64_t count, const int32_t *b, const int32_t *ra,
+                                   const int32_t *rb, const double *const *AU, const int32_t *ldau,
+                                   const double *const *AV, const int32_t *ldav, const double *const *AX,
+                                   const int32_t *ldax, const double *const *BU, const int32_t *ldbu,
+                                   const double *const *BX, const int32_t *ldbx, const double *const *BV,
+                                   const int32_t *ldbv, int32_t kmax, double tol, double *const *U,
+                                   const int32_t *ldu, double *const *V, const int32_t *ldv, double *sigma,
+                                   int32_t *kout)
+{
+    if (!out) return fail(LRBG_EINVAL, "out is NULL");
+    *out = nullptr;
+    RoundArgs a{count, b, ra, rb, AU, AV, AX, BU, BX, BV, ldau, ldav, ldax, ldbu, ldbx, ldbv,
+                kmax, tol, U, V, ldu, ldv, sigma, kout};
+    RoundBuild bld;
+    lrbg_status st = round_layout(a, bld);
+    if (st != LRBG_OK) return st;
+    lrbg_round_plan *p = new (std::nothrow) lrbg_round_plan();
+    if (!p) return fail(LRBG_ENOMEM, "plan allocation failed");
+    p->count = count;
+    auto cleanup = [&](lrbg_status e) {
+        lrbg_round_plan_destroy(p);
+        return e;
+    };
+    if (hipEventCreate(&p->done) != hipSuccess) return cleanup(fail(LRBG_EDEVICE, "event creation failed"));
+    if (count == 0) {
+        *out = p;
+        return LRBG_OK;
+    }
+    if (hipMalloc(&p->d_scratch, bld.total) != hipSuccess)
+        return cleanup(fail(LRBG_ENOMEM, "device allocation for the plan failed"));
+    st = round_build(a, (char *)p->d_scratch, bld);
+    if (st == LRBG_OK) st = plan_from_schedule(bld.s1, LRBG_PLAN_NO_GRAPH, &p->core);
+    if (st == LRBG_OK) st = plan_from_schedule(bld.s2, LRBG_PLAN_NO_GRAPH, &p->bases);
+    if (st != LRBG_OK) return cleanup(st);
+    const size_t nsv = bld.sv.size() * sizeof(SvdDesc);
+    if (hipMalloc(&p->d_svd, std::max<size_t>(nsv, 1)) != hipSuccess)
+        return cleanup(fail(LRBG_ENOMEM, "device allocation for the plan failed"));
+    if (hipMemcpy(p->d_svd, bld.sv.data(), nsv, hipMemcpyHostToDevice) != hipSuccess)
+        return cleanup(fail(LRBG_EDEVICE, "plan upload failed"));
+    for (int c = 0; c < 3; ++c) p->ccount[c] = bld.ccount[c];
+    hipStream_t cs;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+        return cleanup(fail(LRBG_EDEVICE, "capture stream creation failed"));
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        st = fail(LRBG_EDEVICE, "hipStreamBeginCapture failed");
+    if (st == LRBG_OK) {
+        st = enqueue_levels(p->core, cs);
+        if (st == LRBG_OK) st = round_svd_launches(p->ccount, p->d_svd, cs);
+        if (st == LRBG_OK) st = enqueue_levels(p->bases, cs);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(cs, &g);
+        if (st == LRBG_OK && e != hipSuccess) st = fail(LRBG_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        p->graph = g;
+    }
+    if (st == LRBG_OK && hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
+        st = fail(LRBG_EDEVICE, "hipGraphInstantiate failed");
+    (void)hipStreamDestroy(cs);
+    if (st != LRBG_OK) return cleanup(st);
+    *out = p;
+    return LRBG_OK;
+}
+
+lrbg_status lrbg_round_plan_execute(lrbg_round_plan *p, void *stream)
+{
+    if (!p) return fail(LRBG_EINVAL, "plan is NULL");
+    if (p->count == 0) return LRBG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipGraphLaunch(p->exec, s);
+    if (e != hipSuccess) return fail(LRBG_EDEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
+    if (hipEventRecord(p->done, s) != hipSuccess) return fail(LRBG_EDEVICE, "event record failed");
+    p->launched = true;
+    return LRBG_OK;
+}
+
+lrbg_status lrbg_round_plan_destroy(lrbg_round_plan *p)
+{
+    if (!p) return LRBG_OK;
+    if (p->launched && p->done) (void)hipEventSynchronize(p->done);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->core) lrbg_plan_destroy(p->core);
+    if (p->bases) lrbg_plan_destroy(p->bases);
+    if (p->d_svd) (void)hipFree(p->d_svd);
+    if (p->d_scratch) (void)hipFree(p->d_scratch);
+    if (p->done) (void)hipEventDestroy(p->done);
+    delete p;
+    return LRBG_OK;
 }
 
 lrbg_status lrbg_grouped(const lrbg_desc *descs, int64_t count, void *stream)

@@ -94,6 +94,12 @@ def load(path: Optional[str] = None):
     lib.lr_batched_lrmult.restype = ctypes.c_int
     lib.lr_batched_lrmult_round.argtypes = [i64] + [vp] * 15 + [i32, ctypes.c_double] + [vp] * 6 + [vp]
     lib.lr_batched_lrmult_round.restype = ctypes.c_int
+    lib.lrbg_round_plan_create.argtypes = [P(vp), i64] + [vp] * 15 + [i32, ctypes.c_double] + [vp] * 6
+    lib.lrbg_round_plan_create.restype = ctypes.c_int
+    lib.lrbg_round_plan_execute.argtypes = [vp, vp]
+    lib.lrbg_round_plan_execute.restype = ctypes.c_int
+    lib.lrbg_round_plan_destroy.argtypes = [vp]
+    lib.lrbg_round_plan_destroy.restype = ctypes.c_int
     lib.lrbg_grouped.argtypes = [P(lrbg_desc), i64, vp]
     lib.lrbg_grouped.restype = ctypes.c_int
     lib.lrbg_plan_create.argtypes = [P(vp), P(lrbg_desc), i64, ctypes.c_char_p, u32]
@@ -175,19 +181,59 @@ def lr_batched_lrmult(b: Sequence[int], ra: Sequence[int], rb: Sequence[int],
     return _check(st, "lr_batched_lrmult")
 
 
-def lr_batched_lrmult_round(b: Sequence[int], ra: Sequence[int], rb: Sequence[int],
-                            AU, ldau, AV, ldav, AX, ldax, BU, ldbu, BX, ldbx, BV, ldbv,
-                            kmax: int, tol: float, U, ldu, V, ldv, sigma: int, kout: int, stream=None) -> int:
-    """Pointer-array form of the recompressed low-rank product (see include/lrbg.h);
-    sigma and kout are device pointers."""
+def _round_arrays(b, ra, rb, AU, ldau, AV, ldav, AX, ldax, BU, ldbu, BX, ldbx, BV, ldbv, U, ldu, V, ldv):
     i32, vp = ctypes.c_int32, ctypes.c_void_p
     arrs = [_arr(i32, b), _arr(i32, ra), _arr(i32, rb), _arr(vp, AU), _arr(i32, ldau), _arr(vp, AV),
             _arr(i32, ldav), _arr(vp, AX), _arr(i32, ldax), _arr(vp, BU), _arr(i32, ldbu), _arr(vp, BX),
             _arr(i32, ldbx), _arr(vp, BV), _arr(i32, ldbv)]
     outs = [_arr(vp, U), _arr(i32, ldu), _arr(vp, V), _arr(i32, ldv)]
-    st = load().lr_batched_lrmult_round(len(b), *[ctypes.cast(x, vp) for x in arrs], int(kmax), float(tol),
-                                        *[ctypes.cast(x, vp) for x in outs], sigma, kout, _stream_ptr(stream))
+    return [ctypes.cast(x, vp) for x in arrs], [ctypes.cast(x, vp) for x in outs]
+
+
+def lr_batched_lrmult_round(b: Sequence[int], ra: Sequence[int], rb: Sequence[int],
+                            AU, ldau, AV, ldav, AX, ldax, BU, ldbu, BX, ldbx, BV, ldbv,
+                            kmax: int, tol: float, U, ldu, V, ldv, sigma: int, kout: int, stream=None) -> int:
+    """Pointer-array form of the recompressed low-rank product (see include/lrbg.h);
+    sigma and kout are device pointers."""
+    ins, outs = _round_arrays(b, ra, rb, AU, ldau, AV, ldav, AX, ldax, BU, ldbu, BX, ldbx, BV, ldbv, U, ldu, V, ldv)
+    st = load().lr_batched_lrmult_round(len(b), *ins, int(kmax), float(tol), *outs, sigma, kout,
+                                        _stream_ptr(stream))
     return _check(st, "lr_batched_lrmult_round")
+
+
+class RoundPlan:
+    """Owning wrapper of lrbg_round_plan: lr_batched_lrmult_round's arguments
+    (without the stream) scheduled once, replayed by execute()."""
+
+    def __init__(self, b, ra, rb, AU, ldau, AV, ldav, AX, ldax, BU, ldbu, BX, ldbx, BV, ldbv,
+                 kmax: int, tol: float, U, ldu, V, ldv, sigma: int, kout: int, keepalive: Iterable = ()):
+        self._keep = list(keepalive)
+        ins, outs = _round_arrays(b, ra, rb, AU, ldau, AV, ldav, AX, ldax, BU, ldbu, BX, ldbx, BV, ldbv,
+                                  U, ldu, V, ldv)
+        h = ctypes.c_void_p()
+        _check(load().lrbg_round_plan_create(ctypes.byref(h), len(b), *ins, int(kmax), float(tol), *outs,
+                                             sigma, kout), "lrbg_round_plan_create")
+        self.handle = h.value
+
+    def execute(self, stream=None):
+        _check(load().lrbg_round_plan_execute(self.handle, _stream_ptr(stream)), "lrbg_round_plan_execute")
+
+    def close(self):
+        if self.handle:
+            load().lrbg_round_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def lrbg_grouped(descs: Sequence[lrbg_desc], stream=None) -> int:

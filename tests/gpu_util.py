@@ -34,6 +34,13 @@ class DevMat:
             m.buf[1:x.shape[1] + 1, :x.shape[0]] = torch.from_numpy(np.ascontiguousarray(x.T)).to(m.buf.dtype).to(dev())
         return m
 
+    def copy_from(self, x):
+        """Overwrite the matrix in place (same shape) from a host array."""
+        import torch
+        assert x.shape == (self.rows, self.cols)
+        if x.size:
+            self.buf[1:self.cols + 1, :self.rows] = torch.from_numpy(np.ascontiguousarray(x.T)).to(self.buf.dtype).to(dev())
+
     def numpy(self):
         b = self.buf.cpu().numpy()
         return np.asfortranarray(b[1:self.cols + 1, :self.rows].T.astype(np.float64))
