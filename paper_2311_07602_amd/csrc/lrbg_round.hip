@@ -56,7 +56,8 @@ __device__ __forceinline__ double pair_sum(double x)
 // rotated columns to the slots their positions take next (the circle
 // method: position 0 stays, the column at position x >= 2 moves to x - 1 and
 // the one at 1 moves to N - 1).  Rows are placed so that the LPP lanes of
-// 32 / LPP consecutive slots cover distinct banks (no access conflicts):
+// 32 / LPP consecutive slots cover distinct banks (reads never conflict; a
+// write meets at most one other pair's lanes, at the wrap-around slot):
 // either row i of slot x sits at i ^ (LPP (x mod 32 / LPP)) in an unpadded
 // slot, or, where that would leave the slot, slots are padded to a stride
 // that is an odd multiple of LPP.  The rotation is symmetric in the two columns (with
