@@ -245,6 +245,10 @@ typedef struct lrbg_plan lrbg_plan;
                                       PERSISTENT) */
 #define LRBG_PLAN_SCHED_MIX  0x4u  /* interleave compute-bound and memory-bound
                                       tiles instead of longest-first order */
+#define LRBG_PLAN_UNTIMED    0x10u /* execute records no events (less host work
+                                      per replay; lrbg_plan_last_ms returns a
+                                      negative value, and destroy waits for the
+                                      whole device instead of the last replay) */
 
 typedef struct lrbg_plan_stats {
     int64_t products;     /* descriptors in the plan */
@@ -260,14 +264,17 @@ typedef struct lrbg_plan_stats {
  * (op, prec, b, r) bucket (from `tune_cache`, a file written by
  * lrbg_autotune, or built-in defaults when NULL or absent), build the
  * XCD-aware tile schedule, upload it to the device and capture the launch
- * sequence in a hipGraph.  The plan keeps the device pointers; the caller's
+ * sequence in a hipGraph (a plan whose work is one small launch, at most
+ * 4096 tiles, replays by a direct launch instead: a graph launch costs more
+ * than the kernel there).  The plan keeps the device pointers; the caller's
  * buffers must stay valid while the plan is executed.  On success *out owns
  * device memory until lrbg_plan_destroy.
  */
 lrbg_status lrbg_plan_create(lrbg_plan **out, const lrbg_desc *descs, int64_t count,
                              const char *tune_cache, uint32_t flags);
 
-/* Replay the plan on `stream` (hipGraphLaunch; no host work per tile). */
+/* Replay the plan on `stream` (hipGraphLaunch, or the direct launches of a
+ * small or LRBG_PLAN_NO_GRAPH plan; no host work per tile). */
 lrbg_status lrbg_plan_execute(lrbg_plan *plan, void *stream);
 
 /* Free the plan's device memory and graph.  Waits for the plan's work to

@@ -470,7 +470,9 @@ static bool compute_bound(const lrbg_desc &d)
 
 // ------------------------------------------------------------- plans
 
-constexpr uint32_t kPlanFlags = LRBG_PLAN_PERSISTENT | LRBG_PLAN_NO_GRAPH | LRBG_PLAN_SCHED_MIX | LRBG_PLAN_DUAL;
+constexpr uint32_t kPlanFlags =
+    LRBG_PLAN_PERSISTENT | LRBG_PLAN_NO_GRAPH | LRBG_PLAN_SCHED_MIX | LRBG_PLAN_DUAL | LRBG_PLAN_UNTIMED;
+constexpr int64_t kDirectLaunchTiles = 4096;   // a single launch this small is replayed directly
 
 struct Level {
     int64_t off[kFamilies] = {};   // per kernel family: first tile in the plan's tile array
@@ -494,6 +496,7 @@ struct lrbg_plan {
     hipGraphExec_t exec = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timed = false;
+    bool ran_untimed = false;     // LRBG_PLAN_UNTIMED: executed at least once
     lrbg_plan_stats stats{};
 };
 
@@ -921,7 +924,14 @@ static lrbg_status plan_from_schedule(Schedule &sch, uint32_t flags, lrbg_plan *
     }
     if (hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess)
         return cleanup(fail(LRBG_EDEVICE, "event creation failed"));
-    if (!(flags & LRBG_PLAN_NO_GRAPH)) {
+    // one small launch: a direct launch is cheaper than a graph launch
+    int launches = 0;
+    for (const Level &lv : p->levels)
+        for (int f = 0; f < kFamilies; ++f) launches += lv.n[f] > 0;
+    const bool direct = (flags & LRBG_PLAN_NO_GRAPH) ||
+                        (launches <= 1 && !(flags & (LRBG_PLAN_PERSISTENT | LRBG_PLAN_DUAL)) &&
+                         sch.stats.tiles <= kDirectLaunchTiles);
+    if (!direct) {
         hipStream_t cs;
         if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
             return cleanup(fail(LRBG_EDEVICE, "capture stream creation failed"));
@@ -1505,13 +1515,18 @@ lrbg_status lrbg_plan_execute(lrbg_plan *p, void *stream)
 {
     if (!p) return fail(LRBG_EINVAL, "plan is NULL");
     hipStream_t s = (hipStream_t)stream;
-    if (hipEventRecord(p->ev0, s) != hipSuccess) return fail(LRBG_EDEVICE, "event record failed");
+    const bool timing = !(p->flags & LRBG_PLAN_UNTIMED);
+    if (timing && hipEventRecord(p->ev0, s) != hipSuccess) return fail(LRBG_EDEVICE, "event record failed");
     lrbg_status st = LRBG_OK;
     if (p->exec) {
         hipError_t e = hipGraphLaunch(p->exec, s);
         if (e != hipSuccess) st = fail(LRBG_EDEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
     } else {
         st = enqueue_levels(p, s);
+    }
+    if (!timing) {
+        p->ran_untimed = true;
+        return st;
     }
     if (hipEventRecord(p->ev1, s) != hipSuccess) return fail(LRBG_EDEVICE, "event record failed");
     p->timed = st == LRBG_OK;
@@ -1531,6 +1546,7 @@ lrbg_status lrbg_plan_destroy(lrbg_plan *p)
 {
     if (!p) return LRBG_OK;
     if (p->timed && p->ev1) (void)hipEventSynchronize(p->ev1);
+    if (p->ran_untimed) (void)hipDeviceSynchronize();
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->ev0) (void)hipEventDestroy(p->ev0);

@@ -24,6 +24,7 @@ LRBG_OK, LRBG_EINVAL, LRBG_EUNSUPPORTED, LRBG_ENOMEM, LRBG_EDEVICE, LRBG_EBUDGET
 LRBG_OP_DENSE_TS, LRBG_OP_INNER, LRBG_OP_RECOMP, LRBG_OP_LRMULT = 0, 1, 2, 3
 LRBG_FP64, LRBG_BF16X3 = 0, 1
 LRBG_PLAN_PERSISTENT, LRBG_PLAN_NO_GRAPH, LRBG_PLAN_SCHED_MIX, LRBG_PLAN_DUAL = 0x1, 0x2, 0x4, 0x8
+LRBG_PLAN_UNTIMED = 0x10
 
 OPS = {"dense_ts": LRBG_OP_DENSE_TS, "inner": LRBG_OP_INNER, "recomp": LRBG_OP_RECOMP,
        "lrmult": LRBG_OP_LRMULT}

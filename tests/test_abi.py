@@ -162,6 +162,15 @@ def test_lrmult_entry_validates_before_launch():
     assert st == lrbg.LRBG_EUNSUPPORTED
 
 
+def test_plan_flags_validated():
+    d = [mk()]
+    for f in (0, lrbg.LRBG_PLAN_NO_GRAPH, lrbg.LRBG_PLAN_UNTIMED, lrbg.LRBG_PLAN_SCHED_MIX | lrbg.LRBG_PLAN_UNTIMED):
+        lrbg.lrbg_schedule_stats(d, flags=f)
+    with pytest.raises(lrbg.LrbgError) as e:
+        lrbg.lrbg_schedule_stats(d, flags=0x20)
+    assert e.value.status == lrbg.LRBG_EINVAL
+
+
 def test_short_contraction_defaults():
     # the new bases of a recompressed product (b x r times r x k) default to
     # the short-contraction tiles; a square contraction keeps the long tiles

@@ -292,7 +292,8 @@ def _check_cases(cases, outs, bitwise_to=None):
 
 @pytest.mark.parametrize("flags", [0, lrbg.LRBG_PLAN_NO_GRAPH, lrbg.LRBG_PLAN_SCHED_MIX,
                                    lrbg.LRBG_PLAN_PERSISTENT, lrbg.LRBG_PLAN_DUAL,
-                                   lrbg.LRBG_PLAN_DUAL | lrbg.LRBG_PLAN_NO_GRAPH])
+                                   lrbg.LRBG_PLAN_DUAL | lrbg.LRBG_PLAN_NO_GRAPH, lrbg.LRBG_PLAN_UNTIMED,
+                                   lrbg.LRBG_PLAN_UNTIMED | lrbg.LRBG_PLAN_SCHED_MIX])
 def test_grouped_mixed_plan(flags):
     cases = _mixed_batch(7)
     descs, outs, keep = _descs_for(cases)
@@ -305,6 +306,10 @@ def test_grouped_mixed_plan(flags):
         sync()
         _check_cases(cases, outs, bitwise_to=first)
         first = [o.numpy() for o in outs]
+        if flags & lrbg.LRBG_PLAN_UNTIMED:
+            assert p.last_ms() < 0
+        else:
+            assert p.last_ms() >= 0
     p.close()
 
 
