@@ -34,6 +34,7 @@ if ROOT not in sys.path:
 
 METRIC = "useful GFLOP/s + % of roofline on uneven batches; p50/p99 latency at fixed load"
 PROFILE = os.path.join(ROOT, "profiles", "lrbg_grouped_kernel.uneven_batch_20000.md")
+DEFAULT_TUNE = os.path.join(ROOT, "paper_2311_07602_amd", "tune", "mi355x.tune")
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 
@@ -169,9 +170,10 @@ def run_dense_uniform(steps=200, warmup=20, sets=16):
             "note": "launch-inclusive (one plan replay per step: a single small launch, issued directly)"}
 
 
-def run_chain(count=4096, b=512, r=32, steps=20, warmup=3, prec="fp64"):
+def run_chain(count=4096, b=512, r=32, steps=20, warmup=3, prec="fp64", tune_cache=None):
     """Low-rank x low-rank chain: T = V1^T U2 (level 1), W = U1 (T V2^T)
-    (level 2), both levels in one captured graph."""
+    (level 2), both levels in one captured graph, tile variants from the
+    tuning cache (the package's MI355X cache by default)."""
     import torch
     from paper_2311_07602_amd import lrbg, workloads
     stream = torch.cuda.current_stream()
@@ -179,7 +181,7 @@ def run_chain(count=4096, b=512, r=32, steps=20, warmup=3, prec="fp64"):
     w = workloads.chain(count, b, r, prec=prec)
     torch.cuda.synchronize()
     log(f"[bench] chain workload ({prec}) built in {time.perf_counter() - t0:.1f} s")
-    plan = lrbg.Plan(w.descs)
+    plan = lrbg.Plan(w.descs, tune_cache=tune_cache or DEFAULT_TUNE)
     st = plan.stats()
     ms, _ = time_plan(plan, steps, warmup, stream)
     plan.close()
@@ -462,7 +464,7 @@ def main():
     ap.add_argument("--count", type=int, default=20000)
     ap.add_argument("--lr-b", type=int, default=2048)
     ap.add_argument("--lr-r", type=int, default=32)
-    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2311_07602_amd", "tune", "mi355x.tune"))
+    ap.add_argument("--tune-cache", default=DEFAULT_TUNE)
     ap.add_argument("--persistent", action="store_true")
     ap.add_argument("--dual", action="store_true", help="dual-role persistent workgroups (one matrix-core-bound "
                     "and one memory-bound workgroup per CU)")
