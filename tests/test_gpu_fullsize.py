@@ -182,3 +182,42 @@ def test_round_at_scale_sampled():
         for j in range(ko):
             d = min(np.max(np.abs(Ut[:, j] - Uo[:, j])), np.max(np.abs(Ut[:, j] + Uo[:, j])))
             assert d <= 1e-8 * np.max(np.abs(Uo[:, j])), (t, j, d)
+
+
+@pytest.mark.parametrize("r", [8, 32])
+def test_round_plan_at_bench_scale_matches_one_shot(r):
+    """The plan form at the bench's size (20000 instances, b = 1024) gives
+    the one-shot call's outputs bit for bit (same kernels, same schedules)."""
+    import torch
+    from paper_2311_07602_amd import inputs
+    count, b, kmax, tol = 20000, 1024, r // 2, 1e-8
+    per = 4 * b * r + 2 * r * r
+    pin = inputs.device_normal(count * per, seed=90 + r)
+    outs = []
+    for _ in range(2):
+        U = torch.full((count, kmax, b), np.nan, dtype=torch.float64, device="cuda")
+        V = torch.full_like(U, np.nan)
+        sigma = torch.full((count * kmax,), np.nan, dtype=torch.float64, device="cuda")
+        kout = torch.full((count,), -1, dtype=torch.int32, device="cuda")
+        outs.append((U, V, sigma, kout))
+    base = pin.data_ptr()
+    off = lambda t, j: base + 8 * (t * per + j * b * r)
+    offs = lambda t, j: base + 8 * (t * per + 4 * b * r + j * r * r)
+    ts = range(count)
+    def args(o):
+        U, V, sigma, kout = o
+        return ([b] * count, [r] * count, [r] * count,
+                [off(t, 0) for t in ts], [b] * count, [off(t, 1) for t in ts], [b] * count,
+                [offs(t, 0) for t in ts], [r] * count, [off(t, 2) for t in ts], [b] * count,
+                [offs(t, 1) for t in ts], [r] * count, [off(t, 3) for t in ts], [b] * count,
+                kmax, tol, [U[t].data_ptr() for t in ts], [b] * count,
+                [V[t].data_ptr() for t in ts], [b] * count, sigma.data_ptr(), kout.data_ptr())
+    stream = torch.cuda.current_stream()
+    lrbg.lr_batched_lrmult_round(*args(outs[0]), stream=stream)
+    with lrbg.RoundPlan(*args(outs[1])) as plan:
+        plan.execute(stream)
+        plan.execute(stream)
+        torch.cuda.synchronize()
+    for x, y in zip(outs[0], outs[1]):
+        assert torch.equal(x, y)
+    assert int(outs[0][3].min()) == kmax
