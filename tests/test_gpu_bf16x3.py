@@ -173,8 +173,8 @@ def test_chain_bf16x3_inner_fp64_recomp():
 
 def test_error_table_every_bucket():
     """BF16x3 error against the FP64 oracle on the FP64 originals, for both
-    products on every (b, r) bucket of the uneven batch; written to
-    gpurun_out/bf16x3_error_table.txt when that folder exists."""
+    products on every (b, r) bucket of the uneven batch; printed, and written
+    to the file LRBG_ERROR_TABLE names when that variable is set."""
     import os
     rows = []
     for b in inputs.GROUPED_B:
@@ -193,8 +193,8 @@ def test_error_table_every_bucket():
                 e_i = max(e_i, oracle.normalized_error(dT.numpy(), Tref, Dt))
             rows.append((b, r, e_d, e_i))
     text = "b r dense_ts_err inner_err\n" + "\n".join(f"{b} {r} {d:.3e} {i:.3e}" for b, r, d, i in rows)
-    if os.path.isdir("gpurun_out"):
-        with open("gpurun_out/bf16x3_error_table.txt", "w") as f:
+    if os.environ.get("LRBG_ERROR_TABLE"):
+        with open(os.environ["LRBG_ERROR_TABLE"], "w") as f:
             f.write(text + "\n")
     print(text)
     assert max(max(d, i) for _, _, d, i in rows) <= TOL
