@@ -65,26 +65,36 @@ __device__ __forceinline__ double pair_sum(double x)
 // same), so which of the two is "p" does not matter.  Cores up to 32 wide
 // take one wave, whose reads of a step complete before its writes; wider
 // ones separate the two with a barrier.
-template <int NMAX, int LPP>
-__global__ void __launch_bounds__(NMAX / 2 * LPP)
+template <int NMAX, int LPP, int CPW>
+__global__ void __launch_bounds__(NMAX / 2 * LPP * CPW)
 lrbg_core_svd_kernel(const SvdDesc *__restrict__ descs, int count)
 {
-    constexpr int NT = NMAX / 2 * LPP, RPL = NMAX / LPP;
+    constexpr int NT = NMAX / 2 * LPP, RPL = NMAX / LPP;   // threads per core
+    static_assert(CPW == 1 || NT * CPW <= 64, "several cores per workgroup only within one wave");
     constexpr bool SWZ = 32 / LPP <= RPL;
     constexpr int LD = SWZ ? NMAX : NMAX + LPP;
     static_assert(NMAX % (2 * LPP) == 0, "a padded stride must be an odd multiple of LPP");
     // element (slot x, row i)
     auto at = [](int x, int i) { return x * LD + (SWZ ? (i ^ (LPP * (x & (32 / LPP - 1)))) : i); };
-    __shared__ double A[NMAX * LD];
-    __shared__ double V[NMAX * LD];
-    __shared__ double sig[NMAX];
-    __shared__ int32_t perm[NMAX];
-    __shared__ int32_t s_k;
-    const int t = blockIdx.x;
-    if (t >= count) return;
-    const SvdDesc d = descs[t];
+    __shared__ double A_[CPW][NMAX * LD];
+    __shared__ double V_[CPW][NMAX * LD];
+    __shared__ double sig_[CPW][NMAX];
+    __shared__ int32_t perm_[CPW][NMAX];
+    __shared__ int32_t s_k_[CPW];
+    // CPW cores per workgroup, NT threads each (a trailing workgroup may hold
+    // fewer live cores; every thread still takes part in the barriers)
+    const int cw = CPW == 1 ? 0 : (int)threadIdx.x / NT, tid = CPW == 1 ? (int)threadIdx.x : (int)threadIdx.x % NT;
+    const int t = blockIdx.x * CPW + cw;
+    const bool live = CPW == 1 || t < count;   // one core per workgroup: the grid is the count
+    double *A = A_[cw], *V = V_[cw], *sig = sig_[cw];
+    int32_t *perm = perm_[cw], &s_k = s_k_[cw];
+    SvdDesc d{};
+    if (CPW == 1)
+        d = descs[t];
+    else if (live)
+        d = descs[t];
     const bool tr = d.m < d.n;                     // work on G^T
-    const int m = tr ? d.n : d.m, n = tr ? d.m : d.n, tid = threadIdx.x;
+    const int m = tr ? d.n : d.m, n = tr ? d.m : d.n;
 
     // column p starts in slot p
     for (int e = tid; e < NMAX * NMAX; e += NT) {
@@ -102,7 +112,10 @@ lrbg_core_svd_kernel(const SvdDesc *__restrict__ descs, int count)
     const int na = sa == 0 ? 0 : (sa == 1 ? N - 1 : sa - 1);
     const int nb = sb == 0 ? 0 : (sb == 1 ? N - 1 : sb - 1);
     const bool active = pr < pairs;
-    for (int sweep = 0; sweep < kSvdSweeps && N >= 2; ++sweep) {
+    // uniform over the workgroup: with several cores the sweeps continue
+    // until none of them rotates (a converged or empty core just moves its
+    // columns)
+    for (int sweep = 0; sweep < kSvdSweeps && (CPW > 1 || N >= 2); ++sweep) {
         int rotated = 0;
         for (int step = 0; step < N - 1; ++step) {
             double x[RPL], y[RPL], vx[RPL], vy[RPL];
@@ -139,7 +152,7 @@ lrbg_core_svd_kernel(const SvdDesc *__restrict__ descs, int count)
                     rotated = 1;
                 }
             }
-            if constexpr (NT > 64) __syncthreads();   // every wave has read its slots
+            if constexpr (NT * CPW > 64) __syncthreads();   // every wave has read its slots
             if (active) {
 #pragma unroll
                 for (int j = 0; j < RPL; ++j) {
@@ -152,7 +165,7 @@ lrbg_core_svd_kernel(const SvdDesc *__restrict__ descs, int count)
             // One wave: its LDS accesses execute in issue order, so the next
             // step's reads see these writes; only the compiler must not
             // reorder them.  Several waves: a workgroup barrier.
-            if constexpr (NT == 64)
+            if constexpr (NT * CPW <= 64)
                 __builtin_amdgcn_wave_barrier();
             else
                 __syncthreads();
@@ -174,7 +187,7 @@ lrbg_core_svd_kernel(const SvdDesc *__restrict__ descs, int count)
         perm[rank] = tid;
     }
     __syncthreads();
-    if (tid == 0) {
+    if (tid == 0 && live) {
         const double smax = n > 0 ? sig[perm[0]] : 0.0;
         int k = 0;
         while (k < n && k < d.kmax && smax > 0.0 && sig[perm[k]] > d.tol * smax) ++k;
@@ -201,12 +214,12 @@ int launch_core_svd(int nmax, const SvdDesc *descs, int count, void *stream)
 {
     if (count <= 0) return 0;
     hipStream_t s = (hipStream_t)stream;
-    if (nmax == 16)
-        hipLaunchKernelGGL((lrbg_core_svd_kernel<16, 8>), dim3(count), dim3(64), 0, s, descs, count);
+    if (nmax == 16)   // two cores per wave, one per half
+        hipLaunchKernelGGL((lrbg_core_svd_kernel<16, 4, 2>), dim3((count + 1) / 2), dim3(64), 0, s, descs, count);
     else if (nmax == 32)
-        hipLaunchKernelGGL((lrbg_core_svd_kernel<32, 4>), dim3(count), dim3(64), 0, s, descs, count);
+        hipLaunchKernelGGL((lrbg_core_svd_kernel<32, 4, 1>), dim3(count), dim3(64), 0, s, descs, count);
     else if (nmax == 64)
-        hipLaunchKernelGGL((lrbg_core_svd_kernel<64, 8>), dim3(count), dim3(256), 0, s, descs, count);
+        hipLaunchKernelGGL((lrbg_core_svd_kernel<64, 8, 1>), dim3(count), dim3(256), 0, s, descs, count);
     else
         return (int)hipErrorInvalidValue;
     return (int)hipGetLastError();

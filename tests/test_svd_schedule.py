@@ -46,7 +46,7 @@ def slot_index(x, i, NMAX, LPP):
     return x * ld + ((i ^ (LPP * (x & (32 // LPP - 1)))) if swz else i), ld
 
 
-@pytest.mark.parametrize("NMAX,LPP", [(16, 8), (32, 4), (64, 8)])
+@pytest.mark.parametrize("NMAX,LPP", [(16, 4), (16, 8), (32, 4), (64, 8)])
 def test_slot_layout_in_bounds_and_conflict_free(NMAX, LPP):
     RPL = NMAX // LPP
     # a bijection of (slot, row) onto the slot's storage, inside the array
