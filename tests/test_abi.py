@@ -162,6 +162,35 @@ def test_lrmult_entry_validates_before_launch():
     assert st == lrbg.LRBG_EUNSUPPORTED
 
 
+def test_round_entries_validate_before_device_work():
+    """lr_batched_lrmult_round and lrbg_round_plan_create reject bad
+    arguments before any allocation or launch (so this runs without a GPU)."""
+    lib = lrbg.load()
+    i32 = lambda v: (ctypes.c_int32 * 1)(v)
+    p = lambda v: (ctypes.c_void_p * 1)(v)
+    b, r = 256, 16
+    def args(kmax=8, tol=1e-8, ra=r, sigma=BASE + (9 << 30), count=1):
+        return [count, i32(b), i32(ra), i32(r),
+                p(BASE), i32(b), p(BASE + (1 << 30)), i32(b), p(BASE + (2 << 30)), i32(ra),
+                p(BASE + (3 << 30)), i32(b), p(BASE + (4 << 30)), i32(r), p(BASE + (5 << 30)), i32(b),
+                kmax, tol, p(BASE + (6 << 30)), i32(b), p(BASE + (7 << 30)), i32(b), sigma, BASE + (10 << 30)]
+    cases = [(dict(kmax=0), lrbg.LRBG_EUNSUPPORTED), (dict(kmax=65), lrbg.LRBG_EUNSUPPORTED),
+             (dict(tol=-1.0), lrbg.LRBG_EINVAL), (dict(tol=float("nan")), lrbg.LRBG_EINVAL),
+             (dict(ra=65), lrbg.LRBG_EUNSUPPORTED), (dict(sigma=BASE + 4), lrbg.LRBG_EINVAL),
+             (dict(sigma=0), lrbg.LRBG_EINVAL), (dict(count=-1), lrbg.LRBG_EINVAL)]
+    for kw, code in cases:
+        a = args(**kw)
+        assert lib.lr_batched_lrmult_round(*a, None) == code, kw
+        h = ctypes.c_void_p(12345)
+        assert lib.lrbg_round_plan_create(ctypes.byref(h), *a) == code, kw
+        assert h.value is None                                 # *out cleared on error
+    a = args(); a[1] = None                                    # NULL host array
+    assert lib.lr_batched_lrmult_round(*a, None) == lrbg.LRBG_EINVAL
+    assert lib.lr_batched_lrmult_round(0, *([None] * 15), 4, 0.0, *([None] * 6), None) == 0
+    assert lib.lrbg_round_plan_execute(None, None) == lrbg.LRBG_EINVAL
+    assert lib.lrbg_round_plan_destroy(None) == 0
+
+
 def test_plan_flags_validated():
     d = [mk()]
     for f in (0, lrbg.LRBG_PLAN_NO_GRAPH, lrbg.LRBG_PLAN_UNTIMED, lrbg.LRBG_PLAN_SCHED_MIX | lrbg.LRBG_PLAN_UNTIMED):
