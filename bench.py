@@ -400,13 +400,13 @@ def run_blr(nbs=(32, 64, 128), b=512, r=8, nrhs=8, steps=20, warmup=3):
     size (INNER products into the stacked right-hand sides, then one
     DENSE_TS per block row over [A_ii | U_i])."""
     import torch
-    from paper_2311_07602_amd import workloads
+    from paper_2311_07602_amd import lrbg, workloads
     stream = torch.cuda.current_stream()
     out = []
     for nb in nbs:
         m = workloads.blr(nb, b, r, nrhs)
         f, by = m.work()
-        plan = m.plan()
+        plan = m.plan(flags=lrbg.LRBG_PLAN_UNTIMED)
         ms, _ = time_plan(plan, steps, warmup, stream)
         m.close()
         del m

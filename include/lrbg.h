@@ -264,9 +264,9 @@ typedef struct lrbg_plan_stats {
  * (op, prec, b, r) bucket (from `tune_cache`, a file written by
  * lrbg_autotune, or built-in defaults when NULL or absent), build the
  * XCD-aware tile schedule, upload it to the device and capture the launch
- * sequence in a hipGraph (a plan whose work is one small launch, at most
- * 4096 tiles, replays by a direct launch instead: a graph launch costs more
- * than the kernel there).  The plan keeps the device pointers; the caller's
+ * sequence in a hipGraph (a plan whose work is one or two small launches,
+ * at most 4096 tiles, replays by direct launches instead: a graph launch
+ * costs more than the kernels there).  The plan keeps the device pointers; the caller's
  * buffers must stay valid while the plan is executed.  On success *out owns
  * device memory until lrbg_plan_destroy.
  */

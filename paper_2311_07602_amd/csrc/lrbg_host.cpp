@@ -472,7 +472,7 @@ static bool compute_bound(const lrbg_desc &d)
 
 constexpr uint32_t kPlanFlags =
     LRBG_PLAN_PERSISTENT | LRBG_PLAN_NO_GRAPH | LRBG_PLAN_SCHED_MIX | LRBG_PLAN_DUAL | LRBG_PLAN_UNTIMED;
-constexpr int64_t kDirectLaunchTiles = 4096;   // a single launch this small is replayed directly
+constexpr int64_t kDirectLaunchTiles = 4096;   // plans this small (one or two launches) replay directly
 
 struct Level {
     int64_t off[kFamilies] = {};   // per kernel family: first tile in the plan's tile array
@@ -924,12 +924,14 @@ static lrbg_status plan_from_schedule(Schedule &sch, uint32_t flags, lrbg_plan *
     }
     if (hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess)
         return cleanup(fail(LRBG_EDEVICE, "event creation failed"));
-    // one small launch: a direct launch is cheaper than a graph launch
+    // one or two small launches: direct launches are cheaper than a graph
+    // launch (measured: 26 -> 19 us for one launch of 256 tiles, 56 -> 49 us
+    // for two dependent launches of ~1100 tiles)
     int launches = 0;
     for (const Level &lv : p->levels)
         for (int f = 0; f < kFamilies; ++f) launches += lv.n[f] > 0;
     const bool direct = (flags & LRBG_PLAN_NO_GRAPH) ||
-                        (launches <= 1 && !(flags & (LRBG_PLAN_PERSISTENT | LRBG_PLAN_DUAL)) &&
+                        (launches <= 2 && !(flags & (LRBG_PLAN_PERSISTENT | LRBG_PLAN_DUAL)) &&
                          sch.stats.tiles <= kDirectLaunchTiles);
     if (!direct) {
         hipStream_t cs;
