@@ -59,33 +59,98 @@ def time_plan(plan, steps, warmup, stream):
     return total / steps, per
 
 
-def cpu_baseline_grouped(w, seconds_budget=30.0, per_bucket=40):
-    """Oracle on a stratified sample: the first `per_bucket` instances of every
-    (b, r) bucket, both products, all host threads."""
-    import numpy as np
+def cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def host_threads() -> int:
+    """Threads the oracle may use: the process's CPU affinity, capped by the
+    OpenMP limit the environment sets."""
+    import oracle
+    return max(1, min(len(os.sched_getaffinity(0)), oracle.max_threads()))
+
+
+def _timed(fn):
+    t0 = time.perf_counter()
+    fn()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline_grouped(w, per_bucket=40, per_bucket_1t=2):
+    """Oracle on stratified samples of the uneven batch: the first
+    `per_bucket` instances of every (b, r) bucket on all host threads, the
+    first `per_bucket_1t` on one thread; both products."""
     import oracle
     from paper_2311_07602_amd import workloads
     shapes = w.meta["shapes"]
-    chosen, seen = [], {}
-    for i, br in enumerate(shapes):
-        if seen.get(br, 0) < per_bucket:
-            seen[br] = seen.get(br, 0) + 1
-            chosen.append(i)
-    As, Us, Vs, U2s = [], [], [], []
-    flops = 0.0
-    for i in chosen:
-        o = workloads.grouped_operands(w, i)
-        As.append(o["A"]); Us.append(o["U"]); Vs.append(o["V1"]); U2s.append(o["U2"])
-        b, r = shapes[i]
-        flops += 2.0 * b * b * r + 2.0 * b * r * r
-    nthreads = oracle.max_threads()
-    t0 = time.perf_counter()
-    oracle.dense_ts(As, Us, nthreads=nthreads)
-    oracle.inner(Vs, U2s, nthreads=nthreads)
-    dt = time.perf_counter() - t0
+
+    def sample(k):
+        chosen, seen = [], {}
+        for i, br in enumerate(shapes):
+            if seen.get(br, 0) < k:
+                seen[br] = seen.get(br, 0) + 1
+                chosen.append(i)
+        ops = [workloads.grouped_operands(w, i) for i in chosen]
+        flops = sum(2.0 * b * b * r + 2.0 * b * r * r for b, r in (shapes[i] for i in chosen))
+        return chosen, len(seen), ops, flops
+
+    nthreads = host_threads()
+    chosen, nb, ops, flops = sample(per_bucket)
+    dt = _timed(lambda: (oracle.dense_ts([o["A"] for o in ops], [o["U"] for o in ops], nthreads=nthreads),
+                         oracle.inner([o["V1"] for o in ops], [o["U2"] for o in ops], nthreads=nthreads)))
+    chosen1, _, ops1, flops1 = sample(per_bucket_1t)
+    dt1 = _timed(lambda: (oracle.dense_ts([o["A"] for o in ops1], [o["U"] for o in ops1], nthreads=1),
+                          oracle.inner([o["V1"] for o in ops1], [o["U2"] for o in ops1], nthreads=1)))
     return {"value": round(flops / dt / 1e9, 3), "unit": "GFLOP/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"first {per_bucket} instances of each of the {len(seen)} (b,r) buckets "
-                      f"({len(chosen)} instances, both products, {flops / 1e9:.2f} GFLOP) in {dt:.1f} s"}
+            "sample": f"first {per_bucket} instances of each of the {nb} (b,r) buckets "
+                      f"({len(chosen)} instances, both products, {flops / 1e9:.2f} GFLOP) in {dt:.1f} s "
+                      f"on {nthreads} threads",
+            "cpu_model": cpu_model(),
+            "one_thread": {"value": round(flops1 / dt1 / 1e9, 3), "unit": "GFLOP/s", "cores": 1,
+                           "sample": f"first {per_bucket_1t} instances of each bucket ({len(chosen1)} instances, "
+                                     f"{flops1 / 1e9:.2f} GFLOP) in {dt1:.1f} s"}}
+
+
+def cpu_baseline_small_configs(chain_1t_instances=256):
+    """The oracle on the uniform dense batch (64 x 256x256 . 256x16, in full,
+    one thread and all threads) and on the chain (4096 x b=512, r=32, in full
+    on all threads; its first `chain_1t_instances` instances on one thread),
+    with the same flop counts as the GPU lines."""
+    import numpy as np
+    import oracle
+    from paper_2311_07602_amd import inputs
+    nthreads = host_threads()
+    out = {}
+    As, Us = zip(*(inputs.dense_ts_instance(1, i, 256, 16) for i in range(64)))
+    f1 = 64 * 2.0 * 256 * 256 * 16
+    t_all = min(_timed(lambda: oracle.dense_ts(list(As), list(Us), nthreads=nthreads)) for _ in range(3))
+    t_one = min(_timed(lambda: oracle.dense_ts(list(As), list(Us), nthreads=1)) for _ in range(2))
+    out["dense_uniform"] = {"workload": "64 x (A 256x256 . U 256x16), in full",
+                            "all_threads": {"GFLOP/s": round(f1 / t_all / 1e9, 3), "cores": nthreads,
+                                            "ms": round(t_all * 1e3, 2)},
+                            "one_thread": {"GFLOP/s": round(f1 / t_one / 1e9, 3), "cores": 1,
+                                           "ms": round(t_one * 1e3, 2)}}
+    count, b, r = 4096, 512, 32
+    host = inputs.chain_instances(2, count, b, r)
+    ops = [[np.asfortranarray(host[i, t].T) for i in range(count)] for t in range(4)]   # U1, V1, U2, V2
+    fch = count * (2.0 * b * r * r + 2.0 * b * b * r + 2.0 * b * r * r)
+    t_all = _timed(lambda: oracle.chain(ops[1], ops[2], ops[0], ops[3], nthreads=nthreads))
+    n1 = chain_1t_instances
+    t_one = _timed(lambda: oracle.chain(ops[1][:n1], ops[2][:n1], ops[0][:n1], ops[3][:n1], nthreads=1))
+    out["chain"] = {"workload": f"{count} x chain b={b} r={r} (T = V1^T U2, W = U1 (T V2^T))",
+                    "all_threads": {"GFLOP/s": round(fch / t_all / 1e9, 3), "cores": nthreads,
+                                    "s": round(t_all, 2), "sample": "in full"},
+                    "one_thread": {"GFLOP/s": round(fch / count * n1 / t_one / 1e9, 3), "cores": 1,
+                                   "s": round(t_one, 2), "sample": f"first {n1} instances"}}
+    del host, ops
+    return out
 
 
 def run_grouped(args):
@@ -138,6 +203,9 @@ def run_grouped(args):
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample ...")
         line["cpu_baseline"] = cpu_baseline_grouped(w)
+        if not args.no_extras:
+            log("[bench] timing the CPU oracle on the uniform dense batch and the chain ...")
+            line["cpu_baseline"]["configs"] = cpu_baseline_small_configs()
     return line
 
 
@@ -419,27 +487,40 @@ def run_blr(nbs=(32, 64, 128), b=512, r=8, nrhs=8, steps=20, warmup=3):
                         f"{nrhs} columns, FP64, N(0,1) blocks", "bound": "hbm", "sizes": out}
 
 
-def run_serving(budget=64e9, slots=8, sat_requests=300, warm=200, measured=1000, rho=0.7):
-    """Continuous-batching loop: saturated request rate first (all requests
-    queued at t=0), then Poisson arrivals at rho x that rate; latency is
-    arrival -> completion, over the requests after the warm-up ones."""
+def run_serving(budget=64e9, slots=8, sat_requests=400, warm=200, measured=2000, rhos=(0.5, 0.7, 0.9),
+                per_bucket=128, grouped_gflops=None):
+    """Continuous-batching loop over a device-resident operand pool: the
+    saturated request rate first (all requests queued at t=0), then Poisson
+    arrivals at rho x that rate for each rho; latency is arrival ->
+    completion, over the `measured` requests after `warm` warm-up ones."""
     import torch
     from paper_2311_07602_amd import serve
-    ex = serve.GpuExecutor(slots=slots)
-    serve.Scheduler(ex, budget, slots).run(serve.make_requests(30, float("inf"), seed=100))   # warm-up
+    t0 = time.perf_counter()
+    pool = serve.ResidentPool(per_bucket=per_bucket)
+    torch.cuda.synchronize()
+    log(f"[bench] serving pool: {pool.nbytes / 1e9:.1f} GB resident in {time.perf_counter() - t0:.1f} s")
+    ex = serve.GpuExecutor(pool, slots=slots)
+    serve.Scheduler(ex, budget, slots).run(serve.make_requests(50, float("inf"), seed=100))   # warm-up
     torch.cuda.synchronize()
     sat = serve.summarize(serve.Scheduler(ex, budget, slots).run(
         serve.make_requests(sat_requests, float("inf"), seed=101)))
+    if grouped_gflops:
+        sat["of_grouped_kernel_rate"] = round(sat["GFLOP/s"] / grouped_gflops, 3)
     mu = sat["requests_per_s"]
-    reqs = serve.make_requests(warm + measured, rho * mu, seed=102)
-    sch = serve.Scheduler(ex, budget, slots)
-    recs = sch.run(reqs)
-    load = serve.summarize(recs, skip=warm)
+    loads = []
+    for j, rho in enumerate(rhos):
+        reqs = serve.make_requests(warm + measured, rho * mu, seed=102 + j)
+        sch = serve.Scheduler(ex, budget, slots)
+        recs = sch.run(reqs)
+        loads.append({"rho": rho, "rate_per_s": round(rho * mu, 2), "warmup_requests": warm,
+                      **serve.summarize(recs, skip=warm), "max_resident_GB": round(sch.max_resident / 1e9, 2)})
+        log(f"[bench] serving rho={rho}: {loads[-1]}")
+    del ex, pool
+    torch.cuda.empty_cache()
     return {"workload": "Poisson arrivals, requests of 16..2048 instances (A.U and V1^T.U2 each, (b,r) as the "
-                        "uneven batch), FP64 or BF16x3 with p=0.5, operands device-resident, HBM budget "
-                        f"{budget / 1e9:.0f} GB, {slots} streams",
-            "saturated": sat, "offered_load": {"rho": rho, "rate_per_s": round(rho * mu, 2), **load},
-            "max_resident_GB": round(sch.max_resident / 1e9, 2)}
+                        "uneven batch), FP64 or BF16x3 with p=0.5, operands from a device-resident pool of "
+                        f"{per_bucket} blocks per (b,r) bucket, HBM budget {budget / 1e9:.0f} GB, {slots} streams",
+            "saturated": sat, "offered_load": loads}
 
 
 def calibrate_copy(nbytes=1 << 30, reps=5):
@@ -496,10 +577,10 @@ def main():
         log("[bench] extra workloads ...")
         line["extra"] = {"dense_uniform": run_dense_uniform(), "chain_fp64": run_chain(),
                          "chain_bf16x3": run_chain(prec="bf16x3")}
-        # the serving loop allocates per request: run it before the large workloads below
-        # so that the allocator's cache, not fresh device allocations, serves its requests
+        # the serving loop allocates each request's outputs: run it before the large workloads
+        # below so that the allocator's cache, not fresh device allocations, serves them
         log("[bench] serving ...")
-        line["extra"]["serving"] = run_serving()
+        line["extra"]["serving"] = run_serving(grouped_gflops=line["value"])
         log("[bench] vendor batched DGEMM on the uneven batch ...")
         wv = None
         try:

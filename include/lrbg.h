@@ -26,7 +26,7 @@
  *                     E_temp = A_X C_temp, G_XY = E_temp B_X), evaluated in
  *                     that order with the rank-sized intermediates kept on
  *                     chip (the fusion of Alg. 2); k = b, m = rank_A,
- *                     n = rank_B; FP64; m, n <= 64.
+ *                     n = rank_B; FP64; m, n <= 128.
  *
  * Conventions for every entry point:
  *   - All matrices are column-major: element (i, j) of X is at
@@ -41,9 +41,11 @@
  *     six term pairs of order <= 2 on the bf16 matrix cores with FP32
  *     accumulation and returns the output in FP64 (double *).  RECOMP is
  *     FP64 only (LRBG_EUNSUPPORTED otherwise).
- *   - Limits: rank-type dimensions (DENSE_TS n; INNER m, n; RECOMP k) at
- *     most 128 (LRMULT m, n at most 64); block-type dimensions at most
- *     65536; violating either is LRBG_EUNSUPPORTED.
+ *   - Limits: rank-type dimensions (DENSE_TS n; INNER m, n; RECOMP k;
+ *     LRMULT m, n) at most 128, except the ranks and kmax of
+ *     lr_batched_lrmult_round (at most 64, the largest core its batched SVD
+ *     takes); block-type dimensions at most 65536; violating either is
+ *     LRBG_EUNSUPPORTED.
  *   - Pointers named "device" are device (HBM) addresses on the current HIP
  *     device, naturally aligned (8 bytes for FP64, 4 for FP32).  Host arrays
  *     (sizes, leading dimensions, pointer arrays, descriptor arrays) are read
@@ -135,7 +137,7 @@ lrbg_status lr_batched_gemm(int32_t op, int32_t prec, int64_t count,
  * lr_batched_lrmult -- `count` low-rank products G_i = X_A,i (V_A,i^T U_B,i)
  * X_B,i, the paper's batched Alg. 1 (Alg. 2's operand arrays), FP64.
  *   b             : host array [count]: the shared inner (block) dimension.
- *   ra, rb        : host arrays [count]: ranks of the two operands (<= 64).
+ *   ra, rb        : host arrays [count]: ranks of the two operands (<= 128).
  *   AV, ldav      : device V_A, b x ra (the stored A_{V^T} transposed).
  *   BU, ldbu      : device U_B, b x rb.
  *   AX, ldax      : device X_A, ra x ra.

@@ -106,42 +106,48 @@ def chain_instance(cfg: int, i: int, b: int, r: int) -> ChainInstance:
     return ChainInstance(U1, V1, U2, V2)
 
 
-def _one_blas_thread():
-    try:
-        from threadpoolctl import threadpool_limits
-        threadpool_limits(1)
-    except ImportError:
-        pass
-
-
-def _chain_block(args):
-    cfg, lo, hi, b, r = args
-    out = np.empty((hi - lo, 4, r, b))
+def _chain_chunk(cfg: int, lo: int, hi: int, b: int, r: int, scale: np.ndarray, out: np.ndarray) -> None:
+    g = np.empty((hi - lo, 4, b, r))
     for i in range(lo, hi):
-        ci = chain_instance(cfg, i, b, r)
-        for t, x in enumerate((ci.U1, ci.V1, ci.U2, ci.V2)):
-            out[i - lo, t] = x.T
-    return lo, out
+        rng = instance_rng(cfg, i)
+        for t in range(4):
+            g[i - lo, t] = normal_f(rng, b, r)
+    q, rr = np.linalg.qr(g, mode="reduced")                      # [n, 4, b, r], [n, 4, r, r]
+    s = np.sign(np.diagonal(rr, axis1=-2, axis2=-1)).copy()     # [n, 4, r]
+    s[s == 0] = 1.0
+    q = q * s[..., None, :]
+    q = q * scale[None, :, None, :]
+    out[lo:hi] = np.swapaxes(q, -1, -2)
 
 
-def chain_instances(cfg: int, count: int, b: int, r: int, workers: int = 8) -> np.ndarray:
+def chain_instances(cfg: int, count: int, b: int, r: int, chunk: int = 64, threads: int = 8) -> np.ndarray:
     """[count, 4, r, b] array: instance i's U1, V1, U2, V2, each stored
     column-major (row j of the last two axes is column j of the operand).
-    Generated in worker processes (spawned, so no device state is inherited);
-    every instance comes from its own seed, so the result does not depend on
-    the number of workers."""
+
+    Generated in this process: each instance draws its four N(0,1) matrices
+    from its own seed in the order of :func:`chain_instance`, then one
+    stacked reduced QR per chunk of instances orthonormalises them, with the
+    same column-sign fix (diag(R) > 0) and the same scalings folded into V,
+    so the values are those of :func:`chain_instance` instance by instance.
+    Chunks run on a few threads of this process (each QR on one BLAS
+    thread); no worker process is started."""
+    from concurrent.futures import ThreadPoolExecutor
     out = np.empty((count, 4, r, b))
-    step = max(1, min(256, (count + workers - 1) // max(workers, 1)))
-    jobs = [(cfg, lo, min(lo + step, count), b, r) for lo in range(0, count, step)]
-    if workers <= 1 or count < 256:
-        for j in jobs:
-            lo, blk = _chain_block(j)
-            out[lo:lo + len(blk)] = blk
-        return out
-    import multiprocessing as mp
-    with mp.get_context("spawn").Pool(workers, initializer=_one_blas_thread) as pool:
-        for lo, blk in pool.imap_unordered(_chain_block, jobs):
-            out[lo:lo + len(blk)] = blk
+    sig = sigma_profile(r)
+    scale = np.stack([np.ones(r), sig, np.ones(r), sig])          # [operand, col]
+    jobs = [(lo, min(lo + chunk, count)) for lo in range(0, count, chunk)]
+    try:
+        from threadpoolctl import threadpool_limits
+        limit = threadpool_limits(1)
+    except ImportError:
+        limit = None
+    try:
+        with ThreadPoolExecutor(max(1, min(threads, len(jobs)))) as ex:
+            for f in [ex.submit(_chain_chunk, cfg, lo, hi, b, r, scale, out) for lo, hi in jobs]:
+                f.result()
+    finally:
+        if limit is not None:
+            limit.restore_original_limits()
     return out
 
 

@@ -49,9 +49,29 @@ def kernel_stats(kt_dir: str, kernel: str) -> dict:
     raise KeyError(kernel)
 
 
-def counter_per_dispatch(pmc_dir: str, kernel: str) -> List[float]:
+def dispatch_durations_ns(kt_dir: str, kernel: str) -> List[float]:
+    """Duration of every dispatch of `kernel`, in dispatch order, from the
+    kernel trace (end minus start timestamp, ns)."""
+    rows = list(csv.DictReader(open(_csv(kt_dir, "kernel_trace.csv"))))
+    if not rows:
+        raise KeyError(kernel)
+    cols = rows[0].keys()
+    start = next(c for c in cols if c.lower().startswith("start_timestamp"))
+    end = next(c for c in cols if c.lower().startswith("end_timestamp"))
+    name = next(c for c in cols if c.lower() == "kernel_name")
+    hits = sorted((int(r[start]), int(r[end])) for r in rows if kernel in r[name])
+    if not hits:
+        raise KeyError(kernel)
+    return [float(e - s) for s, e in hits]
+
+
+def counter_per_dispatch(pmc_dir: str, kernel: str, counter: Optional[str] = None) -> List[float]:
+    """Per-dispatch value of a counter (summed over its instances), in
+    dispatch order; `counter` selects one counter of a multi-counter run."""
     per: Dict[str, float] = {}
     for row in csv.DictReader(open(_csv(pmc_dir, "counter_collection.csv"))):
+        if counter is not None and row.get("Counter_Name") != counter:
+            continue
         if kernel in row["Kernel_Name"]:
             per[row["Dispatch_Id"]] = per.get(row["Dispatch_Id"], 0.0) + float(row["Counter_Value"])
     if not per:
@@ -61,6 +81,11 @@ def counter_per_dispatch(pmc_dir: str, kernel: str) -> List[float]:
 
 def summarize(args) -> str:
     st = kernel_stats(args.kt, args.kernel)
+    durs = dispatch_durations_ns(args.kt, args.kernel)
+    if args.skip >= len(durs):
+        raise ValueError(f"--skip {args.skip} leaves no dispatch of {len(durs)}")
+    timed = durs[args.skip:]
+    med_ms = statistics.median(timed) * 1e-6
     fetch = counter_per_dispatch(args.fetch, args.kernel)
     write = counter_per_dispatch(args.write, args.kernel)
     cal_f = statistics.median(counter_per_dispatch(args.cal_fetch, args.cal_kernel))
@@ -70,6 +95,15 @@ def summarize(args) -> str:
     f_b = statistics.median(fetch) * 1024.0 * fs
     w_b = statistics.median(write) * 1024.0 * ws
     avg_ms = st["avg_ns"] * 1e-6
+    timed_avg_ms = statistics.fmean(timed) * 1e-6
+    mfma = None
+    if args.mfma:
+        # executed FP64 matrix-core flops (the counter is in units of 512 flops) and the share of
+        # SIMD-cycles the matrix cores were busy (busy cycles summed over SIMDs / (active cycles x SIMDs))
+        mops = statistics.median(counter_per_dispatch(args.mfma, args.kernel, "SQ_INSTS_VALU_MFMA_MOPS_F64"))
+        busy = statistics.median(counter_per_dispatch(args.mfma, args.kernel, "SQ_VALU_MFMA_BUSY_CYCLES"))
+        active = statistics.median(counter_per_dispatch(args.mfma, args.kernel, "GRBM_GUI_ACTIVE"))
+        mfma = {"flops": mops * 512.0, "util": busy / (active * args.simds) if active else float("nan")}
     lines = [
         f"# {args.kernel}: {args.workload}",
         "",
@@ -88,6 +122,10 @@ def summarize(args) -> str:
         f"|---|---|---|---|---|",
         f"| {args.kernel} | {st['calls']} | {avg_ms:.4f} | {st['min_ns'] * 1e-6:.4f} | {st['max_ns'] * 1e-6:.4f} |",
         "",
+        f"Timed dispatches (the {len(timed)} after the first {args.skip}, which are the benchmark's warm-up "
+        f"launches; from the per-dispatch kernel trace): median {med_ms:.4f} ms, mean {timed_avg_ms:.4f} ms, "
+        f"min {min(timed) * 1e-6:.4f} ms, max {max(timed) * 1e-6:.4f} ms.",
+        "",
         "## HBM traffic (--pmc FETCH_SIZE, then --pmc WRITE_SIZE; KiB per dispatch)",
         "",
         f"| counter | kernel (median of {len(fetch)}) | copy of {args.cal_bytes / 2**30:.0f} GiB | scale |",
@@ -98,22 +136,41 @@ def summarize(args) -> str:
         f"Scaled traffic per launch: read {f_b / 1e9:.3f} GB + write {w_b / 1e9:.3f} GB = "
         f"{(f_b + w_b) / 1e9:.3f} GB; algorithmic (compulsory) bytes {args.bytes / 1e9:.3f} GB "
         f"(ratio {(f_b + w_b) / args.bytes:.3f}).",
-        f"Achieved: {args.flops / (avg_ms * 1e-3) / 1e12:.2f} TFLOP/s useful "
-        f"({args.flops / (avg_ms * 1e-3) / 78.6e12 * 100:.1f}% of 78.6), "
-        f"{args.bytes / (avg_ms * 1e-3) / 1e9:.0f} GB/s algorithmic "
-        f"({args.bytes / (avg_ms * 1e-3) / 8.0e12 * 100:.1f}% of 8000).",
+        f"Achieved (median timed dispatch): {args.flops / (med_ms * 1e-3) / 1e12:.2f} TFLOP/s useful "
+        f"({args.flops / (med_ms * 1e-3) / 78.6e12 * 100:.1f}% of 78.6), "
+        f"{args.bytes / (med_ms * 1e-3) / 1e9:.0f} GB/s algorithmic "
+        f"({args.bytes / (med_ms * 1e-3) / 8.0e12 * 100:.1f}% of 8000).",
         "",
+    ]
+    if mfma:
+        lines += [
+            "## FP64 matrix-core work (--pmc SQ_INSTS_VALU_MFMA_MOPS_F64 SQ_VALU_MFMA_BUSY_CYCLES GRBM_GUI_ACTIVE)",
+            "",
+            f"Executed FP64 MFMA flops per launch: {mfma['flops'] / 1e9:.2f} GFLOP (counter x 512) against "
+            f"{args.flops / 1e9:.2f} GFLOP useful (ratio {mfma['flops'] / args.flops:.3f}: the excess is padding "
+            f"of partial tiles); matrix cores busy {mfma['util'] * 100:.1f}% of SIMD-cycles "
+            f"(busy cycles summed over the {args.simds} SIMDs / (GRBM_GUI_ACTIVE x {args.simds})); executed rate "
+            f"{mfma['flops'] / (med_ms * 1e-3) / 1e12:.2f} TFLOP/s at the median timed dispatch.",
+            "",
+        ]
+    lines += [
         "## Machine-readable",
         "",
         "```",
         f"kernel: {args.kernel}",
         f"source_digest: {args.digest or source_digest(args.sources.split(',') if args.sources else None)}",
         f"avg_duration_ms: {avg_ms:.6f}",
+        f"median_timed_duration_ms: {med_ms:.6f}",
+        f"timed_dispatches: {len(timed)}",
         f"algorithmic_flops: {args.flops:.6g}",
         f"algorithmic_bytes: {args.bytes:.6g}",
         f"fetch_bytes_per_launch: {f_b:.6g}",
         f"write_bytes_per_launch: {w_b:.6g}",
         f"traffic_bytes_per_launch: {f_b + w_b:.6g}",
+    ]
+    if mfma:
+        lines += [f"mfma_f64_flops_per_launch: {mfma['flops']:.6g}", f"mfma_busy_frac: {mfma['util']:.4f}"]
+    lines += [
         "```",
         "",
     ]
@@ -168,6 +225,10 @@ def main():
     sm.add_argument("--bytes", type=float, required=True)
     sm.add_argument("--digest", default=None)
     sm.add_argument("--sources", default=None, help="comma list of sources (relative to the package) the digest covers")
+    sm.add_argument("--mfma", default=None, help="counter run with SQ_INSTS_VALU_MFMA_MOPS_F64, "
+                    "SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE")
+    sm.add_argument("--simds", type=int, default=1024, help="SIMDs on the chip (MI355X: 256 CUs x 4)")
+    sm.add_argument("--skip", type=int, default=0, help="warm-up dispatches to leave out of the timed statistics")
     sm.add_argument("--cmd", action="append", default=[])
     sm.add_argument("--out", required=True)
     sub.add_parser("digest")

@@ -14,10 +14,15 @@ recorded.
 
 The scheduler core is independent of the GPU: it drives an executor
 (``launch``/``query``/``release``) under a clock (``now``/``idle``), so its
-policy is tested on the CPU with a simulated executor and clock; the GPU
-executor allocates each request's operands on the device (filled from the
-request's own seed, so a request's data never depends on the mix), launches
-one grouped call on the request's stream and records a completion event.
+policy is tested on the CPU with a simulated executor and clock.  The GPU
+executor serves from a :class:`ResidentPool`: the low-rank blocks live in
+device memory before any request arrives (FP64, and their FP32 roundings for
+split-precision requests), and a request names, for each of its instances,
+one resident block of its (b, r) bucket (drawn from the request's own seed,
+so a request's operands never depend on the mix).  Admission allocates the
+request's outputs, builds its descriptors and issues one grouped call on the
+request's stream, then records a completion event; no operand is copied or
+generated per request.
 """
 from __future__ import annotations
 
@@ -49,6 +54,11 @@ class Request:
     def nbytes(self) -> int:
         lay = request_layout(self.shapes, self.prec)
         return lay[2] + lay[4]
+
+    def slots(self, per_bucket: int) -> np.ndarray:
+        """Resident block index (within its (b, r) bucket) of every instance."""
+        rng = np.random.default_rng([*SEED0, 1, self.seed])
+        return rng.integers(0, per_bucket, self.n)
 
     @property
     def flops(self) -> float:
@@ -205,20 +215,73 @@ def summarize(recs: List[Record], skip: int = 0) -> dict:
             "requests_per_s": round(len(ok) / (t_last - t_first), 2)}
 
 
+def bucket_list():
+    """The (b, r) buckets a request can draw: b over the uneven batch's block
+    sizes, r over its ranks with r <= b/2."""
+    return [(b, r) for b in inputs.GROUPED_B for r in inputs.GROUPED_R if r <= b // 2]
+
+
+class ResidentPool:
+    """Device-resident low-rank blocks, `per_bucket` instances of each (b, r)
+    bucket: A (b x b), U, V1, U2 (b x r), column-major, N(0,1) from a seeded
+    device generator, 256-byte aligned.  `f32` holds the same values rounded
+    to FP32 (round to nearest even), the operands of split-precision
+    requests, so their results can be judged against the FP64 originals."""
+
+    def __init__(self, per_bucket: int = 256, seed: int = 77, device="cuda"):
+        import torch
+        self.per_bucket = int(per_bucket)
+        self.buckets = bucket_list()
+        self.index = {br: i for i, br in enumerate(self.buckets)}
+        sizes = []
+        for b, r in self.buckets:
+            sizes += [b * b, b * r, b * r, b * r] * self.per_bucket
+        off, total = inputs.pool_layout(sizes)
+        # off[((bucket * per_bucket) + slot) * 4 + operand], elements
+        self.offsets = off.reshape(len(self.buckets), self.per_bucket, 4)
+        self.f64 = inputs.device_normal(total, seed=seed, device=device)
+        self.f32 = self.f64.float()
+        self.nbytes = total * 12
+
+    def operand_offsets(self, shapes: np.ndarray, slots: np.ndarray) -> np.ndarray:
+        """[n, 4] element offsets of A, U, V1, U2 for each (b, r) and slot."""
+        bi = np.array([self.index[(int(b), int(r))] for b, r in shapes], dtype=np.int64)
+        return self.offsets[bi, slots]
+
+    def host_operands(self, b: int, r: int, slot: int):
+        """FP64 host copies (column-major) of one resident block's A, U, V1, U2."""
+        o = self.offsets[self.index[(b, r)], slot]
+        def cm(off, rows, cols):
+            t = self.f64[int(off):int(off) + rows * cols].view(cols, rows).T
+            return np.asfortranarray(t.cpu().numpy())
+        return cm(o[0], b, b), cm(o[1], b, r), cm(o[2], b, r), cm(o[3], b, r)
+
+
+def output_layout(shapes: np.ndarray, align: int = 256):
+    """Byte offsets of each instance's outputs (C, T) in one FP64 buffer."""
+    b = shapes[:, 0].astype(np.int64); r = shapes[:, 1].astype(np.int64)
+    sizes = np.stack([b * r, r * r], axis=1).reshape(-1) * 8
+    pad = (sizes + align - 1) // align * align
+    off = np.concatenate([[0], np.cumsum(pad)[:-1]]) if len(pad) else np.zeros(0, np.int64)
+    return off, int(pad.sum())
+
+
 class _Launch:
     """In-flight request on the GPU (hashable by identity)."""
-    __slots__ = ("slot", "event", "ops", "out", "req")
+    __slots__ = ("slot", "event", "out", "req")
 
-    def __init__(self, slot, event, ops, out, req):
-        self.slot, self.event, self.ops, self.out, self.req = slot, event, ops, out, req
+    def __init__(self, slot, event, out, req):
+        self.slot, self.event, self.out, self.req = slot, event, out, req
 
 
 class GpuExecutor:
-    """Runs each request as one grouped call on its own HIP stream."""
+    """Runs each request as one grouped call on its own HIP stream, over the
+    operands of a resident pool."""
 
-    def __init__(self, slots: int = 8, keep_outputs=(), device="cuda"):
+    def __init__(self, pool: ResidentPool, slots: int = 8, keep_outputs=(), device="cuda"):
         import torch
         self.torch = torch
+        self.pool = pool
         self.streams = [torch.cuda.Stream(device=device) for _ in range(slots)]   # default priority
         self.free = list(range(slots))
         self.keep = set(keep_outputs)
@@ -232,39 +295,38 @@ class GpuExecutor:
             raise RuntimeError("no free slot")
         slot = self.free.pop()
         s = self.streams[slot]
-        off_in, off_out, nin, es, nout = request_layout(req.shapes, req.prec)
-        dt = torch.float64 if req.prec == "fp64" else torch.float32
         try:
+            off_out, nout = output_layout(req.shapes)
+            ops = self.pool.operand_offsets(req.shapes, req.slots(self.pool.per_bucket))
             with torch.cuda.stream(s):
-                g = torch.Generator(device=self.device)
-                g.manual_seed(req.seed)
-                ops = torch.randn(nin // es, generator=g, device=self.device, dtype=dt)
-                out = torch.empty(nout // 8, dtype=torch.float64, device=self.device)
-                arr = self._descs(req, ops.data_ptr(), out.data_ptr(), off_in, off_out, es)
-                lrbg.lrbg_grouped_array(arr, s)
-                ev = torch.cuda.Event()
-                ev.record(s)
+                out = torch.empty(max(nout // 8, 1), dtype=torch.float64, device=self.device)
+            src = self.pool.f64 if req.prec == "fp64" else self.pool.f32
+            arr = self._descs(req, src.data_ptr(), src.element_size(), ops, out.data_ptr(), off_out)
+            lrbg.lrbg_grouped_array(arr, s)
+            ev = torch.cuda.Event()
+            ev.record(s)
         except Exception:
             self.free.append(slot)
             raise
-        return _Launch(slot, ev, ops, out, req)
+        return _Launch(slot, ev, out, req)
 
     @staticmethod
-    def _descs(req, pin, pout, off_in, off_out, es):
+    def _descs(req, pin, es, ops, pout, off_out):
         from . import lrbg
         n = req.n
         b = req.shapes[:, 0].astype(np.int64); r = req.shapes[:, 1].astype(np.int64)
         arr = np.zeros(2 * n, dtype=lrbg.desc_dtype())
-        oi = off_in.reshape(n, 4); oo = off_out.reshape(n, 2)
+        oi = ops.astype(np.uint64) * np.uint64(es) + np.uint64(pin)
+        oo = off_out.reshape(n, 2).astype(np.uint64) + np.uint64(pout)
         prec = lrbg.PRECS[req.prec]
         d = arr[0::2]   # C = A U
         d["op"] = lrbg.LRBG_OP_DENSE_TS; d["prec"] = prec
         d["m"] = b; d["n"] = r; d["k"] = b; d["lda"] = b; d["ldb"] = b; d["lds"] = 1; d["ldc"] = b
-        d["a"] = pin + oi[:, 0]; d["b"] = pin + oi[:, 1]; d["c"] = pout + oo[:, 0]
+        d["a"] = oi[:, 0]; d["b"] = oi[:, 1]; d["c"] = oo[:, 0]
         t = arr[1::2]   # T = V1^T U2
         t["op"] = lrbg.LRBG_OP_INNER; t["prec"] = prec
         t["m"] = r; t["n"] = r; t["k"] = b; t["lda"] = b; t["ldb"] = b; t["lds"] = 1; t["ldc"] = r
-        t["a"] = pin + oi[:, 2]; t["b"] = pin + oi[:, 3]; t["c"] = pout + oo[:, 1]
+        t["a"] = oi[:, 2]; t["b"] = oi[:, 3]; t["c"] = oo[:, 1]
         return arr
 
     def query(self, h) -> bool:
@@ -274,5 +336,18 @@ class GpuExecutor:
         if h.req.rid in self.keep:
             h.event.synchronize()
             self.outputs[h.req.rid] = h.out.cpu().numpy()
-        h.ops = h.out = None
+        h.out = None
         self.free.append(h.slot)
+
+
+def request_outputs(req: Request, flat: np.ndarray):
+    """(C, T) of every instance of a request from its flat output buffer."""
+    off, _ = output_layout(req.shapes)
+    off = off.reshape(req.n, 2) // 8
+    out = []
+    for i, (b, r) in enumerate(req.shapes):
+        b, r = int(b), int(r)
+        C = flat[off[i, 0]:off[i, 0] + b * r].reshape(r, b).T
+        T = flat[off[i, 1]:off[i, 1] + r * r].reshape(r, r).T
+        out.append((C, T))
+    return out

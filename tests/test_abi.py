@@ -149,6 +149,24 @@ def test_lrmult_validation_and_accounting():
         lrbg.LRBG_EINVAL
 
 
+def test_lrmult_accounting_at_the_papers_tabulated_shapes():
+    """The useful-flop count the library reports for a batch of fused
+    low-rank products equals the paper's GFLOPS equation (Sec. 7: batch x
+    (4 r^3 + 2 r^2 b)) at every (rank, block size) of the paper's printed
+    rank-96 and rank-128 tables (tests/golden/paper_tables.json)."""
+    import json
+    tab = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_tables.json")))
+    assert tab["gflops_equation"] == "batch_size * (4*rank^3 + 2*rank^2*block_size) / time"
+    shapes = sorted({(t["rank"], b) for t in tab["tables"] for b in t["block_size"]})
+    assert shapes == [(96, 512), (96, 1024), (96, 2048), (128, 512), (128, 1024), (128, 2048)]
+    batch = 3
+    for r, b in shapes:
+        descs = [mk("lrmult", m=r, n=r, k=b, base=BASE * (i + 1)) for i in range(batch)]
+        st = lrbg.lrbg_schedule_stats(descs)
+        assert st["useful_flops"] == batch * (4 * r ** 3 + 2 * r ** 2 * b), (r, b)
+        assert st["hbm_bytes"] == batch * 8 * (2 * b * r + 3 * r * r), (r, b)
+
+
 def test_lrmult_entry_validates_before_launch():
     lib = lrbg.load()
     assert lib.lr_batched_lrmult(1, *([None] * 13), None) == lrbg.LRBG_EINVAL

@@ -289,6 +289,23 @@ def test_error_metric(orc):
     assert orc.normalized_error(C4, R, D) == float("inf")
 
 
+def test_normwise_error_hand_computed(orc):
+    """max_ij |C - Cref| / (||A||_F ||B||_F) on values worked by hand:
+    A = [[3, 0], [0, 4]] (||A||_F = 5), B = [[1, 2], [2, 4]] (||B||_F = 5);
+    the largest entry of |C - Cref| is 0.5, so the error is 0.5 / 25."""
+    A = np.array([[3.0, 0.0], [0.0, 4.0]]); B = np.array([[1.0, 2.0], [2.0, 4.0]])
+    Cref = A @ B
+    C = Cref.copy(); C[0, 1] -= 0.5; C[1, 0] += 0.25
+    a_fro, b_fro = float(np.sqrt((A * A).sum())), float(np.sqrt((B * B).sum()))
+    assert (a_fro, b_fro) == (5.0, 5.0)
+    assert orc.normwise_error(C, Cref, a_fro, b_fro) == 0.02
+    assert orc.normwise_error(Cref, Cref, a_fro, b_fro) == 0.0
+    assert orc.normwise_error(np.zeros((0, 3)), np.zeros((0, 3)), 1.0, 1.0) == 0.0
+    # zero operands: an exact zero result has no error, anything else is unbounded
+    assert orc.normwise_error(np.zeros((2, 2)), np.zeros((2, 2)), 0.0, 5.0) == 0.0
+    assert orc.normwise_error(C, Cref, 0.0, 5.0) == float("inf")
+
+
 def test_dot2_ill_conditioned_exact(orc):
     """Dot2 recovers sums that plain summation loses entirely: the rounding
     error of a product (a*a - fl(a*a)) and cancellation of huge terms.  The

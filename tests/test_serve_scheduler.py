@@ -131,3 +131,28 @@ def test_layout_offsets_aligned_and_disjoint():
         assert np.all(off_in % 256 == 0) and np.all(off_out % 256 == 0)
         assert np.all(np.diff(off_in) > 0) and off_in[-1] < nin
         assert r.nbytes == nin + nout
+
+
+def test_resident_pool_descriptors_validate_on_host():
+    """The descriptors a request is served with (built over a resident pool,
+    here on the host) pass the library's validation as one level, and the
+    library's accounting equals the request's own flop count."""
+    from paper_2311_07602_amd import lrbg
+    pool = serve.ResidentPool(per_bucket=2, seed=3, device="cpu")
+    assert len(pool.buckets) == 22
+    for req in serve.make_requests(6, float("inf"), seed=21, nmax=300):
+        off_out, nout = serve.output_layout(req.shapes)
+        slots = req.slots(pool.per_bucket)
+        assert slots.min() >= 0 and slots.max() < pool.per_bucket
+        assert np.array_equal(slots, req.slots(pool.per_bucket))           # fixed by the request's seed
+        src = pool.f64 if req.prec == "fp64" else pool.f32
+        ops = pool.operand_offsets(req.shapes, slots)
+        # every operand lies inside the pool
+        b = req.shapes[:, 0]; r = req.shapes[:, 1]
+        ends = ops + np.stack([b * b, b * r, b * r, b * r], axis=1)
+        assert ops.min() >= 0 and ends.max() <= src.numel()
+        arr = serve.GpuExecutor._descs(req, src.data_ptr(), src.element_size(), ops, 1 << 44, off_out)
+        descs = [lrbg.lrbg_desc.from_buffer_copy(arr[i].tobytes()) for i in range(len(arr))]
+        st = lrbg.lrbg_schedule_stats(descs)
+        assert st["levels"] == 1 and st["products"] == 2 * req.n
+        assert st["useful_flops"] == pytest.approx(req.flops, rel=1e-12)
