@@ -249,3 +249,104 @@ double orc_dot2(int64_t n, const double *x, int64_t incx, const double *y,
     }
     return s + c;
 }
+
+/*
+ * Thin QR factorisation W = Q R by Householder reflections, the first step of
+ * the rounded addition of two low-rank blocks (Sec. 2 names the low-rank
+ * product as the first step of that algorithm; the addition itself stacks
+ * the two blocks' bases, [A_U | B_U] and [A_V | B_V], and orthogonalises
+ * them before the small core is decomposed).
+ *   W m x n (read only), Q m x p, R p x n, p = min(m, n).
+ * Textbook column-by-column Householder QR (Golub and Van Loan, Matrix
+ * Computations, the Householder vector of Sec. 5.1.3 and the QR of
+ * Sec. 5.2.2), with Q formed by backward accumulation (Sec. 5.1.6):
+ *   for j = 0 .. p-1, with x = H(j:m-1, j):
+ *     sigma = x(1:)^T x(1:);  v = [1; x(1:) / v0]
+ *     sigma = 0:  beta = 0 if x0 >= 0 (H_j = I), else beta = 2, v = e_1
+ *                 (H_j flips the sign of row j)
+ *     otherwise:  mu = sqrt(x0^2 + sigma),
+ *                 v0 = x0 - mu if x0 <= 0, else -sigma / (x0 + mu),
+ *                 beta = 2 v0^2 / (sigma + v0^2)
+ *     H(j:m-1, j:n-1) <- (I - beta v v^T) H(j:m-1, j:n-1)
+ *   so that H_j x = |x| e_1: R has a non-negative diagonal, and Q and R are
+ *   unique when W has full column rank.  Q = H_0 H_1 ... H_{p-1} [I_p; 0].
+ * Returns non-zero if scratch memory could not be allocated.
+ */
+static int householder_qr_one(int m, int n, const double *W, int ldw,
+                              double *Q, int ldq, double *R, int ldr)
+{
+    const int p = m < n ? m : n;
+    double *H = NULL, *v = NULL, *beta = NULL, *V = NULL;
+    if (m > 0 && n > 0) {
+        H = (double *)malloc(sizeof(double) * (size_t)m * (size_t)n);
+        v = (double *)malloc(sizeof(double) * (size_t)m);
+        V = (double *)malloc(sizeof(double) * (size_t)m * (size_t)(p > 0 ? p : 1));
+        beta = (double *)malloc(sizeof(double) * (size_t)(p > 0 ? p : 1));
+        if (!H || !v || !V || !beta) { free(H); free(v); free(V); free(beta); return 1; }
+    }
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < m; ++i)
+            H[(size_t)i + (size_t)j * m] = AT(W, i, j, ldw);
+    for (int j = 0; j < p; ++j) {
+        const double x0 = H[(size_t)j + (size_t)j * m];
+        double sigma = 0.0;
+        for (int i = j + 1; i < m; ++i)
+            sigma = sigma + H[(size_t)i + (size_t)j * m] * H[(size_t)i + (size_t)j * m];
+        double b;
+        v[j] = 1.0;
+        if (sigma == 0.0) {
+            b = x0 >= 0.0 ? 0.0 : 2.0;
+            for (int i = j + 1; i < m; ++i) v[i] = 0.0;
+        } else {
+            const double mu = sqrt(x0 * x0 + sigma);
+            const double v0 = x0 <= 0.0 ? x0 - mu : -sigma / (x0 + mu);
+            b = 2.0 * v0 * v0 / (sigma + v0 * v0);
+            for (int i = j + 1; i < m; ++i) v[i] = H[(size_t)i + (size_t)j * m] / v0;
+        }
+        beta[j] = b;
+        for (int c = j; c < n; ++c) {
+            double w = 0.0;
+            for (int i = j; i < m; ++i)
+                w = w + v[i] * H[(size_t)i + (size_t)c * m];
+            for (int i = j; i < m; ++i)
+                H[(size_t)i + (size_t)c * m] = H[(size_t)i + (size_t)c * m] - b * w * v[i];
+        }
+        for (int i = 0; i < m; ++i)
+            V[(size_t)i + (size_t)j * m] = i < j ? 0.0 : v[i];
+    }
+    /* R: the upper trapezoid of the reduced matrix */
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < p; ++i)
+            AT(R, i, j, ldr) = i <= j ? H[(size_t)i + (size_t)j * m] : 0.0;
+    /* Q = H_0 ... H_{p-1} [I_p; 0], applied from the last reflector back */
+    for (int j = 0; j < p; ++j)
+        for (int i = 0; i < m; ++i)
+            AT(Q, i, j, ldq) = i == j ? 1.0 : 0.0;
+    for (int j = p - 1; j >= 0; --j)
+        for (int c = j; c < p; ++c) {
+            double w = 0.0;
+            for (int i = j; i < m; ++i)
+                w = w + V[(size_t)i + (size_t)j * m] * AT(Q, i, c, ldq);
+            for (int i = j; i < m; ++i)
+                AT(Q, i, c, ldq) = AT(Q, i, c, ldq) - beta[j] * w * V[(size_t)i + (size_t)j * m];
+        }
+    free(H);
+    free(v);
+    free(V);
+    free(beta);
+    return 0;
+}
+
+int orc_householder_qr(int64_t count, const int32_t *m, const int32_t *n,
+                       const double *const *W, const int32_t *ldw,
+                       double *const *Q, const int32_t *ldq,
+                       double *const *R, const int32_t *ldr, int nthreads)
+{
+    set_threads(nthreads);
+    int failed = 0;
+    int64_t t;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : failed)
+    for (t = 0; t < count; ++t)
+        failed |= householder_qr_one(m[t], n[t], W[t], ldw[t], Q[t], ldq[t], R[t], ldr[t]);
+    return failed;
+}

@@ -25,7 +25,8 @@ _LIB_PATH = os.path.join(_HERE, "liblrbg_oracle.so")
 _lib = None
 
 __all__ = [
-    "load", "dense_ts", "inner", "recomp", "chain", "lr_mult", "lr_mult_round", "blr_matvec", "dot2",
+    "load", "dense_ts", "inner", "recomp", "chain", "lr_mult", "lr_mult_round", "householder_qr", "lr_add_round",
+    "blr_matvec", "dot2",
     "max_threads", "normalized_error", "normwise_error", "col_major",
 ]
 
@@ -49,6 +50,8 @@ def load():
     lib.orc_recomp.restype = ctypes.c_int
     lib.orc_lr_mult.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int]
     lib.orc_lr_mult.restype = ctypes.c_int
+    lib.orc_householder_qr.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int]
+    lib.orc_householder_qr.restype = ctypes.c_int
     lib.orc_dot2.argtypes = [i64, vp, i64, vp, i64]
     lib.orc_dot2.restype = ctypes.c_double
     lib.orc_max_threads.argtypes = []
@@ -172,19 +175,68 @@ def lr_mult_round(AU, AV, AX, BU, BX, BV, kmax: int, tol: float):
     B_V Y_k (the oracle's loops).  Returns (U, sigma, V, k) with U, V
     b x kmax and sigma of length kmax, zero beyond k."""
     G = lr_mult([AV], [BU], [AX], [BX])[0]
-    ra, rb = G.shape
-    if G.size == 0:
+    Xk, sig, Yk, k = _truncate(G, kmax, tol)
+    U = dense_ts([AU], [Xk])[0]
+    V = dense_ts([BV], [Yk])[0]
+    return U, sig, V, k
+
+
+def householder_qr(Ws, nthreads: int = 0):
+    """Thin QR W_t = Q_t R_t of each W_t (m x n) by Householder reflections,
+    Q m x p with orthonormal columns and R p x n upper trapezoidal with a
+    non-negative diagonal, p = min(m, n) (the oracle's loops).  Returns a
+    list of (Q, R)."""
+    cnt = len(Ws)
+    m = _i32([w.shape[0] for w in Ws]); n = _i32([w.shape[1] for w in Ws])
+    Qs = [col_major(int(m[t]), int(min(m[t], n[t]))) for t in range(cnt)]
+    Rs = [col_major(int(min(m[t], n[t])), int(n[t])) for t in range(cnt)]
+    pw, lw = _arrays(Ws); pq, lq = _arrays(Qs); pr, lr = _arrays(Rs)
+    rc = load().orc_householder_qr(cnt, _p(m), _p(n), _p(pw), _p(lw), _p(pq), _p(lq), _p(pr), _p(lr), nthreads)
+    if rc:
+        raise MemoryError("oracle householder_qr: allocation failed")
+    return list(zip(Qs, Rs))
+
+
+def _truncate(M, kmax: int, tol: float):
+    """SVD of the small core M (LAPACK through numpy, a library step) and
+    the truncation rule shared by the recompressed product and the rounded
+    addition: keep the k <= kmax largest singular values above tol * sigma_1
+    (none if sigma_1 = 0).  Returns (X_k, sigma, Y_k, k) with X_k, Y_k padded
+    with zero columns to kmax and sigma of length kmax, zero beyond k."""
+    ra, rb = M.shape
+    if M.size == 0:
         s = np.zeros(0); X = np.zeros((ra, 0)); Yt = np.zeros((0, rb))
     else:
-        X, s, Yt = np.linalg.svd(G, full_matrices=False)
+        X, s, Yt = np.linalg.svd(M, full_matrices=False)
     k = 0
     while k < len(s) and k < kmax and s[0] > 0 and s[k] > tol * s[0]:
         k += 1
     Xk = col_major(ra, kmax, fill=0.0); Yk = col_major(rb, kmax, fill=0.0)
     Xk[:, :k] = X[:, :k]; Yk[:, :k] = Yt[:k, :].T
     sig = np.zeros(kmax); sig[:k] = s[:k]
-    U = dense_ts([AU], [Xk])[0]
-    V = dense_ts([BV], [Yk])[0]
+    return Xk, sig, Yk, k
+
+
+def lr_add_round(AU, AV, AX, BU, BX, BV, kmax: int, tol: float):
+    """Rounded addition of two low-rank blocks A = A_U A_X A_V^T and
+    B = B_U B_X B_V^T (b x b, ranks ra and rb, bases of any conditioning):
+    A + B = [A_U | B_U] diag(A_X, B_X) [A_V | B_V]^T; Householder QR of both
+    stacked bases (the oracle's loops), the small core
+    M = R_U diag(A_X, B_X) R_V^T (the oracle's recompression loops), its
+    SVD and truncation (as in ``lr_mult_round``), and the new bases Q_U X_k
+    and Q_V Y_k (the oracle's loops).  Returns (U, sigma, V, k) with U, V
+    b x kmax and sigma of length kmax, zero beyond k."""
+    b, ra = AU.shape
+    rb = BU.shape[1]
+    WU = col_major(b, ra + rb); WU[:, :ra] = AU; WU[:, ra:] = BU
+    WV = col_major(b, ra + rb); WV[:, :ra] = AV; WV[:, ra:] = BV
+    (QU, RU), (QV, RV) = householder_qr([WU, WV])
+    D = col_major(ra + rb, ra + rb, fill=0.0)
+    D[:ra, :ra] = AX; D[ra:, ra:] = BX
+    M = recomp([RU], [D], [RV])[0]
+    Xk, sig, Yk, k = _truncate(M, kmax, tol)
+    U = dense_ts([QU], [Xk])[0]
+    V = dense_ts([QV], [Yk])[0]
     return U, sig, V, k
 
 

@@ -30,6 +30,13 @@ MUTANTS = {
     "lr_mult_AX_transposed": ("AT(AX, i, l, ldax)", "AT(AX, l, i, ldax)"),
     "lr_mult_BX_transposed": ("AT(BX, l, j, ldbx)", "AT(BX, j, l, ldbx)"),
     "dot2_no_product_error": ("c = c + (ep + es);", "c = c + es;"),
+    "qr_wrong_householder_lead": ("x0 <= 0.0 ? x0 - mu :", "x0 <= 0.0 ? x0 + mu :"),
+    "qr_beta_missing_factor_two": ("b = 2.0 * v0 * v0 / (sigma + v0 * v0);", "b = v0 * v0 / (sigma + v0 * v0);"),
+    "qr_update_skips_pivot_column": ("for (int c = j; c < n; ++c) {", "for (int c = j + 1; c < n; ++c) {"),
+    "qr_q_accumulated_forward": ("for (int j = p - 1; j >= 0; --j)", "for (int j = 0; j < p; ++j)"),
+    "qr_no_sign_flip": ("b = x0 >= 0.0 ? 0.0 : 2.0;", "b = 0.0;"),
+    "qr_norm_includes_pivot": ("for (int i = j + 1; i < m; ++i)\n            sigma = sigma",
+                               "for (int i = j; i < m; ++i)\n            sigma = sigma"),
 }
 
 

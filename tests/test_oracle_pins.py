@@ -404,3 +404,162 @@ def test_blr_matvec_selected_rows_equal_full_evaluation(orc):
     full = orc.blr_matvec(D, U, V, X)
     part = orc.blr_matvec(D, U, V, X, rows=[3, 0])
     assert np.array_equal(part[0], full[3]) and np.array_equal(part[1], full[0])
+
+
+# ----------------------------------------------------- Householder QR
+
+def _qr_checks(W, Q, R, tol=1e-14):
+    m, n = W.shape
+    p = min(m, n)
+    assert Q.shape == (m, p) and R.shape == (p, n)
+    scale = max(np.abs(W).max(), 1e-300)
+    assert np.max(np.abs(Q @ R - W)) <= tol * (m + n) * scale
+    assert np.max(np.abs(Q.T @ Q - np.eye(p))) <= tol * (m + n)
+    assert np.all(np.tril(R, -1) == 0)
+    assert np.all(np.diag(R) >= 0)
+
+
+def test_householder_qr_hadamard_closed_form(orc):
+    """Columns of a Hadamard matrix are orthogonal with norm 2: every
+    reflector's quantities are exact in binary64, so R = 2 I and Q = H / 2
+    bit for bit (H_0's sign case x0 > 0 and the later x0 <= 0 cases both
+    occur)."""
+    H = np.array([[1, 1, 1, 1], [1, -1, 1, -1], [1, 1, -1, -1], [1, -1, -1, 1]], dtype=float)
+    (Q, R), = orc.householder_qr([np.asfortranarray(H)])
+    assert np.array_equal(R, 2.0 * np.eye(4))
+    assert np.array_equal(Q, H / 2.0)
+    # a signed column permutation (the first pivot negative, so the x0 <= 0
+    # branch starts): R = 2 I and Q = Hs / 2 to rounding (thirds appear)
+    Hs = np.asfortranarray(H[:, [2, 0, 3, 1]] * np.array([-1.0, 1.0, -1.0, 1.0]))
+    (Q2, R2), = orc.householder_qr([Hs])
+    assert np.max(np.abs(R2 - 2.0 * np.eye(4))) <= 4 * 2.0 ** -52
+    assert np.max(np.abs(Q2 - Hs / 2.0)) <= 4 * 2.0 ** -52
+
+
+@pytest.mark.parametrize("m,n", [(10, 4), (4, 4), (3, 6), (64, 24), (1, 1), (5, 1), (1, 5), (37, 36)])
+def test_householder_qr_invariants_and_library(orc, m, n):
+    """Q R = W, orthonormal Q, upper-trapezoidal R with a non-negative
+    diagonal; with full column rank Q and R are unique, so they agree with
+    LAPACK's QR (numpy) once its signs are normalised the same way."""
+    rng = np.random.default_rng(m * 100 + n)
+    W = inputs.normal_f(rng, m, n)
+    (Q, R), = orc.householder_qr([W])
+    _qr_checks(W, Q, R)
+    q, r = np.linalg.qr(W)
+    sg = np.where(np.diag(r) < 0, -1.0, 1.0)
+    assert np.max(np.abs(q * sg - Q)) <= 1e-13
+    assert np.max(np.abs((r.T * sg).T - R)) <= 1e-13 * np.abs(W).max() * m
+
+
+def test_householder_qr_ld_gap_and_batch(orc):
+    rng = np.random.default_rng(5)
+    Ws = []
+    for m, n, ld in [(9, 3, 12), (6, 6, 7), (4, 2, 4)]:
+        W = orc.col_major(m, n, ld)
+        W[:, :] = rng.standard_normal((m, n))
+        Ws.append(W)
+    before = [W.copy() for W in Ws]
+    out = orc.householder_qr(Ws)
+    for W, W0, (Q, R) in zip(Ws, before, out):
+        _qr_checks(W, Q, R)
+        assert np.array_equal(W, W0)           # the input is read only
+
+
+def test_householder_qr_gram_exact_integer(orc):
+    """R^T R = W^T W: the Gram matrix of integer columns is exact in
+    integers; each entry of R^T R must match it to rounding."""
+    rng = np.random.default_rng(6)
+    for m, n in [(7, 3), (5, 5), (12, 4)]:
+        Wi = rng.integers(-3, 4, size=(m, n))
+        W = np.asfortranarray(Wi.astype(float))
+        (Q, R), = orc.householder_qr([W])
+        G = exact_int_matmul(Wi.T, Wi)
+        assert np.max(np.abs(R.T @ R - G)) <= 64 * 2.0 ** -52 * (np.abs(Wi).max() ** 2) * m
+
+
+def test_householder_qr_rank_deficient_and_sign_cases(orc):
+    """Duplicate and zero columns (the stacked bases of two blocks sharing a
+    basis) still give Q R = W with orthonormal Q; a column that is already a
+    negative multiple of e_j takes the sign flip (beta = 2) and yields a
+    non-negative R_jj."""
+    rng = np.random.default_rng(8)
+    A = inputs.normal_f(rng, 20, 3)
+    W = np.asfortranarray(np.hstack([A, A[:, [1]], np.zeros((20, 1)), A[:, [0]] * -2.0]))
+    (Q, R), = orc.householder_qr([W])
+    _qr_checks(W, Q, R, tol=1e-13)
+    assert np.max(np.abs(np.diag(R)[3:])) <= 1e-13 * np.abs(W).max() * 20
+    E = np.asfortranarray(np.array([[-3.0, 1.0], [0.0, 2.0], [0.0, 0.0]]))
+    (Q, R), = orc.householder_qr([E])
+    assert np.array_equal(R, np.array([[3.0, -1.0], [0.0, 2.0]]))
+    assert np.array_equal(Q, np.array([[-1.0, 0.0], [0.0, 1.0], [0.0, 0.0]]))
+
+
+# ------------------------------------------------- rounded addition
+
+def _lr_blocks(rng, b, ra, rb):
+    return (inputs.normal_f(rng, b, ra), inputs.normal_f(rng, b, ra), inputs.normal_f(rng, ra, ra),
+            inputs.normal_f(rng, b, rb), inputs.normal_f(rng, rb, rb), inputs.normal_f(rng, b, rb))
+
+
+@pytest.mark.parametrize("b,ra,rb,kmax", [(30, 4, 3, 7), (16, 5, 5, 10), (6, 4, 4, 6), (25, 1, 6, 3)])
+def test_lr_add_round_equals_dense_truncated_svd(orc, b, ra, rb, kmax):
+    """The rounded addition is the truncated SVD of the dense sum A + B: the
+    singular values agree with LAPACK's SVD of the explicitly formed b x b
+    sum, and U diag(sigma) V^T with its truncation (N(0,1) factors: the
+    spectrum has gaps)."""
+    rng = np.random.default_rng(b * 7 + ra + rb)
+    AU, AV, AX, BU, BX, BV = _lr_blocks(rng, b, ra, rb)
+    S = AU @ AX @ AV.T + BU @ BX @ BV.T
+    X, s, Yt = np.linalg.svd(S)
+    U, sig, V, k = orc.lr_add_round(AU, AV, AX, BU, BX, BV, kmax, 0.0)
+    kk = min(kmax, ra + rb, b)
+    assert k == kk
+    assert np.max(np.abs(sig[:k] - s[:k])) <= 1e-12 * s[0]
+    assert np.all(sig[k:] == 0) and np.all(U[:, k:] == 0) and np.all(V[:, k:] == 0)
+    trunc = X[:, :k] @ np.diag(s[:k]) @ Yt[:k]
+    assert np.max(np.abs(U[:, :k] @ np.diag(sig[:k]) @ V[:, :k].T - trunc)) <= 1e-11 * s[0]
+    assert np.allclose(U[:, :k].T @ U[:, :k], np.eye(k), atol=1e-13)
+    assert np.allclose(V[:, :k].T @ V[:, :k], np.eye(k), atol=1e-13)
+
+
+def test_lr_add_round_planted_spectrum(orc):
+    """A_U, B_U (and A_V, B_V) are complementary column blocks of orthonormal
+    P (and Q) and the cores are diagonal: A + B = P diag(s) Q^T, so the
+    singular values are the planted ones and the tolerance decides k."""
+    rng = np.random.default_rng(43)
+    b, ra, rb = 50, 4, 3
+    s = np.array([5.0, 1e-3, 2.0, 1e-9, 3.0, 1e-14, 0.5])
+    P = inputs.orthonormal_f(rng, b, ra + rb); Q = inputs.orthonormal_f(rng, b, ra + rb)
+    AU, BU = np.asfortranarray(P[:, :ra]), np.asfortranarray(P[:, ra:])
+    AV, BV = np.asfortranarray(Q[:, :ra]), np.asfortranarray(Q[:, ra:])
+    AX, BX = np.asfortranarray(np.diag(s[:ra])), np.asfortranarray(np.diag(s[ra:]))
+    order = np.argsort(-s)
+    for tol, kmax, want in ((1e-6, 7, 5), (1e-12, 7, 6), (0.0, 3, 3), (0.5, 7, 2)):
+        U, sig, V, k = orc.lr_add_round(AU, AV, AX, BU, BX, BV, kmax, tol)
+        assert k == want
+        assert np.allclose(sig[:k], s[order[:k]], rtol=1e-13, atol=1e-15)
+        keep = order[:k]
+        trunc = P[:, keep] @ np.diag(s[keep]) @ Q[:, keep].T
+        assert np.max(np.abs(U[:, :k] @ np.diag(sig[:k]) @ V[:, :k].T - trunc)) < 1e-13
+
+
+def test_lr_add_round_shared_bases_and_cancellation(orc):
+    """B with the same orthonormal bases as A: the stacked bases are exactly
+    rank deficient and A + B = A_U (A_X + B_X) A_V^T, whose singular values
+    are those of A_X + B_X.  B = -A cancels to the zero block."""
+    rng = np.random.default_rng(44)
+    b, r = 40, 5
+    AU = inputs.orthonormal_f(rng, b, r); AV = inputs.orthonormal_f(rng, b, r)
+    AX = inputs.normal_f(rng, r, r); BX = inputs.normal_f(rng, r, r)
+    U, sig, V, k = orc.lr_add_round(AU, AV, AX, AU, BX, AV, 2 * r, 1e-10)
+    s = np.linalg.svd(AX + BX, compute_uv=False)
+    assert k == r
+    assert np.max(np.abs(sig[:r] - s)) <= 1e-13 * s[0]
+    full = AU @ (AX + BX) @ AV.T
+    assert np.max(np.abs(U[:, :k] @ np.diag(sig[:k]) @ V[:, :k].T - full)) <= 1e-13 * s[0]
+    # B = -A: the sum is zero up to the rounding of the QR and of the core,
+    # so every singular value is at the noise level of A's
+    U, sig, V, k = orc.lr_add_round(AU, AV, AX, AU, np.asfortranarray(-AX), AV, 2 * r, 0.0)
+    sa = np.linalg.svd(AX, compute_uv=False)[0]
+    assert np.all(sig <= 16 * r * 2.0 ** -52 * sa)
+    assert np.max(np.abs(U[:, :k] @ np.diag(sig[:k]) @ V[:, :k].T)) <= 16 * r * 2.0 ** -52 * sa
