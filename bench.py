@@ -70,11 +70,19 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
+_HOST_THREADS = None
+
+
 def host_threads() -> int:
     """Threads the oracle may use: the process's CPU affinity, capped by the
-    OpenMP limit the environment sets."""
-    import oracle
-    return max(1, min(len(os.sched_getaffinity(0)), oracle.max_threads()))
+    OpenMP limit the environment sets.  Read once, before any oracle call:
+    a call with an explicit thread count changes the OpenMP default that
+    later queries would see."""
+    global _HOST_THREADS
+    if _HOST_THREADS is None:
+        import oracle
+        _HOST_THREADS = max(1, min(len(os.sched_getaffinity(0)), oracle.max_threads()))
+    return _HOST_THREADS
 
 
 def _timed(fn):
@@ -462,6 +470,74 @@ def run_round(count=20000, b=1024, rs=(8, 16, 32), tol=1e-8, steps=10, warmup=2)
             "sizes": out}
 
 
+def lradd_work(b, ra, rb, k):
+    """Useful FP64 flops and compulsory HBM bytes of one rounded addition:
+    Householder QR of both b x s stacked bases (2 b s^2 - 2 s^3 / 3 each),
+    the core (E = R_U diag(A_X, B_X): 2 s (ra^2 + rb^2); M = E R_V^T: 2 s^3),
+    and the two new bases Q [X_k; 0] (4 k (b s - s^2 / 2) each; the SVD's
+    iterations are not counted); bytes: the four bases and two cores read
+    once, U, V, sigma and kout written once."""
+    s = ra + rb
+    flops = 2 * (2.0 * b * s * s - 2.0 * s ** 3 / 3) + 2.0 * s * (ra * ra + rb * rb) + 2.0 * s ** 3 \
+        + 2 * 4.0 * k * (b * s - s * s / 2.0)
+    bytes_ = 8.0 * (2 * b * ra + 2 * b * rb + ra * ra + rb * rb + 2 * b * k + k) + 4.0
+    return flops, bytes_
+
+
+def run_add(count=20000, b=1024, rs=(8, 16, 32), tol=1e-8, steps=5, warmup=2):
+    """The rounded addition of two rank-r blocks (stacked rank 2r) recompressed
+    to rank <= r on device-resident N(0,1) operands: QR of both stacked bases,
+    the core, its truncated SVD and the new bases; one-shot calls (host
+    scheduling included) and their device time."""
+    import torch
+    from paper_2311_07602_amd import inputs, lrbg
+    stream = torch.cuda.current_stream()
+    out = []
+    for r in rs:
+        kmax = r
+        per = 4 * b * r + 2 * r * r
+        pin = inputs.device_normal(count * per, seed=27 + r)
+        U = torch.empty(count, kmax, b, dtype=torch.float64, device="cuda")
+        V = torch.empty_like(U)
+        sigma = torch.empty(count * kmax, dtype=torch.float64, device="cuda")
+        kout = torch.empty(count, dtype=torch.int32, device="cuda")
+        base = pin.data_ptr()
+        off = lambda t, j: base + 8 * (t * per + j * b * r)
+        offs = lambda t, j: base + 8 * (t * per + 4 * b * r + j * r * r)
+        ts = range(count)
+        args = ([b] * count, [r] * count, [r] * count,
+                [off(t, 0) for t in ts], [b] * count, [off(t, 1) for t in ts], [b] * count,
+                [offs(t, 0) for t in ts], [r] * count, [off(t, 2) for t in ts], [b] * count,
+                [offs(t, 1) for t in ts], [r] * count, [off(t, 3) for t in ts], [b] * count,
+                kmax, tol, [U[t].data_ptr() for t in ts], [b] * count, [V[t].data_ptr() for t in ts], [b] * count,
+                sigma.data_ptr(), kout.data_ptr())
+        call = lambda: lrbg.lr_batched_lradd_round(*args, stream=stream)
+        ms = time_calls(call, steps, warmup, stream)
+        dev = []
+        for _ in range(3):
+            torch.cuda._sleep(int(2e8))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            call()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            dev.append(e0.elapsed_time(e1))
+        f1, b1 = lradd_work(b, r, r, kmax)
+        dms = min(dev)
+        roof = max(f1 * count / (PEAK_FP64_TFLOPS * 1e12), b1 * count / (PEAK_HBM_GBS * 1e9)) * 1e3
+        out.append({"b": b, "r": r, "kmax": kmax, "ms_per_call": round(ms, 4), "device_ms": round(dms, 4),
+                    "GFLOP/s": round(f1 * count / dms / 1e6, 1), "GB/s": round(b1 * count / dms / 1e6, 1),
+                    "roofline_ms": round(roof, 4), "frac_of_roofline_time": round(roof / dms, 4),
+                    "kept_rank_mean": round(float(kout.double().mean()), 2)})
+        log(f"[bench] rounded addition b={b} r={r}: {ms:.4f} ms per call, {dms:.4f} ms on the device")
+        del pin, U, V
+        torch.cuda.empty_cache()
+    return {"workload": f"{count} x (A_U A_X A_V^T + B_U B_X B_V^T), both of rank r, recompressed to rank <= r "
+                        f"(tol {tol}), FP64, lr_batched_lradd_round calls (QR of both stacked bases, core, batched "
+                        f"SVD, new bases)", "bound": "fp64 vector ALU (78.6 TFLOP/s) for r >= 16",
+            "sizes": out}
+
+
 def run_blr(nbs=(32, 64, 128), b=512, r=8, nrhs=8, steps=20, warmup=3):
     """Weakly admissible BLR matrix times 8 right-hand sides (rank 8), the
     application of the paper's evaluation; one captured two-level plan per
@@ -597,6 +673,8 @@ def main():
         line["extra"]["lrmult_paper_shapes"] = run_lrmult_paper()
         log("[bench] recompressed low-rank products ...")
         line["extra"]["lrmult_round"] = run_round()
+        log("[bench] rounded additions of low-rank blocks ...")
+        line["extra"]["lradd_round"] = run_add()
         log("[bench] BLR matrix x 8 right-hand sides ...")
         line["extra"]["blr_matvec"] = run_blr()
     print(json.dumps(line), flush=True)

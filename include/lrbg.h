@@ -191,6 +191,43 @@ lrbg_status lr_batched_lrmult_round(int64_t count, const int32_t *b, const int32
                                     double *sigma, int32_t *kout, void *stream);
 
 /*
+ * lr_batched_lradd_round -- `count` rounded additions of two low-rank
+ * blocks: A = A_U A_X A_V^T and B = B_U B_X B_V^T (b x b blocks of ranks ra
+ * and rb; the bases need not be orthonormal and may share columns) give
+ *   A + B = [A_U | B_U] diag(A_X, B_X) [A_V | B_V]^T,
+ * recompressed by a Householder QR of both stacked bases ([A_U | B_U] =
+ * Q_U R_U, [A_V | B_V] = Q_V R_V), the singular value decomposition of the
+ * small core M = R_U diag(A_X, B_X) R_V^T = X S Y^T, truncation to the k
+ * largest singular values with sigma_i > tol * sigma_1, k <= kmax, and the
+ * new bases U = Q_U X_k, V = Q_V Y_k.  The result is A + B ~ U diag(sigma)
+ * V^T: the rounded addition whose first step is the low-rank product of
+ * Alg. 1 (Sec. 2).  FP64.
+ *   b, ra, rb     : host arrays [count]; ra + rb <= 64.
+ *   AU, AV        : device b x ra.   AX: device ra x ra.
+ *   BU, BV        : device b x rb.   BX: device rb x rb.
+ *   kmax, tol     : 1 <= kmax <= 64; relative truncation threshold tol >= 0.
+ *   U, V, sigma, kout : as lr_batched_lrmult_round (U, V b x kmax, zero
+ *                   beyond the kept rank; sigma [count * kmax] descending;
+ *                   kout [count]).
+ * Errors as lr_batched_lrmult_round; in addition every output (U, V,
+ * sigma, kout) must be disjoint from the others and from every input.
+ * Uniqueness as lr_batched_lrmult_round.  Scratch for the reflectors, the
+ * factors and the cores is allocated by the library (pooled, reused once
+ * the call's work has run).
+ */
+lrbg_status lr_batched_lradd_round(int64_t count, const int32_t *b, const int32_t *ra, const int32_t *rb,
+                                   const double *const *AU, const int32_t *ldau,
+                                   const double *const *AV, const int32_t *ldav,
+                                   const double *const *AX, const int32_t *ldax,
+                                   const double *const *BU, const int32_t *ldbu,
+                                   const double *const *BX, const int32_t *ldbx,
+                                   const double *const *BV, const int32_t *ldbv,
+                                   int32_t kmax, double tol,
+                                   double *const *U, const int32_t *ldu,
+                                   double *const *V, const int32_t *ldv,
+                                   double *sigma, int32_t *kout, void *stream);
+
+/*
  * lrbg_round_plan -- lr_batched_lrmult_round built once and replayed: the
  * same arguments (without the stream), validated and scheduled at creation;
  * the plan owns the scratch for G, X, Y, the schedules of the fused core

@@ -34,7 +34,8 @@ def _run(cmd, verbose):
         print("\n".join(msgs))
 
 
-SOURCES = ("lrbg_kernels.hip", "lrbg_lrmult.hip", "lrbg_round.hip", "lrbg_short.hip", "lrbg_host.cpp")
+SOURCES = ("lrbg_kernels.hip", "lrbg_lrmult.hip", "lrbg_round.hip", "lrbg_short.hip", "lrbg_add.hip",
+           "lrbg_host.cpp")
 
 
 def build(verbose: bool = False) -> str:

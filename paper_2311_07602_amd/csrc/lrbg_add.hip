@@ -1,0 +1,338 @@
+// Rounded addition of two low-rank blocks: a batched QR of the stacked
+// bases, the small core, its truncated SVD (the kernel of lrbg_round.hip)
+// and the new bases.
+//
+// The sum of A = A_U A_X A_V^T and B = B_U B_X B_V^T (b x b blocks of ranks
+// ra and rb, bases of any conditioning) is
+//   A + B = [A_U | B_U] diag(A_X, B_X) [A_V | B_V]^T.
+// With the thin QR factorisations [A_U | B_U] = Q_U R_U and
+// [A_V | B_V] = Q_V R_V this is Q_U M Q_V^T with the s x s core
+// M = R_U diag(A_X, B_X) R_V^T (s = ra + rb); the SVD M = X S Y^T truncated
+// to k terms gives A + B ~ (Q_U X_k) S_k (Q_V Y_k)^T.  This is the rounded
+// addition whose first step Sec. 2 names the low-rank product to be.
+//
+// QR (one wavefront per stacked basis, s <= 64, lane c owns column c): the
+// basis is read from HBM once, top to bottom.  Its first s0 = min(s, b) rows
+// are reduced in LDS by Householder reflections with pivots on the diagonal;
+// every later block of kQrRows rows is then reduced against the running
+// triangular factor R.  Reflection j of a block acts on row j of R and on
+// the block's rows only, v = [e_j; y_j] (R is triangular), so the block's
+// columns stay in the lanes' registers: the lane owning column j forms the
+// reflection from its own registers and R_jj, publishes y_j through LDS,
+// and every lane to its right applies it to its column.  Reflections follow
+// LAPACK's convention: beta = -sign(alpha) sqrt(alpha^2 + |x|^2),
+// tau = (beta - alpha) / beta, y = x / (alpha - beta); tau = 0 when x = 0.
+// The reflectors and taus go to scratch; Q is never formed.  Every
+// transformation is an orthogonal map of the basis's own rows, so Q has
+// orthonormal columns to working precision whatever the conditioning of the
+// basis (an exactly rank-deficient stack -- two blocks sharing a basis --
+// included).
+//
+// Core (one wavefront per instance): E = R_U diag(A_X, B_X) column by column
+// in registers, then M = E R_V^T.
+//
+// New bases (one wavefront per stacked basis, lane c owns output column c <
+// kmax): U = Q [X_k; 0], applying the stored reflections in reverse order:
+// blocks from the last to the first, each producing its kQrRows output rows
+// in registers while updating the s x kmax top part Z in LDS, then the
+// reflections of the first s0 rows on Z, which gives the top s0 rows.
+#include "lrbg_tiles.h"
+
+namespace lrbg {
+
+template <int S>
+__global__ void __launch_bounds__(64) lrbg_qr_factor_kernel(const QrDesc *__restrict__ descs, int count)
+{
+    if ((int)blockIdx.x >= count) return;
+    const QrDesc d = descs[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int c0 = d.c0, s = d.c0 + d.c1, b = d.b, s0 = s < b ? s : b;
+    __shared__ double R[S * S];        // first rows, then the triangular factor; row-major, stride S
+    __shared__ double xs[kQrRows];     // tail of the current reflection
+    __shared__ double sh_tau;
+    const bool mine = lane < s;
+    gcp cp = (gcp)(lane < c0 ? d.w0 + (size_t)lane * d.ld0 : mine ? d.w1 + (size_t)(lane - c0) * d.ld1 : d.w0);
+    gp ws = (gp)d.ws;
+    gp tau0 = ws + (size_t)s * s;
+    gp T = tau0 + s;
+    gp blk = T + (size_t)s0 * s;
+
+    // ---- first s0 rows: Householder QR in LDS, pivots on the diagonal
+    if (lane < S)
+        for (int i = 0; i < S; ++i) R[i * S + lane] = (mine && i < s0) ? cp[i] : 0.0;
+    __syncthreads();
+    double my_tau = 0.0;
+    for (int j = 0; j < s0; ++j) {
+        if (lane == j) {
+            const double alpha = R[j * S + j];
+            double nrm2 = 0.0;
+            for (int i = j + 1; i < s0; ++i) nrm2 += R[i * S + j] * R[i * S + j];
+            double tau = 0.0;
+            if (nrm2 > 0.0) {
+                const double beta = -copysign(sqrt(alpha * alpha + nrm2), alpha);
+                tau = (beta - alpha) / beta;
+                const double scale = 1.0 / (alpha - beta);
+                for (int i = j + 1; i < s0; ++i) R[i * S + j] *= scale;
+                R[j * S + j] = beta;
+            }
+            sh_tau = tau;
+            my_tau = tau;
+        }
+        __syncthreads();
+        const double tau = sh_tau;
+        if (tau != 0.0 && lane > j && lane < s) {
+            double w = R[j * S + lane];
+            for (int i = j + 1; i < s0; ++i) w += R[i * S + j] * R[i * S + lane];
+            const double tw = tau * w;
+            R[j * S + lane] -= tw;
+            for (int i = j + 1; i < s0; ++i) R[i * S + lane] -= tw * R[i * S + j];
+        }
+        __syncthreads();
+    }
+    if (mine) {
+        for (int i = 0; i < s0; ++i) T[(size_t)i * s + lane] = R[i * S + lane];
+        tau0[lane] = my_tau;
+    }
+    // keep the triangle: R below the diagonal becomes zero
+    if (lane < S)
+        for (int i = lane + 1; i < S; ++i) R[i * S + lane] = 0.0;
+    __syncthreads();
+
+    // ---- later blocks: reflections [e_j; y_j] against R, columns in registers
+    gp bp = blk;
+    for (int r0 = s0; r0 < b; r0 += kQrRows, bp += s + (size_t)kQrRows * s) {
+        const int hb = b - r0 < kQrRows ? b - r0 : kQrRows;
+        double x[kQrRows];
+        if (hb == kQrRows) {
+#pragma unroll
+            for (int i = 0; i < kQrRows; ++i) x[i] = mine ? cp[r0 + i] : 0.0;
+        } else {
+#pragma unroll
+            for (int i = 0; i < kQrRows; ++i) x[i] = (mine && i < hb) ? cp[r0 + i] : 0.0;
+        }
+        double my_t = 0.0;
+        for (int j = 0; j < s; ++j) {
+            if (lane == j) {
+                double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0;
+#pragma unroll
+                for (int i = 0; i < kQrRows; i += 4) {
+                    n0 += x[i] * x[i];
+                    n1 += x[i + 1] * x[i + 1];
+                    n2 += x[i + 2] * x[i + 2];
+                    n3 += x[i + 3] * x[i + 3];
+                }
+                const double nrm2 = (n0 + n1) + (n2 + n3);
+                const double alpha = R[j * S + j];
+                double tau = 0.0, scale = 0.0;
+                if (nrm2 > 0.0) {
+                    const double beta = -copysign(sqrt(alpha * alpha + nrm2), alpha);
+                    tau = (beta - alpha) / beta;
+                    scale = 1.0 / (alpha - beta);
+                    R[j * S + j] = beta;
+                }
+#pragma unroll
+                for (int i = 0; i < kQrRows; ++i) {
+                    x[i] *= scale;
+                    xs[i] = x[i];
+                }
+                sh_tau = tau;
+                my_t = tau;
+            }
+            __syncthreads();
+            const double tau = sh_tau;
+            if (tau != 0.0 && lane > j && lane < s) {
+                double w0 = R[j * S + lane], w1 = 0.0, w2 = 0.0, w3 = 0.0;
+#pragma unroll
+                for (int i = 0; i < kQrRows; i += 4) {
+                    w0 += xs[i] * x[i];
+                    w1 += xs[i + 1] * x[i + 1];
+                    w2 += xs[i + 2] * x[i + 2];
+                    w3 += xs[i + 3] * x[i + 3];
+                }
+                const double tw = tau * ((w0 + w1) + (w2 + w3));
+                R[j * S + lane] -= tw;
+#pragma unroll
+                for (int i = 0; i < kQrRows; ++i) x[i] -= tw * xs[i];
+            }
+            __syncthreads();
+        }
+        if (mine) {
+            gp Y = bp + s + (size_t)lane * kQrRows;
+#pragma unroll
+            for (int i = 0; i < kQrRows; ++i) Y[i] = x[i];
+            bp[lane] = my_t;
+        }
+    }
+    if (mine)
+        for (int i = 0; i < s; ++i) ws[(size_t)i * s + lane] = R[i * S + lane];
+}
+
+template <int S>
+__global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restrict__ descs, int count)
+{
+    if ((int)blockIdx.x >= count) return;
+    const QrDesc d = descs[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int s = d.c0 + d.c1, b = d.b, s0 = s < b ? s : b, km = d.kmax;
+    __shared__ double Z[S * 64];          // s x kmax top part, Z[j * 64 + c]
+    __shared__ double Yl[kQrRows * S];    // a block's reflection tails (column j at j * kQrRows)
+    __shared__ double tl[S];
+    const bool mine = lane < km;
+    gcp xk = (gcp)d.xk;
+    for (int j = 0; j < S; ++j) Z[j * 64 + lane] = (mine && j < s) ? xk[j + (size_t)lane * s] : 0.0;
+    gcp ws = (gcp)d.ws;
+    gcp tau0 = ws + (size_t)s * s;
+    gcp T = tau0 + s;
+    gcp blk = T + (size_t)s0 * s;
+    const int nblk = b > s0 ? (b - s0 + kQrRows - 1) / kQrRows : 0;
+    for (int bi = nblk - 1; bi >= 0; --bi) {
+        gcp bp = blk + (size_t)bi * (s + (size_t)kQrRows * s);
+        const int r0 = s0 + bi * kQrRows, hb = b - r0 < kQrRows ? b - r0 : kQrRows;
+        __syncthreads();                  // the previous block's reads of Yl are done
+        for (int e = lane; e < s * kQrRows; e += 64) Yl[e] = bp[s + e];
+        if (lane < s) tl[lane] = bp[lane];
+        __syncthreads();
+        double u[kQrRows];
+#pragma unroll
+        for (int i = 0; i < kQrRows; ++i) u[i] = 0.0;
+        for (int j = s - 1; j >= 0; --j) {
+            const double tau = tl[j];
+            if (tau == 0.0) continue;
+            const double *y = Yl + j * kQrRows;
+            double w0 = Z[j * 64 + lane], w1 = 0.0, w2 = 0.0, w3 = 0.0;
+#pragma unroll
+            for (int i = 0; i < kQrRows; i += 4) {
+                w0 += y[i] * u[i];
+                w1 += y[i + 1] * u[i + 1];
+                w2 += y[i + 2] * u[i + 2];
+                w3 += y[i + 3] * u[i + 3];
+            }
+            const double tw = tau * ((w0 + w1) + (w2 + w3));
+            Z[j * 64 + lane] -= tw;
+#pragma unroll
+            for (int i = 0; i < kQrRows; ++i) u[i] -= tw * y[i];
+        }
+        if (mine) {
+            gp o = (gp)d.out + (size_t)lane * d.ldo + r0;
+            if (hb == kQrRows) {
+#pragma unroll
+                for (int i = 0; i < kQrRows; ++i) o[i] = u[i];
+            } else {
+#pragma unroll
+                for (int i = 0; i < kQrRows; ++i)
+                    if (i < hb) o[i] = u[i];
+            }
+        }
+    }
+    // the first s0 rows: reflections with pivots on the diagonal
+    __syncthreads();
+    for (int e = lane; e < s0 * s; e += 64) Yl[e] = T[e];
+    if (lane < s) tl[lane] = tau0[lane];
+    __syncthreads();
+    for (int j = s0 - 1; j >= 0; --j) {
+        const double tau = tl[j];
+        if (tau == 0.0) continue;
+        double w = Z[j * 64 + lane];
+        for (int i = j + 1; i < s0; ++i) w += Yl[i * s + j] * Z[i * 64 + lane];
+        const double tw = tau * w;
+        Z[j * 64 + lane] -= tw;
+        for (int i = j + 1; i < s0; ++i) Z[i * 64 + lane] -= tw * Yl[i * s + j];
+    }
+    if (mine) {
+        gp o = (gp)d.out + (size_t)lane * d.ldo;
+        for (int i = 0; i < s0; ++i) o[i] = Z[i * 64 + lane];
+    }
+}
+
+template <int S>
+__global__ void __launch_bounds__(64) lrbg_add_core_kernel(const AddCoreDesc *__restrict__ descs, int count)
+{
+    if ((int)blockIdx.x >= count) return;
+    const AddCoreDesc d = descs[blockIdx.x];
+    const int lane = threadIdx.x, ra = d.ra, rb = d.rb, s = d.ra + d.rb;
+    __shared__ double RU[S * S];    // R_U, then E = R_U diag(A_X, B_X); row-major, stride S
+    __shared__ double RVt[S * S];   // R_V transposed: RVt[l * S + c] = R_V(c, l)
+    gcp ru = (gcp)d.ru, rv = (gcp)d.rv;
+    for (int e = lane; e < s * s; e += 64) {
+        const int i = e / s, c = e % s;
+        RU[i * S + c] = ru[e];
+        RVt[c * S + i] = rv[e];
+    }
+    __syncthreads();
+    // E(:, l) = R_U(:, block of l) * D(block of l, l), lane l
+    double e_[S];
+#pragma unroll
+    for (int i = 0; i < S; ++i) e_[i] = 0.0;
+    if (lane < ra) {
+        gcp ax = (gcp)d.ax + (size_t)lane * d.ldax;
+        for (int m = 0; m < ra; ++m) {
+            const double dx = ax[m];
+#pragma unroll
+            for (int i = 0; i < S; ++i) e_[i] += RU[i * S + m] * dx;
+        }
+    } else if (lane < s) {
+        gcp bx = (gcp)d.bx + (size_t)(lane - ra) * d.ldbx;
+        for (int m = 0; m < rb; ++m) {
+            const double dx = bx[m];
+#pragma unroll
+            for (int i = 0; i < S; ++i) e_[i] += RU[i * S + ra + m] * dx;
+        }
+    }
+    __syncthreads();
+    if (lane < S) {
+#pragma unroll
+        for (int i = 0; i < S; ++i) RU[i * S + lane] = e_[i];
+    }
+    __syncthreads();
+    // M(:, c) = sum_l E(:, l) R_V(c, l), lane c
+    if (lane < s) {
+        double mc[S];
+#pragma unroll
+        for (int i = 0; i < S; ++i) mc[i] = 0.0;
+        for (int l = 0; l < s; ++l) {
+            const double v = RVt[l * S + lane];
+#pragma unroll
+            for (int i = 0; i < S; ++i) mc[i] += RU[i * S + l] * v;
+        }
+        gp g = (gp)d.g + (size_t)lane * s;
+#pragma unroll
+        for (int i = 0; i < S; ++i)
+            if (i < s) g[i] = mc[i];
+    }
+}
+
+template <typename D, typename K16, typename K32, typename K64>
+static int launch_by_class(int cols, const D *descs, int count, void *stream, K16 k16, K32 k32, K64 k64)
+{
+    if (count <= 0) return 0;
+    hipStream_t st = (hipStream_t)stream;
+    if (cols == 16)
+        hipLaunchKernelGGL(k16, dim3(count), dim3(64), 0, st, descs, count);
+    else if (cols == 32)
+        hipLaunchKernelGGL(k32, dim3(count), dim3(64), 0, st, descs, count);
+    else if (cols == 64)
+        hipLaunchKernelGGL(k64, dim3(count), dim3(64), 0, st, descs, count);
+    else
+        return (int)hipErrorInvalidValue;
+    return (int)hipGetLastError();
+}
+
+int launch_qr_factor(int cols, const QrDesc *descs, int count, void *stream)
+{
+    return launch_by_class(cols, descs, count, stream, lrbg_qr_factor_kernel<16>, lrbg_qr_factor_kernel<32>,
+                           lrbg_qr_factor_kernel<64>);
+}
+
+int launch_qr_apply(int cols, const QrDesc *descs, int count, void *stream)
+{
+    return launch_by_class(cols, descs, count, stream, lrbg_qr_apply_kernel<16>, lrbg_qr_apply_kernel<32>,
+                           lrbg_qr_apply_kernel<64>);
+}
+
+int launch_add_core(int cols, const AddCoreDesc *descs, int count, void *stream)
+{
+    return launch_by_class(cols, descs, count, stream, lrbg_add_core_kernel<16>, lrbg_add_core_kernel<32>,
+                           lrbg_add_core_kernel<64>);
+}
+
+}  // namespace lrbg

@@ -993,13 +993,33 @@ static Staging *acquire_staging(size_t bytes, bool with_host = true)
         best->recorded = false;
         return best;
     }
+    // small buffers by powers of two, large ones by 64 MiB steps (a power of
+    // two would hold up to twice a large scratch's size)
     size_t cap = 4096;
-    while (cap < bytes) cap *= 2;
+    while (cap < bytes && cap < (size_t(64) << 20)) cap *= 2;
+    if (cap < bytes) cap = (bytes + (size_t(64) << 20) - 1) / (size_t(64) << 20) * (size_t(64) << 20);
     Staging *st = new (std::nothrow) Staging();
     if (!st) return nullptr;
     if (hipMalloc(&st->dev, cap) != hipSuccess) {
-        delete st;
-        return nullptr;
+        // out of device memory: return the idle buffers of the pool, then retry once
+        (void)hipGetLastError();
+        for (size_t q = 0; q < g_staging.size();) {
+            Staging *o = g_staging[q];
+            if (!o->in_use) {
+                (void)hipFree(o->dev);
+                if (o->host) (void)hipHostFree(o->host);
+                if (o->ev) (void)hipEventDestroy(o->ev);
+                delete o;
+                g_staging.erase(g_staging.begin() + (std::ptrdiff_t)q);
+            } else {
+                ++q;
+            }
+        }
+        if (hipMalloc(&st->dev, cap) != hipSuccess) {
+            (void)hipGetLastError();
+            delete st;
+            return nullptr;
+        }
     }
     if ((with_host && hipHostMalloc(&st->host, cap, hipHostMallocDefault) != hipSuccess) ||
         hipEventCreateWithFlags(&st->ev, hipEventDisableTiming) != hipSuccess) {
@@ -1274,6 +1294,263 @@ static lrbg_status lrmult_round(const RoundArgs &a, hipStream_t stream)
     return st;
 }
 
+
+// The sum of two low-rank blocks recompressed (see lr_batched_lradd_round):
+// QR of both stacked bases, the core M = R_U diag(A_X, B_X) R_V^T, its
+// truncated SVD, and the new bases Q_U X_k and Q_V Y_k; the kernels are in
+// lrbg_add.hip, the SVD is the recompressed product's.  Scratch per
+// instance: both stacked bases' reflectors and factors, M, X, Y.
+
+static int width_class(int s) { return s <= 16 ? 0 : s <= 32 ? 1 : 2; }
+static const int kWidthClasses[3] = {16, 32, 64};
+
+struct AddBuild {
+    size_t total = 0;
+    std::vector<size_t> owu, owv, og, ox, oy;
+    std::vector<QrDesc> qr[3];
+    std::vector<AddCoreDesc> core[3];
+    std::vector<SvdDesc> sv[3];
+};
+
+// Outputs must be disjoint from each other and from every input: a sweep
+// over the operands ordered by first byte, testing element-exact overlap
+// only between operands whose byte spans meet.
+static lrbg_status check_disjoint(std::vector<std::pair<Mat, bool>> &ops)
+{
+    std::sort(ops.begin(), ops.end(), [](const std::pair<Mat, bool> &x, const std::pair<Mat, bool> &y) {
+        return x.first.range().lo < y.first.range().lo;
+    });
+    std::vector<const std::pair<Mat, bool> *> active;
+    for (const auto &op : ops) {
+        if (op.first.empty()) continue;
+        const Range r = op.first.range();
+        size_t keep = 0;
+        for (size_t q = 0; q < active.size(); ++q)
+            if (active[q]->first.range().hi > r.lo) active[keep++] = active[q];
+        active.resize(keep);
+        for (const auto *o : active)
+            if ((op.second || o->second) && mats_overlap(op.first, o->first))
+                return fail(LRBG_EINVAL, "an output overlaps %s (products %lld and %lld)",
+                            op.second && o->second ? "another output" : "an input", (long long)o->first.idx,
+                            (long long)op.first.idx);
+        active.push_back(&op);
+    }
+    return LRBG_OK;
+}
+
+static lrbg_status add_validate(const RoundArgs &a)
+{
+    const int64_t n = a.count;
+    if (n < 0) return fail(LRBG_EINVAL, "negative count");
+    if (n == 0) return LRBG_OK;
+    if (!a.b || !a.ra || !a.rb || !a.AU || !a.AV || !a.AX || !a.BU || !a.BX || !a.BV || !a.ldau || !a.ldav ||
+        !a.ldax || !a.ldbu || !a.ldbx || !a.ldbv || !a.U || !a.V || !a.ldu || !a.ldv)
+        return fail(LRBG_EINVAL, "a required host array is NULL");
+    if (!a.sigma || !a.kout) return fail(LRBG_EINVAL, "sigma and kout must be device arrays");
+    if ((uintptr_t)a.sigma % 8 || (uintptr_t)a.kout % 4) return fail(LRBG_EINVAL, "sigma or kout misaligned");
+    if (a.kmax < 1 || a.kmax > kQrMaxCols) return fail(LRBG_EUNSUPPORTED, "kmax must be in [1, %d]", kQrMaxCols);
+    if (!(a.tol >= 0.0) || !std::isfinite(a.tol)) return fail(LRBG_EINVAL, "tol must be finite and >= 0");
+    std::vector<std::pair<Mat, bool>> ops;
+    ops.reserve((size_t)n * 8 + 2);
+    for (int64_t t = 0; t < n; ++t) {
+        const int b = a.b[t], ra = a.ra[t], rb = a.rb[t], km = a.kmax;
+        if (b < 0 || ra < 0 || rb < 0) return fail(LRBG_EINVAL, "product %lld: negative size", (long long)t);
+        if (ra + rb > kQrMaxCols)
+            return fail(LRBG_EUNSUPPORTED, "product %lld: ra + rb = %d exceeds %d", (long long)t, ra + rb,
+                        kQrMaxCols);
+        if (b > kMaxBlock)
+            return fail(LRBG_EUNSUPPORTED, "product %lld: block dimension %d exceeds %d", (long long)t, b, kMaxBlock);
+        const void *ptr[8] = {a.AU[t], a.AV[t], a.AX[t], a.BU[t], a.BX[t], a.BV[t], a.U[t], a.V[t]};
+        const int ld[8] = {a.ldau[t], a.ldav[t], a.ldax[t], a.ldbu[t], a.ldbx[t], a.ldbv[t], a.ldu[t], a.ldv[t]};
+        const int rows[8] = {b, b, ra, b, rb, b, b, b}, cols[8] = {ra, ra, ra, rb, rb, rb, km, km};
+        const char *nm[8] = {"A_U", "A_V", "A_X", "B_U", "B_X", "B_V", "U", "V"};
+        for (int q = 0; q < 8; ++q) {
+            if (ld[q] < std::max(1, rows[q]))
+                return fail(LRBG_EINVAL, "product %lld: ld of %s = %d < rows = %d", (long long)t, nm[q], ld[q],
+                            rows[q]);
+            if (rows[q] > 0 && cols[q] > 0) {
+                if (!ptr[q]) return fail(LRBG_EINVAL, "product %lld: %s is NULL", (long long)t, nm[q]);
+                if ((uintptr_t)ptr[q] % 8)
+                    return fail(LRBG_EINVAL, "product %lld: %s not 8-byte aligned", (long long)t, nm[q]);
+            }
+            ops.emplace_back(mat_of(ptr[q], rows[q], cols[q], ld[q], 8, t), q >= 6);
+        }
+    }
+    Mat sg, ko;
+    sg.p = (uintptr_t)a.sigma;
+    sg.cols = 1;
+    sg.row_bytes = sg.ld_bytes = (uintptr_t)n * (uintptr_t)a.kmax * 8;
+    ko.p = (uintptr_t)a.kout;
+    ko.cols = 1;
+    ko.row_bytes = ko.ld_bytes = (uintptr_t)n * 4;
+    ops.emplace_back(sg, true);
+    ops.emplace_back(ko, true);
+    return check_disjoint(ops);
+}
+
+static void add_layout(const RoundArgs &a, AddBuild &ab)
+{
+    const size_t n = (size_t)a.count;
+    ab.total = 0;
+    auto take = [&](size_t elems) {
+        const size_t o = ab.total;
+        ab.total += (elems * 8 + 255) / 256 * 256;
+        return o;
+    };
+    ab.owu.resize(n);
+    ab.owv.resize(n);
+    ab.og.resize(n);
+    ab.ox.resize(n);
+    ab.oy.resize(n);
+    for (size_t t = 0; t < n; ++t) {
+        const int s = a.ra[t] + a.rb[t];
+        ab.owu[t] = take(qr_scratch_doubles(a.b[t], s));
+        ab.owv[t] = take(qr_scratch_doubles(a.b[t], s));
+        ab.og[t] = take((size_t)s * s);
+        ab.ox[t] = take((size_t)s * a.kmax);
+        ab.oy[t] = take((size_t)s * a.kmax);
+    }
+    ab.total = std::max<size_t>(ab.total, 256);
+}
+
+static void add_build(const RoundArgs &a, char *base, AddBuild &ab)
+{
+    for (int c = 0; c < 3; ++c) {
+        ab.qr[c].clear();
+        ab.core[c].clear();
+        ab.sv[c].clear();
+    }
+    for (int64_t t = 0; t < a.count; ++t) {
+        const int ra = a.ra[t], rb = a.rb[t], s = ra + rb, c = width_class(s);
+        double *wu = (double *)(base + ab.owu[t]), *wv = (double *)(base + ab.owv[t]);
+        double *G = (double *)(base + ab.og[t]), *X = (double *)(base + ab.ox[t]), *Y = (double *)(base + ab.oy[t]);
+        QrDesc u{}, v{};
+        u.w0 = a.AU[t];
+        u.ld0 = a.ldau[t];
+        u.w1 = a.BU[t];
+        u.ld1 = a.ldbu[t];
+        u.ws = wu;
+        u.xk = X;
+        u.out = a.U[t];
+        u.ldo = a.ldu[t];
+        v.w0 = a.AV[t];
+        v.ld0 = a.ldav[t];
+        v.w1 = a.BV[t];
+        v.ld1 = a.ldbv[t];
+        v.ws = wv;
+        v.xk = Y;
+        v.out = a.V[t];
+        v.ldo = a.ldv[t];
+        u.b = v.b = a.b[t];
+        u.c0 = v.c0 = ra;
+        u.c1 = v.c1 = rb;
+        u.kmax = v.kmax = a.kmax;
+        ab.qr[c].push_back(u);
+        ab.qr[c].push_back(v);
+        AddCoreDesc cd{};
+        cd.ru = wu;
+        cd.rv = wv;
+        cd.ax = a.AX[t];
+        cd.bx = a.BX[t];
+        cd.ldax = a.ldax[t];
+        cd.ldbx = a.ldbx[t];
+        cd.g = G;
+        cd.ra = ra;
+        cd.rb = rb;
+        ab.core[c].push_back(cd);
+        SvdDesc sd{};
+        sd.g = G;
+        sd.x = X;
+        sd.y = Y;
+        sd.sigma = a.sigma + t * a.kmax;
+        sd.kout = a.kout + t;
+        sd.tol = a.tol;
+        sd.m = sd.n = s;
+        sd.ldg = sd.ldx = sd.ldy = std::max(s, 1);
+        sd.kmax = a.kmax;
+        ab.sv[c].push_back(sd);
+    }
+}
+
+// Device tables of a built addition, packed in one upload: per width class
+// the QR descriptors, the core descriptors, the SVD descriptors.
+struct AddTables {
+    size_t bytes = 0;
+    size_t oq[3], oc[3], os[3];
+};
+
+static AddTables add_tables(const AddBuild &ab)
+{
+    AddTables tb;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) / 256 * 256;
+        return o;
+    };
+    for (int c = 0; c < 3; ++c) {
+        tb.oq[c] = take(ab.qr[c].size() * sizeof(QrDesc));
+        tb.oc[c] = take(ab.core[c].size() * sizeof(AddCoreDesc));
+        tb.os[c] = take(ab.sv[c].size() * sizeof(SvdDesc));
+    }
+    tb.bytes = std::max<size_t>(off, 256);
+    return tb;
+}
+
+static void add_pack(const AddBuild &ab, const AddTables &tb, char *host)
+{
+    for (int c = 0; c < 3; ++c) {
+        memcpy(host + tb.oq[c], ab.qr[c].data(), ab.qr[c].size() * sizeof(QrDesc));
+        memcpy(host + tb.oc[c], ab.core[c].data(), ab.core[c].size() * sizeof(AddCoreDesc));
+        memcpy(host + tb.os[c], ab.sv[c].data(), ab.sv[c].size() * sizeof(SvdDesc));
+    }
+}
+
+static lrbg_status add_launches(const AddBuild &ab, const AddTables &tb, const char *dev, hipStream_t stream)
+{
+    int rc = 0;
+    for (int c = 0; c < 3 && !rc; ++c)
+        rc = launch_qr_factor(kWidthClasses[c], (const QrDesc *)(dev + tb.oq[c]), (int)ab.qr[c].size(), stream);
+    for (int c = 0; c < 3 && !rc; ++c)
+        rc = launch_add_core(kWidthClasses[c], (const AddCoreDesc *)(dev + tb.oc[c]), (int)ab.core[c].size(),
+                             stream);
+    for (int c = 0; c < 3 && !rc; ++c)
+        rc = launch_core_svd(kWidthClasses[c], (const SvdDesc *)(dev + tb.os[c]), (int)ab.sv[c].size(), stream);
+    for (int c = 0; c < 3 && !rc; ++c)
+        rc = launch_qr_apply(kWidthClasses[c], (const QrDesc *)(dev + tb.oq[c]), (int)ab.qr[c].size(), stream);
+    if (rc) return fail(LRBG_EDEVICE, "rounded-addition launch failed: %s", hipGetErrorString((hipError_t)rc));
+    return LRBG_OK;
+}
+
+static lrbg_status lradd_round(const RoundArgs &a, hipStream_t stream)
+{
+    lrbg_status st = add_validate(a);
+    if (st != LRBG_OK || a.count == 0) return st;
+    if (a.count > INT32_MAX / 2) return fail(LRBG_EUNSUPPORTED, "count above %d", INT32_MAX / 2);
+    AddBuild ab;
+    add_layout(a, ab);
+    Staging *scr = acquire_staging(ab.total, false);
+    if (!scr) return fail(LRBG_ENOMEM, "scratch allocation failed");
+    add_build(a, (char *)scr->dev, ab);
+    const AddTables tb = add_tables(ab);
+    Staging *sd = acquire_staging(tb.bytes);
+    if (!sd) {
+        release_staging(scr);
+        return fail(LRBG_ENOMEM, "staging allocation failed");
+    }
+    add_pack(ab, tb, (char *)sd->host);
+    hipError_t e = hipMemcpyAsync(sd->dev, sd->host, tb.bytes, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) st = fail(LRBG_EDEVICE, "hipMemcpyAsync: %s", hipGetErrorString(e));
+    if (st == LRBG_OK) st = add_launches(ab, tb, (const char *)sd->dev, stream);
+    // scratch and tables are released once everything above has run
+    if (record_release(scr, stream) != hipSuccess || record_release(sd, stream) != hipSuccess) {
+        (void)hipStreamSynchronize(stream);
+        release_staging(scr);
+        release_staging(sd);
+    }
+    return st;
+}
+
 }  // namespace lrbg
 
 // A recompressed product built once: scratch, the two sub-plans (launched by
@@ -1371,6 +1648,19 @@ lrbg_status lr_batched_lrmult_round(int64_t count, const int32_t *b, const int32
     RoundArgs a{count, b, ra, rb, AU, AV, AX, BU, BX, BV, ldau, ldav, ldax, ldbu, ldbx, ldbv,
                 kmax, tol, U, V, ldu, ldv, sigma, kout};
     return lrmult_round(a, (hipStream_t)stream);
+}
+
+lrbg_status lr_batched_lradd_round(int64_t count, const int32_t *b, const int32_t *ra, const int32_t *rb,
+                                   const double *const *AU, const int32_t *ldau, const double *const *AV,
+                                   const int32_t *ldav, const double *const *AX, const int32_t *ldax,
+                                   const double *const *BU, const int32_t *ldbu, const double *const *BX,
+                                   const int32_t *ldbx, const double *const *BV, const int32_t *ldbv, int32_t kmax,
+                                   double tol, double *const *U, const int32_t *ldu, double *const *V,
+                                   const int32_t *ldv, double *sigma, int32_t *kout, void *stream)
+{
+    RoundArgs a{count, b, ra, rb, AU, AV, AX, BU, BX, BV, ldau, ldav, ldax, ldbu, ldbx, ldbv,
+                kmax, tol, U, V, ldu, ldv, sigma, kout};
+    return lradd_round(a, (hipStream_t)stream);
 }
 
 lrbg_status lrbg_round_plan_create(lrbg_round_plan **out, int64_t count, const int32_t *b, const int32_t *ra,

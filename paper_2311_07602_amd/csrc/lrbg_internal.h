@@ -2,6 +2,7 @@
 // library: the device descriptor of one product, the tile record of the
 // grouped schedule, and the table of compiled tile variants.
 #pragma once
+#include <stddef.h>
 #include <stdint.h>
 
 namespace lrbg {
@@ -159,6 +160,43 @@ struct SvdDesc {
     int32_t m, n, ldg, ldx, ldy, kmax;
 };
 
+// One stacked basis [W0 | W1] (b x s, s = c0 + c1 <= 64) of a rounded
+// addition: the QR factorisation writes its reflectors and triangular factor
+// to `ws`; the basis update applies them to the singular vectors `xk`
+// (s x kmax, ld s) and writes the new basis `out` (b x kmax, ld ldo).
+struct QrDesc {
+    const double *w0;   // b x c0, ld ld0 (A_U or A_V)
+    const double *w1;   // b x c1, ld ld1 (B_U or B_V)
+    double *ws;         // scratch, qr_scratch_doubles(b, s) doubles
+    const double *xk;
+    double *out;
+    int32_t b, c0, c1, ld0, ld1, ldo, kmax, pad;
+};
+
+// The core of a rounded addition, M = R_U diag(A_X, B_X) R_V^T (s x s).
+struct AddCoreDesc {
+    const double *ru, *rv;   // s x s triangular factors, row-major (scratch)
+    const double *ax, *bx;   // ra x ra (ld ldax), rb x rb (ld ldbx)
+    double *g;               // M, column-major, ld s (scratch)
+    int32_t ra, rb, ldax, ldbx;
+};
+
+// Rows per block of the QR after the first s0 = min(s, b) rows.
+constexpr int kQrRows = 64;
+constexpr int kQrMaxCols = 64;
+
+// Scratch of one stacked basis (doubles): the triangular factor R (s x s,
+// row-major), the first s0 rows' reflector factors (s taus, then the s0 x s
+// reduced rows, row-major: R above the diagonal, reflector tails below),
+// then per block of kQrRows rows s taus and the block's reflector tails
+// (kQrRows x s, column-major).
+inline size_t qr_scratch_doubles(int b, int s)
+{
+    const int s0 = s < b ? s : b;
+    const size_t nblk = b > s0 ? (size_t)(b - s0 + kQrRows - 1) / kQrRows : 0;
+    return (size_t)s * s + s + (size_t)s0 * s + nblk * ((size_t)s + (size_t)kQrRows * s);
+}
+
 // Kernel launch helpers (defined in the lrbg_*.hip kernel sources).
 int launch_persistent(const DevDesc *descs, const Tile *tiles, const int32_t *qinfo,
                       int32_t *counters, int grid, void *stream);
@@ -172,5 +210,9 @@ int launch_short_family(const DevDesc *descs, const Tile *tiles, int ntiles, voi
 int persistent_blocks_per_cu();
 int launch_core_svd(int nmax, const SvdDesc *descs, int count, void *stream);
 int svd_max_dim();
+// Rounded addition: launches for one class of stacked widths (cols in {16, 32, 64}).
+int launch_qr_factor(int cols, const QrDesc *descs, int count, void *stream);
+int launch_qr_apply(int cols, const QrDesc *descs, int count, void *stream);
+int launch_add_core(int cols, const AddCoreDesc *descs, int count, void *stream);
 
 }  // namespace lrbg

@@ -209,6 +209,35 @@ def test_round_entries_validate_before_device_work():
     assert lib.lrbg_round_plan_destroy(None) == 0
 
 
+def test_lradd_validates_before_device_work():
+    """The rounded addition rejects malformed arguments on the host, before
+    any device work (so this runs without a GPU)."""
+    lib = lrbg.load()
+    i32 = lambda *v: (ctypes.c_int32 * len(v))(*v)
+    p = lambda *v: (ctypes.c_void_p * len(v))(*v)
+    b, ra, rb = 256, 16, 8
+    G = 1 << 30
+
+    def args(kmax=8, tol=1e-8, r_a=ra, sigma=BASE + 9 * G, U=BASE + 6 * G, ldu=b, count=1, AX=BASE + 2 * G):
+        return [count, i32(b), i32(r_a), i32(rb),
+                p(BASE), i32(b), p(BASE + G), i32(b), p(AX), i32(r_a),
+                p(BASE + 3 * G), i32(b), p(BASE + 4 * G), i32(rb), p(BASE + 5 * G), i32(b),
+                kmax, tol, p(U), i32(ldu), p(BASE + 7 * G), i32(b), sigma, BASE + 10 * G]
+    cases = [(dict(kmax=0), lrbg.LRBG_EUNSUPPORTED), (dict(kmax=65), lrbg.LRBG_EUNSUPPORTED),
+             (dict(tol=-1.0), lrbg.LRBG_EINVAL), (dict(tol=float("inf")), lrbg.LRBG_EINVAL),
+             (dict(r_a=57), lrbg.LRBG_EUNSUPPORTED), (dict(sigma=BASE + 4), lrbg.LRBG_EINVAL),
+             (dict(count=-1), lrbg.LRBG_EINVAL), (dict(ldu=b - 1), lrbg.LRBG_EINVAL),
+             (dict(U=BASE + 8), lrbg.LRBG_EINVAL),                # U inside A_U
+             (dict(U=BASE + 9 * G - 8), lrbg.LRBG_EINVAL),        # U runs into sigma
+             (dict(AX=BASE + 7 * G + 64), lrbg.LRBG_EINVAL),      # an input inside V
+             (dict(U=0), lrbg.LRBG_EINVAL), (dict(U=BASE + 6 * G + 4), lrbg.LRBG_EINVAL)]
+    for kw, code in cases:
+        assert lib.lr_batched_lradd_round(*args(**kw), None) == code, kw
+    a = args(); a[2] = None
+    assert lib.lr_batched_lradd_round(*a, None) == lrbg.LRBG_EINVAL
+    assert lib.lr_batched_lradd_round(0, *([None] * 15), 4, 0.0, *([None] * 6), None) == 0
+
+
 def test_plan_flags_validated():
     d = [mk()]
     for f in (0, lrbg.LRBG_PLAN_NO_GRAPH, lrbg.LRBG_PLAN_UNTIMED, lrbg.LRBG_PLAN_SCHED_MIX | lrbg.LRBG_PLAN_UNTIMED):

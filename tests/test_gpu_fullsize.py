@@ -225,3 +225,49 @@ def test_round_plan_at_bench_scale_matches_one_shot(r):
     for x, y in zip(outs[0], outs[1]):
         assert torch.equal(x, y)
     assert int(outs[0][3].min()) == kmax
+
+
+@pytest.mark.parametrize("r", [8, 32])
+def test_lradd_at_bench_scale_sampled(r):
+    """The rounded addition at the benchmark's size (20000 instances, b =
+    1024, both ranks r, kept rank <= r, N(0,1) factors): sampled instances
+    against the oracle -- kept rank, singular values within 1e-12 sigma_1,
+    the kept sum, and orthonormal new bases."""
+    import torch
+    from paper_2311_07602_amd import inputs
+    count, b, kmax, tol = 20000, 1024, r, 1e-8
+    per = 4 * b * r + 2 * r * r
+    pin = inputs.device_normal(count * per, seed=27 + r)
+    U = torch.full((count, kmax, b), np.nan, dtype=torch.float64, device="cuda")
+    V = torch.full_like(U, np.nan)
+    sigma = torch.full((count * kmax,), np.nan, dtype=torch.float64, device="cuda")
+    kout = torch.full((count,), -1, dtype=torch.int32, device="cuda")
+    base = pin.data_ptr()
+    off = lambda t, j: base + 8 * (t * per + j * b * r)
+    offs = lambda t, j: base + 8 * (t * per + 4 * b * r + j * r * r)
+    ts = range(count)
+    lrbg.lr_batched_lradd_round([b] * count, [r] * count, [r] * count,
+                                [off(t, 0) for t in ts], [b] * count, [off(t, 1) for t in ts], [b] * count,
+                                [offs(t, 0) for t in ts], [r] * count, [off(t, 2) for t in ts], [b] * count,
+                                [offs(t, 1) for t in ts], [r] * count, [off(t, 3) for t in ts], [b] * count,
+                                kmax, tol, [U[t].data_ptr() for t in ts], [b] * count,
+                                [V[t].data_ptr() for t in ts], [b] * count, sigma.data_ptr(), kout.data_ptr(),
+                                torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    sig = sigma.cpu().numpy().reshape(count, kmax)
+    ks = kout.cpu().numpy()
+    assert np.all(ks == kmax)
+    cm = lambda t0, o, rows, cols: np.asfortranarray(
+        pin[t0 * per + o:t0 * per + o + rows * cols].cpu().numpy().reshape(cols, rows).T)
+    for t in (0, 4321, 19999):
+        AU, AV, BU, BV = (cm(t, j * b * r, b, r) for j in range(4))
+        AX, BX = cm(t, 4 * b * r, r, r), cm(t, 4 * b * r + r * r, r, r)
+        Uo, so, Vo, ko = oracle.lr_add_round(AU, AV, AX, BU, BX, BV, kmax, tol)
+        assert ks[t] == ko
+        assert np.all(np.abs(sig[t] - so) <= 1e-12 * so[0])
+        Ut, Vt = U[t].cpu().numpy().T, V[t].cpu().numpy().T
+        assert np.max(np.abs(Ut.T @ Ut - np.eye(kmax))) <= 1e-12
+        assert np.max(np.abs(Vt.T @ Vt - np.eye(kmax))) <= 1e-12
+        P = Ut @ np.diag(sig[t]) @ Vt.T
+        Po = Uo @ np.diag(so) @ Vo.T
+        assert np.max(np.abs(P - Po)) <= 1e-11 * so[0], t
