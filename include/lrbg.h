@@ -228,6 +228,41 @@ lrbg_status lr_batched_lradd_round(int64_t count, const int32_t *b, const int32_
                                    double *sigma, int32_t *kout, void *stream);
 
 /*
+ * lr_batched_lrmult_round_noalloc -- lr_batched_lrmult_round for callers
+ * that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, same
+ * kernels and schedules, and so the same results bit for bit; the cores G,
+ * the singular vectors X, Y and the launch tables live in a fixed device
+ * array of LRBG_NOALLOC_SCRATCH_BYTES that each GPU holds from the first
+ * call on it until the process ends, instead of library allocations.  The
+ * call allocates no device or pinned host memory; it uploads its tables
+ * with one hipMemcpyAsync from host memory on `stream`.
+ *   Limit: a call whose cores, singular vectors (8 bytes per element of
+ *   each ra x rb core and of the ra x kmax and rb x kmax vector blocks,
+ *   each rounded up to 256 bytes) and tables (about 90 bytes per product
+ *   plus 16 per tile) exceed the array returns LRBG_EUNSUPPORTED before
+ *   anything is launched; split the batch.
+ *   Concurrency: every call on a GPU uses that GPU's one array and leaves
+ *   its contents behind; calls on one stream are ordered, but calls that
+ *   overlap on one GPU (different streams or threads) race and must not be
+ *   issued.  Nothing in the array needs to start at zero (every element a
+ *   call reads, it has written first).
+ */
+#define LRBG_NOALLOC_SCRATCH_BYTES (128ull << 20)
+lrbg_status lr_batched_lrmult_round_noalloc(int64_t count, const int32_t *b, const int32_t *ra,
+                                            const int32_t *rb,
+                                            const double *const *AU, const int32_t *ldau,
+                                            const double *const *AV, const int32_t *ldav,
+                                            const double *const *AX, const int32_t *ldax,
+                                            const double *const *BU, const int32_t *ldbu,
+                                            const double *const *BX, const int32_t *ldbx,
+                                            const double *const *BV, const int32_t *ldbv,
+                                            int32_t kmax, double tol,
+                                            double *const *U, const int32_t *ldu,
+                                            double *const *V, const int32_t *ldv,
+                                            double *sigma, int32_t *kout, void *stream);
+
+/*
  * lrbg_round_plan -- lr_batched_lrmult_round built once and replayed: the
  * same arguments (without the stream), validated and scheduled at creation;
  * the plan owns the scratch for G, X, Y, the schedules of the fused core

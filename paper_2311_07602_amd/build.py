@@ -34,7 +34,7 @@ def _run(cmd, verbose):
         print("\n".join(msgs))
 
 
-SOURCES = ("lrbg_kernels.hip", "lrbg_lrmult.hip", "lrbg_round.hip", "lrbg_short.hip", "lrbg_add.hip",
+SOURCES = ("lrbg_kernels.hip", "lrbg_lrmult.hip", "lrbg_round.hip", "lrbg_short.hip", "lrbg_scratch.hip", "lrbg_add.hip",
            "lrbg_host.cpp")
 
 

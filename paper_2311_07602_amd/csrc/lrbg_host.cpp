@@ -1294,7 +1294,66 @@ static lrbg_status lrmult_round(const RoundArgs &a, hipStream_t stream)
     return st;
 }
 
+// ------------------------- recompressed product without allocation
+// The same kernels and schedules as lrmult_round, with every device buffer
+// the library needs (G, X, Y, the SVD descriptors, both schedules' product
+// descriptors and tile lists) placed in the fixed per-device scratch array:
+// the cores first, then the tables, each 256-byte aligned.  The tables are
+// uploaded with one hipMemcpyAsync from host memory on the caller's stream.
 
+// Launch every level of a schedule whose tables sit at dd / dt.
+static lrbg_status launch_levels_at(const Schedule &sch, const DevDesc *dd, const Tile *dt, hipStream_t stream)
+{
+    for (const Level &lv : sch.levels)
+        for (int f = 0; f < kFamilies; ++f) {
+            const int rc = launch_family(f, dd, dt + lv.off[f], lv.n[f], stream);
+            if (rc) return fail(LRBG_EDEVICE, "grouped launch failed: %s", hipGetErrorString((hipError_t)rc));
+        }
+    return LRBG_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+static lrbg_status lrmult_round_noalloc(const RoundArgs &a, hipStream_t stream)
+{
+    RoundBuild rb;
+    lrbg_status st = round_layout(a, rb);
+    if (st != LRBG_OK || a.count == 0) return st;
+    const size_t cap = noalloc_scratch_bytes();
+    if (rb.total > cap)
+        return fail(LRBG_EUNSUPPORTED, "the cores and singular vectors need %zu bytes of scratch; the fixed "
+                    "scratch holds %zu (split the batch)", rb.total, cap);
+    void *base = nullptr;
+    const int e0 = noalloc_scratch(&base);
+    if (e0) return fail(LRBG_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString((hipError_t)e0));
+    char *scr = (char *)base;
+    st = round_build(a, scr, rb);
+    if (st != LRBG_OK) return st;
+    const size_t nsv = rb.sv.size() * sizeof(SvdDesc);
+    const size_t nd1 = rb.s1.descs.size() * sizeof(DevDesc), nt1 = rb.s1.tiles.size() * sizeof(Tile);
+    const size_t nd2 = rb.s2.descs.size() * sizeof(DevDesc), nt2 = rb.s2.tiles.size() * sizeof(Tile);
+    const size_t o_sv = align256(rb.total), o_d1 = o_sv + align256(nsv), o_t1 = o_d1 + align256(nd1);
+    const size_t o_d2 = o_t1 + align256(nt1), o_t2 = o_d2 + align256(nd2), end = o_t2 + align256(nt2);
+    if (end > cap)
+        return fail(LRBG_EUNSUPPORTED, "the call needs %zu bytes of scratch; the fixed scratch holds %zu "
+                    "(split the batch)", end, cap);
+    std::vector<char> host(end - o_sv);
+    memcpy(host.data(), rb.sv.data(), nsv);
+    memcpy(host.data() + (o_d1 - o_sv), rb.s1.descs.data(), nd1);
+    memcpy(host.data() + (o_t1 - o_sv), rb.s1.tiles.data(), nt1);
+    memcpy(host.data() + (o_d2 - o_sv), rb.s2.descs.data(), nd2);
+    memcpy(host.data() + (o_t2 - o_sv), rb.s2.tiles.data(), nt2);
+    // from pageable host memory: the call returns once the source has been
+    // read, so `host` may go out of scope; the copy stays ordered on `stream`
+    const hipError_t e = hipMemcpyAsync(scr + o_sv, host.data(), host.size(), hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return fail(LRBG_EDEVICE, "hipMemcpyAsync: %s", hipGetErrorString(e));
+    st = launch_levels_at(rb.s1, (const DevDesc *)(scr + o_d1), (const Tile *)(scr + o_t1), stream);
+    if (st == LRBG_OK) st = round_svd_launches(rb.ccount, (const SvdDesc *)(scr + o_sv), stream);
+    if (st == LRBG_OK) st = launch_levels_at(rb.s2, (const DevDesc *)(scr + o_d2), (const Tile *)(scr + o_t2), stream);
+    return st;
+}
+
+// ------------------------------------------------------ rounded addition
 // The sum of two low-rank blocks recompressed (see lr_batched_lradd_round):
 // QR of both stacked bases, the core M = R_U diag(A_X, B_X) R_V^T, its
 // truncated SVD, and the new bases Q_U X_k and Q_V Y_k; the kernels are in
@@ -1661,6 +1720,20 @@ lrbg_status lr_batched_lradd_round(int64_t count, const int32_t *b, const int32_
     RoundArgs a{count, b, ra, rb, AU, AV, AX, BU, BX, BV, ldau, ldav, ldax, ldbu, ldbx, ldbv,
                 kmax, tol, U, V, ldu, ldv, sigma, kout};
     return lradd_round(a, (hipStream_t)stream);
+}
+
+lrbg_status lr_batched_lrmult_round_noalloc(int64_t count, const int32_t *b, const int32_t *ra, const int32_t *rb,
+                                            const double *const *AU, const int32_t *ldau, const double *const *AV,
+                                            const int32_t *ldav, const double *const *AX, const int32_t *ldax,
+                                            const double *const *BU, const int32_t *ldbu, const double *const *BX,
+                                            const int32_t *ldbx, const double *const *BV, const int32_t *ldbv,
+                                            int32_t kmax, double tol, double *const *U, const int32_t *ldu,
+                                            double *const *V, const int32_t *ldv, double *sigma, int32_t *kout,
+                                            void *stream)
+{
+    RoundArgs a{count, b, ra, rb, AU, AV, AX, BU, BX, BV, ldau, ldav, ldax, ldbu, ldbx, ldbv,
+                kmax, tol, U, V, ldu, ldv, sigma, kout};
+    return lrmult_round_noalloc(a, (hipStream_t)stream);
 }
 
 lrbg_status lrbg_round_plan_create(lrbg_round_plan **out, int64_t count, const int32_t *b, const int32_t *ra,

@@ -214,5 +214,8 @@ int svd_max_dim();
 int launch_qr_factor(int cols, const QrDesc *descs, int count, void *stream);
 int launch_qr_apply(int cols, const QrDesc *descs, int count, void *stream);
 int launch_add_core(int cols, const AddCoreDesc *descs, int count, void *stream);
+// The fixed per-device scratch of the allocation-free entry point.
+size_t noalloc_scratch_bytes();
+int noalloc_scratch(void **ptr);
 
 }  // namespace lrbg

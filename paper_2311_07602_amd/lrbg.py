@@ -97,6 +97,8 @@ def load(path: Optional[str] = None):
     lib.lr_batched_lrmult_round.restype = ctypes.c_int
     lib.lr_batched_lradd_round.argtypes = [i64] + [vp] * 15 + [i32, ctypes.c_double] + [vp] * 6 + [vp]
     lib.lr_batched_lradd_round.restype = ctypes.c_int
+    lib.lr_batched_lrmult_round_noalloc.argtypes = [i64] + [vp] * 15 + [i32, ctypes.c_double] + [vp] * 6 + [vp]
+    lib.lr_batched_lrmult_round_noalloc.restype = ctypes.c_int
     lib.lrbg_round_plan_create.argtypes = [P(vp), i64] + [vp] * 15 + [i32, ctypes.c_double] + [vp] * 6
     lib.lrbg_round_plan_create.restype = ctypes.c_int
     lib.lrbg_round_plan_execute.argtypes = [vp, vp]
@@ -213,6 +215,21 @@ def lr_batched_lradd_round(b: Sequence[int], ra: Sequence[int], rb: Sequence[int
     st = load().lr_batched_lradd_round(len(b), *ins, int(kmax), float(tol), *outs, sigma, kout,
                                        _stream_ptr(stream))
     return _check(st, "lr_batched_lradd_round")
+
+
+LRBG_NOALLOC_SCRATCH_BYTES = 128 << 20
+
+
+def lr_batched_lrmult_round_noalloc(b: Sequence[int], ra: Sequence[int], rb: Sequence[int],
+                                    AU, ldau, AV, ldav, AX, ldax, BU, ldbu, BX, ldbx, BV, ldbv,
+                                    kmax: int, tol: float, U, ldu, V, ldv, sigma: int, kout: int,
+                                    stream=None) -> int:
+    """lr_batched_lrmult_round with its scratch in the library's fixed
+    per-GPU array (no device allocation; see include/lrbg.h)."""
+    ins, outs = _round_arrays(b, ra, rb, AU, ldau, AV, ldav, AX, ldax, BU, ldbu, BX, ldbx, BV, ldbv, U, ldu, V, ldv)
+    st = load().lr_batched_lrmult_round_noalloc(len(b), *ins, int(kmax), float(tol), *outs, sigma, kout,
+                                                _stream_ptr(stream))
+    return _check(st, "lr_batched_lrmult_round_noalloc")
 
 
 class RoundPlan:

@@ -199,14 +199,35 @@ def test_round_entries_validate_before_device_work():
     for kw, code in cases:
         a = args(**kw)
         assert lib.lr_batched_lrmult_round(*a, None) == code, kw
+        assert lib.lr_batched_lrmult_round_noalloc(*a, None) == code, kw
         h = ctypes.c_void_p(12345)
         assert lib.lrbg_round_plan_create(ctypes.byref(h), *a) == code, kw
         assert h.value is None                                 # *out cleared on error
     a = args(); a[1] = None                                    # NULL host array
     assert lib.lr_batched_lrmult_round(*a, None) == lrbg.LRBG_EINVAL
     assert lib.lr_batched_lrmult_round(0, *([None] * 15), 4, 0.0, *([None] * 6), None) == 0
+    assert lib.lr_batched_lrmult_round_noalloc(*a, None) == lrbg.LRBG_EINVAL
+    assert lib.lr_batched_lrmult_round_noalloc(0, *([None] * 15), 4, 0.0, *([None] * 6), None) == 0
     assert lib.lrbg_round_plan_execute(None, None) == lrbg.LRBG_EINVAL
     assert lib.lrbg_round_plan_destroy(None) == 0
+
+
+def test_noalloc_round_rejects_batches_beyond_its_scratch():
+    """The allocation-free recompressed product sizes its cores and vectors
+    on the host and refuses a batch that does not fit the fixed array before
+    touching the device: 2000 products of rank 64 with kmax = 64 need
+    3 x 32 KiB each, 188 MiB in all, against 128 MiB."""
+    lib = lrbg.load()
+    n, b, r = 2000, 256, 64
+    ia = lambda v: (ctypes.c_int32 * n)(*([v] * n))
+    pa = lambda base: (ctypes.c_void_p * n)(*[base + t * (1 << 20) for t in range(n)])
+    a = [n, ia(b), ia(r), ia(r)]
+    for j in range(6):
+        a += [pa(BASE + (j << 32)), ia(b if j in (0, 1, 3, 5) else r)]
+    a += [64, 0.0, pa(BASE + (6 << 32)), ia(b), pa(BASE + (7 << 32)), ia(b), BASE + (8 << 32), BASE + (9 << 32)]
+    assert lib.lr_batched_lrmult_round_noalloc(*a, None) == lrbg.LRBG_EUNSUPPORTED
+    msg = lrbg.lrbg_last_error()
+    assert "scratch" in msg and str(lrbg.LRBG_NOALLOC_SCRATCH_BYTES) in msg, msg
 
 
 def test_lradd_validates_before_device_work():
