@@ -40,30 +40,42 @@
 
 namespace lrbg {
 
+// G = 64 / S stacked bases per wavefront, one per group of S lanes (group g
+// = lanes g S .. g S + S - 1, lane c of a group owns column c).  Loops run to
+// the widest case of the class and to the largest block count of the
+// wavefront; a column beyond a basis's width, a row beyond its end and a
+// group without a basis are zeros, whose reflections are the identity
+// (tau = 0), so every group follows the same control flow.
 template <int S>
 __global__ void __launch_bounds__(64) lrbg_qr_factor_kernel(const QrDesc *__restrict__ descs, int count)
 {
-    if ((int)blockIdx.x >= count) return;
-    const QrDesc d = descs[blockIdx.x];
-    const int lane = threadIdx.x;
+    constexpr int G = 64 / S;
+    const int lane = threadIdx.x, g = lane / S, c = lane % S;
+    const int t = (int)blockIdx.x * G + g;
+    QrDesc d{};
+    if (t < count) d = descs[t];
     const int c0 = d.c0, s = d.c0 + d.c1, b = d.b, s0 = s < b ? s : b;
-    __shared__ double R[S * S];        // first rows, then the triangular factor; row-major, stride S
-    __shared__ double xs[kQrRows];     // tail of the current reflection
-    __shared__ double sh_tau;
-    const bool mine = lane < s;
-    gcp cp = (gcp)(lane < c0 ? d.w0 + (size_t)lane * d.ld0 : mine ? d.w1 + (size_t)(lane - c0) * d.ld1 : d.w0);
+    __shared__ double R_[G][S * S];      // first rows, then the triangular factor; row-major, stride S
+    __shared__ double xs_[G][kQrRows];   // the current reflection's unscaled tail
+    __shared__ double tau_[G], sc_[G];
+    __shared__ int nb_[G];
+    double *R = R_[g], *xs = xs_[g];
+    const bool mine = c < s;
+    gcp cp = (gcp)(!mine ? d.w0 : c < c0 ? d.w0 + (size_t)c * d.ld0 : d.w1 + (size_t)(c - c0) * d.ld1);
     gp ws = (gp)d.ws;
     gp tau0 = ws + (size_t)s * s;
     gp T = tau0 + s;
     gp blk = T + (size_t)s0 * s;
+    const int nblk = b > s0 ? (b - s0 + kQrRows - 1) / kQrRows : 0;
+    if (c == 0) nb_[g] = nblk;
 
     // ---- first s0 rows: Householder QR in LDS, pivots on the diagonal
-    if (lane < S)
-        for (int i = 0; i < S; ++i) R[i * S + lane] = (mine && i < s0) ? cp[i] : 0.0;
+    for (int i = 0; i < S; ++i) R[i * S + c] = (mine && i < s0) ? cp[i] : 0.0;
     __syncthreads();
     double my_tau = 0.0;
-    for (int j = 0; j < s0; ++j) {
-        if (lane == j) {
+    for (int j = 0; j < S; ++j) {
+        const bool act = j < s0;
+        if (act && c == j) {
             const double alpha = R[j * S + j];
             double nrm2 = 0.0;
             for (int i = j + 1; i < s0; ++i) nrm2 += R[i * S + j] * R[i * S + j];
@@ -75,44 +87,48 @@ __global__ void __launch_bounds__(64) lrbg_qr_factor_kernel(const QrDesc *__rest
                 for (int i = j + 1; i < s0; ++i) R[i * S + j] *= scale;
                 R[j * S + j] = beta;
             }
-            sh_tau = tau;
+            tau_[g] = tau;
             my_tau = tau;
         }
         __syncthreads();
-        const double tau = sh_tau;
-        if (tau != 0.0 && lane > j && lane < s) {
-            double w = R[j * S + lane];
-            for (int i = j + 1; i < s0; ++i) w += R[i * S + j] * R[i * S + lane];
+        const double tau = act ? tau_[g] : 0.0;
+        if (tau != 0.0 && c > j && mine) {
+            double w = R[j * S + c];
+            for (int i = j + 1; i < s0; ++i) w += R[i * S + j] * R[i * S + c];
             const double tw = tau * w;
-            R[j * S + lane] -= tw;
-            for (int i = j + 1; i < s0; ++i) R[i * S + lane] -= tw * R[i * S + j];
+            R[j * S + c] -= tw;
+            for (int i = j + 1; i < s0; ++i) R[i * S + c] -= tw * R[i * S + j];
         }
         __syncthreads();
     }
     if (mine) {
-        for (int i = 0; i < s0; ++i) T[(size_t)i * s + lane] = R[i * S + lane];
-        tau0[lane] = my_tau;
+        for (int i = 0; i < s0; ++i) T[(size_t)i * s + c] = R[i * S + c];
+        tau0[c] = my_tau;
     }
     // keep the triangle: R below the diagonal becomes zero
-    if (lane < S)
-        for (int i = lane + 1; i < S; ++i) R[i * S + lane] = 0.0;
+    for (int i = c + 1; i < S; ++i) R[i * S + c] = 0.0;
     __syncthreads();
-
-    // ---- later blocks: reflections [e_j; y_j] against R, columns in registers
-    gp bp = blk;
-    for (int r0 = s0; r0 < b; r0 += kQrRows, bp += s + (size_t)kQrRows * s) {
-        const int hb = b - r0 < kQrRows ? b - r0 : kQrRows;
-        double x[kQrRows];
-        if (hb == kQrRows) {
+    int nbmax = 0;
 #pragma unroll
-            for (int i = 0; i < kQrRows; ++i) x[i] = mine ? cp[r0 + i] : 0.0;
+    for (int q = 0; q < G; ++q) nbmax = nb_[q] > nbmax ? nb_[q] : nbmax;
+
+    // ---- later blocks: reflections [e_j; y_j] against R, columns in registers.
+    // The pivot lane publishes its column unscaled with the scale 1 / (alpha -
+    // beta); every lane scales its own column once, when the block is stored.
+    for (int kb = 0; kb < nbmax; ++kb) {
+        const int r0 = s0 + kb * kQrRows;
+        const int hb = kb < nblk ? (b - r0 < kQrRows ? b - r0 : kQrRows) : 0;
+        double x[kQrRows];
+        if (hb == kQrRows && mine) {
+#pragma unroll
+            for (int i = 0; i < kQrRows; ++i) x[i] = cp[r0 + i];
         } else {
 #pragma unroll
             for (int i = 0; i < kQrRows; ++i) x[i] = (mine && i < hb) ? cp[r0 + i] : 0.0;
         }
-        double my_t = 0.0;
-        for (int j = 0; j < s; ++j) {
-            if (lane == j) {
+        double my_t = 0.0, my_sc = 0.0;
+        for (int j = 0; j < S; ++j) {
+            if (c == j) {
                 double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0;
 #pragma unroll
                 for (int i = 0; i < kQrRows; i += 4) {
@@ -131,17 +147,17 @@ __global__ void __launch_bounds__(64) lrbg_qr_factor_kernel(const QrDesc *__rest
                     R[j * S + j] = beta;
                 }
 #pragma unroll
-                for (int i = 0; i < kQrRows; ++i) {
-                    x[i] *= scale;
-                    xs[i] = x[i];
-                }
-                sh_tau = tau;
+                for (int i = 0; i < kQrRows; ++i) xs[i] = x[i];
+                tau_[g] = tau;
+                sc_[g] = scale;
                 my_t = tau;
+                my_sc = scale;
             }
             __syncthreads();
-            const double tau = sh_tau;
-            if (tau != 0.0 && lane > j && lane < s) {
-                double w0 = R[j * S + lane], w1 = 0.0, w2 = 0.0, w3 = 0.0;
+            const double tau = tau_[g];
+            if (tau != 0.0 && c > j) {
+                const double scale = sc_[g];
+                double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
 #pragma unroll
                 for (int i = 0; i < kQrRows; i += 4) {
                     w0 += xs[i] * x[i];
@@ -149,57 +165,75 @@ __global__ void __launch_bounds__(64) lrbg_qr_factor_kernel(const QrDesc *__rest
                     w2 += xs[i + 2] * x[i + 2];
                     w3 += xs[i + 3] * x[i + 3];
                 }
-                const double tw = tau * ((w0 + w1) + (w2 + w3));
-                R[j * S + lane] -= tw;
+                const double tw = tau * (R[j * S + c] + scale * ((w0 + w1) + (w2 + w3)));
+                R[j * S + c] -= tw;
+                const double f = tw * scale;
 #pragma unroll
-                for (int i = 0; i < kQrRows; ++i) x[i] -= tw * xs[i];
+                for (int i = 0; i < kQrRows; ++i) x[i] -= f * xs[i];
             }
             __syncthreads();
         }
-        if (mine) {
-            gp Y = bp + s + (size_t)lane * kQrRows;
+        if (mine && kb < nblk) {
+            gp bp = blk + (size_t)kb * (s + (size_t)kQrRows * s);
+            gp Y = bp + s + (size_t)c * kQrRows;
 #pragma unroll
-            for (int i = 0; i < kQrRows; ++i) Y[i] = x[i];
-            bp[lane] = my_t;
+            for (int i = 0; i < kQrRows; ++i) Y[i] = x[i] * my_sc;
+            bp[c] = my_t;
         }
     }
     if (mine)
-        for (int i = 0; i < s; ++i) ws[(size_t)i * s + lane] = R[i * S + lane];
+        for (int i = 0; i < s; ++i) ws[(size_t)i * s + c] = R[i * S + c];
 }
 
+// As the factorisation, G = 64 / S stacked bases per wavefront; lane c of a
+// group computes output column c < min(kmax, S) (a basis of width s has
+// rank <= s <= S, so any later columns are zero and are filled at the end).
 template <int S>
 __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restrict__ descs, int count)
 {
-    if ((int)blockIdx.x >= count) return;
-    const QrDesc d = descs[blockIdx.x];
-    const int lane = threadIdx.x;
+    constexpr int G = 64 / S;
+    const int lane = threadIdx.x, g = lane / S, c = lane % S;
+    const int t = (int)blockIdx.x * G + g;
+    QrDesc d{};
+    if (t < count) d = descs[t];
     const int s = d.c0 + d.c1, b = d.b, s0 = s < b ? s : b, km = d.kmax;
-    __shared__ double Z[S * 64];          // s x kmax top part, Z[j * 64 + c]
-    __shared__ double Yl[kQrRows * S];    // a block's reflection tails (column j at j * kQrRows)
-    __shared__ double tl[S];
-    const bool mine = lane < km;
+    __shared__ double Z_[G][S * S];            // s x kmax top part, Z[j * S + c]
+    // a block's reflection tails (column j at j * kQrRows), later the first
+    // s0 rows' reduced matrix (s0 x s, s0 <= S): room for the larger
+    constexpr int YL = (kQrRows > S ? kQrRows : S) * S;
+    __shared__ double Yl_[G][YL];
+    __shared__ double tl_[G][S];
+    __shared__ int nb_[G];
+    double *Z = Z_[g], *Yl = Yl_[g], *tl = tl_[g];
+    const bool mine = c < km;
     gcp xk = (gcp)d.xk;
-    for (int j = 0; j < S; ++j) Z[j * 64 + lane] = (mine && j < s) ? xk[j + (size_t)lane * s] : 0.0;
+    for (int j = 0; j < S; ++j) Z[j * S + c] = (mine && j < s) ? xk[j + (size_t)c * s] : 0.0;
     gcp ws = (gcp)d.ws;
     gcp tau0 = ws + (size_t)s * s;
     gcp T = tau0 + s;
     gcp blk = T + (size_t)s0 * s;
     const int nblk = b > s0 ? (b - s0 + kQrRows - 1) / kQrRows : 0;
-    for (int bi = nblk - 1; bi >= 0; --bi) {
-        gcp bp = blk + (size_t)bi * (s + (size_t)kQrRows * s);
-        const int r0 = s0 + bi * kQrRows, hb = b - r0 < kQrRows ? b - r0 : kQrRows;
-        __syncthreads();                  // the previous block's reads of Yl are done
-        for (int e = lane; e < s * kQrRows; e += 64) Yl[e] = bp[s + e];
-        if (lane < s) tl[lane] = bp[lane];
+    if (c == 0) nb_[g] = nblk;
+    __syncthreads();
+    int nbmax = 0;
+#pragma unroll
+    for (int q = 0; q < G; ++q) nbmax = nb_[q] > nbmax ? nb_[q] : nbmax;
+    for (int kb = nbmax - 1; kb >= 0; --kb) {
+        const bool live = kb < nblk;
+        gcp bp = blk + (size_t)kb * (s + (size_t)kQrRows * s);
+        const int r0 = s0 + kb * kQrRows, hb = live ? (b - r0 < kQrRows ? b - r0 : kQrRows) : 0;
+        __syncthreads();                       // the previous block's reads of Yl are done
+        for (int e = c; e < S * kQrRows; e += S) Yl[e] = (live && e < s * kQrRows) ? bp[s + e] : 0.0;
+        tl[c] = (live && c < s) ? bp[c] : 0.0;
         __syncthreads();
         double u[kQrRows];
 #pragma unroll
         for (int i = 0; i < kQrRows; ++i) u[i] = 0.0;
-        for (int j = s - 1; j >= 0; --j) {
+        for (int j = S - 1; j >= 0; --j) {
             const double tau = tl[j];
             if (tau == 0.0) continue;
             const double *y = Yl + j * kQrRows;
-            double w0 = Z[j * 64 + lane], w1 = 0.0, w2 = 0.0, w3 = 0.0;
+            double w0 = Z[j * S + c], w1 = 0.0, w2 = 0.0, w3 = 0.0;
 #pragma unroll
             for (int i = 0; i < kQrRows; i += 4) {
                 w0 += y[i] * u[i];
@@ -208,12 +242,12 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
                 w3 += y[i + 3] * u[i + 3];
             }
             const double tw = tau * ((w0 + w1) + (w2 + w3));
-            Z[j * 64 + lane] -= tw;
+            Z[j * S + c] -= tw;
 #pragma unroll
             for (int i = 0; i < kQrRows; ++i) u[i] -= tw * y[i];
         }
-        if (mine) {
-            gp o = (gp)d.out + (size_t)lane * d.ldo + r0;
+        if (mine && live) {
+            gp o = (gp)d.out + (size_t)c * d.ldo + r0;
             if (hb == kQrRows) {
 #pragma unroll
                 for (int i = 0; i < kQrRows; ++i) o[i] = u[i];
@@ -226,21 +260,26 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
     }
     // the first s0 rows: reflections with pivots on the diagonal
     __syncthreads();
-    for (int e = lane; e < s0 * s; e += 64) Yl[e] = T[e];
-    if (lane < s) tl[lane] = tau0[lane];
+    for (int e = c; e < s0 * s; e += S) Yl[e] = T[e];   // s0 * s <= S * S <= YL
+    tl[c] = c < s ? tau0[c] : 0.0;
     __syncthreads();
-    for (int j = s0 - 1; j >= 0; --j) {
-        const double tau = tl[j];
+    for (int j = S - 1; j >= 0; --j) {
+        const double tau = j < s0 ? tl[j] : 0.0;
         if (tau == 0.0) continue;
-        double w = Z[j * 64 + lane];
-        for (int i = j + 1; i < s0; ++i) w += Yl[i * s + j] * Z[i * 64 + lane];
+        double w = Z[j * S + c];
+        for (int i = j + 1; i < s0; ++i) w += Yl[i * s + j] * Z[i * S + c];
         const double tw = tau * w;
-        Z[j * 64 + lane] -= tw;
-        for (int i = j + 1; i < s0; ++i) Z[i * 64 + lane] -= tw * Yl[i * s + j];
+        Z[j * S + c] -= tw;
+        for (int i = j + 1; i < s0; ++i) Z[i * S + c] -= tw * Yl[i * s + j];
     }
     if (mine) {
-        gp o = (gp)d.out + (size_t)lane * d.ldo;
-        for (int i = 0; i < s0; ++i) o[i] = Z[i * 64 + lane];
+        gp o = (gp)d.out + (size_t)c * d.ldo;
+        for (int i = 0; i < s0; ++i) o[i] = Z[i * S + c];
+    }
+    // output columns S .. kmax - 1 (kmax above the class width): zero
+    for (int col = S + c; col < km; col += S) {
+        gp o = (gp)d.out + (size_t)col * d.ldo;
+        for (int i = 0; i < b; ++i) o[i] = 0.0;
     }
 }
 
@@ -301,17 +340,20 @@ __global__ void __launch_bounds__(64) lrbg_add_core_kernel(const AddCoreDesc *__
     }
 }
 
+// per: descriptors per workgroup of each class (16, 32, 64 wide)
 template <typename D, typename K16, typename K32, typename K64>
-static int launch_by_class(int cols, const D *descs, int count, void *stream, K16 k16, K32 k32, K64 k64)
+static int launch_by_class(int cols, const D *descs, int count, void *stream, K16 k16, K32 k32, K64 k64,
+                           const int (&per)[3])
 {
     if (count <= 0) return 0;
     hipStream_t st = (hipStream_t)stream;
+    auto grid = [&](int q) { return dim3((unsigned)((count + per[q] - 1) / per[q])); };
     if (cols == 16)
-        hipLaunchKernelGGL(k16, dim3(count), dim3(64), 0, st, descs, count);
+        hipLaunchKernelGGL(k16, grid(0), dim3(64), 0, st, descs, count);
     else if (cols == 32)
-        hipLaunchKernelGGL(k32, dim3(count), dim3(64), 0, st, descs, count);
+        hipLaunchKernelGGL(k32, grid(1), dim3(64), 0, st, descs, count);
     else if (cols == 64)
-        hipLaunchKernelGGL(k64, dim3(count), dim3(64), 0, st, descs, count);
+        hipLaunchKernelGGL(k64, grid(2), dim3(64), 0, st, descs, count);
     else
         return (int)hipErrorInvalidValue;
     return (int)hipGetLastError();
@@ -320,19 +362,19 @@ static int launch_by_class(int cols, const D *descs, int count, void *stream, K1
 int launch_qr_factor(int cols, const QrDesc *descs, int count, void *stream)
 {
     return launch_by_class(cols, descs, count, stream, lrbg_qr_factor_kernel<16>, lrbg_qr_factor_kernel<32>,
-                           lrbg_qr_factor_kernel<64>);
+                           lrbg_qr_factor_kernel<64>, {4, 2, 1});
 }
 
 int launch_qr_apply(int cols, const QrDesc *descs, int count, void *stream)
 {
     return launch_by_class(cols, descs, count, stream, lrbg_qr_apply_kernel<16>, lrbg_qr_apply_kernel<32>,
-                           lrbg_qr_apply_kernel<64>);
+                           lrbg_qr_apply_kernel<64>, {4, 2, 1});
 }
 
 int launch_add_core(int cols, const AddCoreDesc *descs, int count, void *stream)
 {
     return launch_by_class(cols, descs, count, stream, lrbg_add_core_kernel<16>, lrbg_add_core_kernel<32>,
-                           lrbg_add_core_kernel<64>);
+                           lrbg_add_core_kernel<64>, {1, 1, 1});
 }
 
 }  // namespace lrbg

@@ -1529,6 +1529,10 @@ static void add_build(const RoundArgs &a, char *base, AddBuild &ab)
         sd.kmax = a.kmax;
         ab.sv[c].push_back(sd);
     }
+    // a wavefront runs 64 / width stacked bases side by side for as many row
+    // blocks as the longest of them: keep bases of similar length together
+    for (int c = 0; c < 3; ++c)
+        std::stable_sort(ab.qr[c].begin(), ab.qr[c].end(), [](const QrDesc &x, const QrDesc &y) { return x.b > y.b; });
 }
 
 // Device tables of a built addition, packed in one upload: per width class

@@ -182,7 +182,7 @@ struct AddCoreDesc {
 };
 
 // Rows per block of the QR after the first s0 = min(s, b) rows.
-constexpr int kQrRows = 64;
+constexpr int kQrRows = 32;
 constexpr int kQrMaxCols = 64;
 
 // Scratch of one stacked basis (doubles): the triangular factor R (s x s,
