@@ -390,12 +390,36 @@ lrbg_status lrbg_schedule_variants(const lrbg_desc *descs, int64_t count, const 
  * lrbg_autotune -- for every (op, prec, b, r) bucket present in `sample`,
  * time each candidate tile variant on the sample's own buffers (outputs are
  * overwritten) and write the fastest to `cache_out` (text, one bucket per
- * line).  `reps` timed repetitions per candidate (>= 1).  Synchronous.
+ * line, plus a "#cand" line per candidate with its time).  Candidates are
+ * the variants that fit every product of the bucket and belong to the kernel
+ * family of the bucket's built-in default (a variant of another family would
+ * add a launch to every plan level holding the bucket).  `reps` timed
+ * repetitions per candidate (>= 1), minimum kept.  Synchronous.
  */
 lrbg_status lrbg_autotune(const lrbg_desc *sample, int64_t count,
                           const char *cache_out, int32_t reps);
 
-/* Number of tile variants compiled in, and the name of one (for tooling). */
+/*
+ * lrbg_autotune_mix -- refine a tuning cache inside a mixed batch.  Starting
+ * from the picks of `cache_in` (a file written by lrbg_autotune; built-in
+ * defaults for buckets it lacks), each (op, prec, b, r) bucket of `sample`,
+ * largest estimated share of the batch first, tries each compatible variant
+ * of the same kernel family whose isolated time in `cache_in` is within
+ * 1.5x of the bucket's best:
+ * the whole sample is planned (with `flags`, as the caller's plans will be)
+ * with that one change and replayed alternately with the current plan
+ * (`reps` timed replays each, medians compared); a change that is faster by
+ * more than 0.4% twice in a row is kept.  At most `passes` passes over the
+ * buckets, stopping after a pass that keeps nothing.  `cache_out` gets the
+ * input's candidate lines, one "#mix" line per trial and every bucket's pick
+ * with its own isolated time.  Synchronous; outputs of the sample are
+ * overwritten.  The paper tunes its kernels per processor empirically
+ * (Table 1, the B_skinny sweep of Sec. 6); this is the batch-level analogue.
+ */
+lrbg_status lrbg_autotune_mix(const lrbg_desc *sample, int64_t count, const char *cache_in,
+                              const char *cache_out, int32_t reps, int32_t passes, uint32_t flags);
+
+/* Number of tile variants compiled in, and the name of one (for tooling). *//* Number of tile variants compiled in, and the name of one (for tooling). */
 int32_t lrbg_variant_count(void);
 const char *lrbg_variant_name(int32_t v);
 

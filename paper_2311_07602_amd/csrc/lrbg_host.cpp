@@ -1958,8 +1958,12 @@ lrbg_status lrbg_autotune(const lrbg_desc *sample, int64_t count, const char *ca
         auto &vec = kv.second;
         int best = 0;
         double best_ms = 1e300;
+        // candidates from the kernel family of the bucket's default variant:
+        // a variant of another family would add a launch to every plan level
+        // that holds the bucket, which an isolated timing cannot show
+        const int fam = family_of(default_variant(vec[0]));
         for (int v = 1; v < kNumVariants && result == LRBG_OK; ++v) {
-            bool ok = true;
+            bool ok = family_of(v) == fam;
             for (auto &d : vec) ok = ok && variant_fits(v, d);
             if (!ok) continue;
             Schedule sch;
@@ -2000,6 +2004,211 @@ lrbg_status lrbg_autotune(const lrbg_desc *sample, int64_t count, const char *ca
         std::ofstream f(cache_out);
         if (!f) return fail(LRBG_EINVAL, "cannot write %s", cache_out);
         f << os.str();
+    }
+    return LRBG_OK;
+}
+
+}  // extern "C"
+
+// In-mix coordinate search.  A bucket's fastest variant in isolation is not
+// always its fastest inside a mixed batch (neighbouring tiles share the CU's
+// LDS, matrix cores and HBM), so starting from the isolation picks of
+// `cache_in` each bucket of the sample, largest estimated share first, tries
+// every compatible candidate whose isolated time is within kMixIsoSlack of
+// the bucket's best: the whole sample is scheduled with that one change and
+// its plan is replayed alternately with the current plan; a change that
+// makes the median replay faster by more than kMixGain (and again in a
+// confirming run with twice the repetitions) is kept.  Passes repeat until
+// one keeps nothing.  The output keeps the input's candidate lines (isolated
+// times), adds a "#mix" line per trial, and lists every bucket's pick with
+// that variant's own isolated time.
+namespace lrbg {
+constexpr double kMixGain = 0.004;
+constexpr double kMixIsoSlack = 1.5;
+
+struct CacheFile {
+    TuneTable tt;
+    std::vector<std::string> cand_lines;
+    std::map<std::pair<BucketKey, int>, double> iso_ms;   // (bucket, variant) -> isolated ms
+    std::map<BucketKey, double> best_iso;
+};
+
+static void read_cache_file(const char *path, CacheFile &cf)
+{
+    load_tune_cache(path, cf.tt);
+    if (!path || !*path) return;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        if (line.rfind("#cand ", 0) != 0) continue;
+        cf.cand_lines.push_back(line);
+        std::istringstream is(line.substr(6));
+        int op, prec, b, r;
+        std::string nm;
+        double ms;
+        if (!(is >> op >> prec >> b >> r >> nm >> ms)) continue;
+        const int v = variant_by_name(nm);
+        if (!v) continue;
+        const BucketKey key(op, prec, b, r);
+        cf.iso_ms[{key, v}] = ms;
+        auto it = cf.best_iso.find(key);
+        if (it == cf.best_iso.end() || ms < it->second) cf.best_iso[key] = ms;
+    }
+}
+
+// Median of `reps` replays of each plan, replayed alternately (a, b, a, b, ...).
+static lrbg_status time_pair(lrbg_plan *a, lrbg_plan *b, int reps, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                             double &ma, double &mb)
+{
+    std::vector<double> ta, tb;
+    for (int r = 0; r <= reps; ++r)
+        for (int w = 0; w < 2; ++w) {
+            lrbg_plan *p = w ? b : a;
+            if (hipEventRecord(e0, s) != hipSuccess) return fail(LRBG_EDEVICE, "event record failed");
+            lrbg_status st = p->exec ? (hipGraphLaunch(p->exec, s) == hipSuccess ? LRBG_OK : LRBG_EDEVICE)
+                                     : enqueue_levels(p, s);
+            if (st != LRBG_OK) return fail(LRBG_EDEVICE, "autotune replay failed");
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+                return fail(LRBG_EDEVICE, "autotune run failed");
+            float t = 0;
+            (void)hipEventElapsedTime(&t, e0, e1);
+            if (r > 0) (w ? tb : ta).push_back(t);   // the first replay of each warms up
+        }
+    auto med = [](std::vector<double> &v) {
+        std::sort(v.begin(), v.end());
+        const size_t n = v.size();
+        return n % 2 ? v[n / 2] : 0.5 * (v[n / 2 - 1] + v[n / 2]);
+    };
+    ma = med(ta);
+    mb = med(tb);
+    return LRBG_OK;
+}
+
+static lrbg_status plan_with(const lrbg_desc *ds, int64_t n, const TuneTable &tt, uint32_t flags, lrbg_plan **p)
+{
+    Schedule sch;
+    lrbg_status st = build_schedule(ds, n, tt, flags, nullptr, sch);
+    if (st != LRBG_OK) return st;
+    return plan_from_schedule(sch, flags, p);
+}
+}  // namespace lrbg
+
+extern "C" {
+
+lrbg_status lrbg_autotune_mix(const lrbg_desc *sample, int64_t count, const char *cache_in, const char *cache_out,
+                              int32_t reps, int32_t passes, uint32_t flags)
+{
+    if (count <= 0 || !sample) return fail(LRBG_EINVAL, "empty sample");
+    if (reps < 1 || passes < 1) return fail(LRBG_EINVAL, "reps and passes must be >= 1");
+    if (flags & ~(uint32_t)(LRBG_PLAN_PERSISTENT | LRBG_PLAN_NO_GRAPH | LRBG_PLAN_SCHED_MIX | LRBG_PLAN_DUAL |
+                            LRBG_PLAN_UNTIMED))
+        return fail(LRBG_EINVAL, "unknown plan flags 0x%x", flags);
+    for (int64_t i = 0; i < count; ++i) {
+        lrbg_status st = validate_one(sample[i], i);
+        if (st != LRBG_OK) return st;
+    }
+    CacheFile cf;
+    read_cache_file(cache_in, cf);
+    // buckets of the sample: estimated time, current pick, candidates
+    std::map<BucketKey, double> share;
+    std::map<BucketKey, std::vector<int64_t>> members;
+    for (int64_t i = 0; i < count; ++i) {
+        const BucketKey key = bucket_of(sample[i]);
+        share[key] += est_time(sample[i]);
+        members[key].push_back(i);
+    }
+    TuneTable cur = cf.tt;
+    std::vector<BucketKey> order;
+    std::map<BucketKey, std::vector<int>> cands;
+    for (auto &kv : members) {
+        const BucketKey &key = kv.first;
+        auto fits_all = [&](int v) {
+            for (int64_t i : kv.second)
+                if (!variant_fits(v, sample[i])) return false;
+            return true;
+        };
+        if (!cur.choice.count(key) || !fits_all(cur.choice[key])) cur.choice[key] = default_variant(sample[kv.second[0]]);
+        auto bi = cf.best_iso.find(key);
+        const int fam = family_of(default_variant(sample[kv.second[0]]));
+        for (int v = 1; v < kNumVariants; ++v) {
+            if (v == cur.choice[key] || family_of(v) != fam || !fits_all(v)) continue;
+            if (bi != cf.best_iso.end()) {
+                auto iv = cf.iso_ms.find({key, v});
+                if (iv == cf.iso_ms.end() || iv->second > kMixIsoSlack * bi->second) continue;
+            }
+            cands[key].push_back(v);
+        }
+        order.push_back(key);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](const BucketKey &x, const BucketKey &y) { return share[x] > share[y]; });
+    hipStream_t s;
+    HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::ostringstream mix;
+    lrbg_plan *base = nullptr;
+    lrbg_status st = LRBG_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        st = fail(LRBG_EDEVICE, "event creation failed");
+    if (st == LRBG_OK) st = plan_with(sample, count, cur, flags, &base);
+    auto key_str = [](const BucketKey &k) {
+        std::ostringstream o;
+        o << std::get<0>(k) << " " << std::get<1>(k) << " " << std::get<2>(k) << " " << std::get<3>(k);
+        return o.str();
+    };
+    for (int pass = 0; pass < passes && st == LRBG_OK; ++pass) {
+        bool changed = false;
+        for (const BucketKey &key : order) {
+            for (int v : cands[key]) {
+                if (st != LRBG_OK || v == cur.choice[key]) continue;
+                TuneTable trial = cur;
+                trial.choice[key] = v;
+                lrbg_plan *p = nullptr;
+                if (plan_with(sample, count, trial, flags, &p) != LRBG_OK) continue;
+                double mb = 0, mc = 0;
+                st = time_pair(base, p, reps, s, e0, e1, mb, mc);
+                bool keep = st == LRBG_OK && mc < mb * (1.0 - kMixGain);
+                double mb2 = 0, mc2 = 0;
+                if (keep) {
+                    st = time_pair(base, p, 2 * reps, s, e0, e1, mb2, mc2);
+                    keep = st == LRBG_OK && mc2 < mb2 * (1.0 - kMixGain);
+                }
+                mix << "#mix " << key_str(key) << " " << variant_name(cur.choice[key]) << " -> " << variant_name(v)
+                    << " batch_ms " << mb << " " << mc;
+                if (mb2 > 0) mix << " confirm " << mb2 << " " << mc2;
+                mix << (keep ? " kept" : "") << "\n";
+                if (keep) {
+                    lrbg_plan_destroy(base);
+                    base = p;
+                    cur = trial;
+                    changed = true;
+                } else {
+                    lrbg_plan_destroy(p);
+                }
+            }
+        }
+        if (!changed) break;
+    }
+    if (base) lrbg_plan_destroy(base);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(s);
+    if (st != LRBG_OK) return st;
+    if (cache_out) {
+        std::ofstream f(cache_out);
+        if (!f) return fail(LRBG_EINVAL, "cannot write %s", cache_out);
+        f << "# lrbg tuning cache: op prec b r variant ms (ms: the variant's isolated time in its bucket; #cand: "
+             "every candidate in isolation; #mix: whole-sample replays, current -> trial, median ms)\n";
+        for (const std::string &l : cf.cand_lines) f << l << "\n";
+        f << mix.str();
+        for (auto &kv : cur.choice) {
+            auto iv = cf.iso_ms.find({kv.first, kv.second});
+            f << key_str(kv.first) << " " << variant_name(kv.second) << " ";
+            if (iv != cf.iso_ms.end())
+                f << iv->second;
+            else
+                f << "nan";
+            f << "\n";
+        }
     }
     return LRBG_OK;
 }

@@ -123,6 +123,8 @@ def load(path: Optional[str] = None):
     lib.lrbg_plan_last_ms.restype = ctypes.c_double
     lib.lrbg_autotune.argtypes = [P(lrbg_desc), i64, ctypes.c_char_p, i32]
     lib.lrbg_autotune.restype = ctypes.c_int
+    lib.lrbg_autotune_mix.argtypes = [P(lrbg_desc), i64, ctypes.c_char_p, ctypes.c_char_p, i32, i32, u32]
+    lib.lrbg_autotune_mix.restype = ctypes.c_int
     lib.lrbg_variant_count.argtypes = []
     lib.lrbg_variant_count.restype = i32
     lib.lrbg_variant_name.argtypes = [i32]
@@ -327,6 +329,13 @@ def lrbg_plan_last_ms(plan: int) -> float:
 def lrbg_autotune(descs: Sequence[lrbg_desc], cache_out: str, reps: int = 3) -> int:
     arr = (lrbg_desc * max(len(descs), 1))(*descs)
     return _check(load().lrbg_autotune(arr, len(descs), cache_out.encode(), reps), "lrbg_autotune")
+
+
+def lrbg_autotune_mix(descs: Sequence[lrbg_desc], cache_in: Optional[str], cache_out: str, reps: int = 5,
+                      passes: int = 2, flags: int = 0) -> int:
+    arr = (lrbg_desc * max(len(descs), 1))(*descs)
+    return _check(load().lrbg_autotune_mix(arr, len(descs), cache_in.encode() if cache_in else None,
+                                           cache_out.encode(), reps, passes, flags), "lrbg_autotune_mix")
 
 
 def lrbg_variant_names() -> List[str]:
