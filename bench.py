@@ -305,6 +305,43 @@ def run_lrmult_config(args):
             "roofline": roof, "step_ms_min": round(min(per), 4), "step_ms_max": round(max(per), 4)}
 
 
+def run_chain_recomp_config(args):
+    """The recompression level of the low-rank chain alone (``--config
+    chain_recomp``): 4096 x W = U1 (T V2^T), b = 512, r = 32, with T from one
+    run of the whole chain; the plan holds only the recompression products,
+    so every timed launch is the HBM-write-bound RECOMP kernel."""
+    import torch
+    from paper_2311_07602_amd import lrbg, workloads
+    stream = torch.cuda.current_stream()
+    count, b, r = 4096, 512, 32
+    w = workloads.chain(count, b, r)
+    full = lrbg.Plan(w.descs, tune_cache=args.tune_cache)
+    full.execute(stream)
+    torch.cuda.synchronize()
+    full.close()
+    plan = lrbg.Plan(w.descs[count:], tune_cache=args.tune_cache)
+    st = plan.stats()
+    ms, per = time_plan(plan, args.steps, args.warmup, stream)
+    plan.close()
+    f, by = st["useful_flops"], st["hbm_bytes"]
+    t_f, t_b = f / (PEAK_FP64_TFLOPS * 1e12), by / (PEAK_HBM_GBS * 1e9)
+    from paper_2311_07602_amd import profiling
+    prof = os.path.join(ROOT, "profiles", "lrbg_grouped_kernel.chain_recomp_4096.md")
+    traffic = profiling.current_traffic(prof) if os.path.exists(prof) else None
+    return {"metric": METRIC, "value": round(f / (ms * 1e-3) / 1e9, 2), "unit": "GFLOP/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"{count} x W = U1 (T V2^T), b={b}, r={r}, FP64 (the recompression level of "
+                                   f"the low-rank chain)", "instances": count, "tiles": st["tiles"],
+                       "launch": "hipGraph replay, one grouped kernel"},
+            "roofline": {"bound": "hbm", "achieved": round(by / ms / 1e6, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": round(by / ms / 1e6 / PEAK_HBM_GBS, 4), "traffic": traffic,
+                         "kernel": "lrbg_grouped_kernel", "algorithmic_flops": f, "algorithmic_bytes": by,
+                         "roofline_ms": round(max(t_f, t_b) * 1e3, 4),
+                         "frac_of_roofline_time": round(max(t_f, t_b) * 1e3 / ms, 4)},
+            "step_ms_min": round(min(per), 4), "step_ms_max": round(max(per), 4)}
+
+
 def time_calls(fn, steps, warmup, stream):
     """Average time of fn() (device work enqueued on `stream`), HIP events."""
     import torch
@@ -616,8 +653,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="grouped", choices=["grouped", "lrmult"],
-                    help="grouped: the uneven batch (default); lrmult: one (b, r) of the paper's fused product")
+    ap.add_argument("--config", default="grouped", choices=["grouped", "lrmult", "chain_recomp"],
+                    help="grouped: the uneven batch (default); lrmult: one (b, r) of the paper's fused product; "
+                         "chain_recomp: the recompression level of the low-rank chain alone")
     ap.add_argument("--count", type=int, default=20000)
     ap.add_argument("--lr-b", type=int, default=2048)
     ap.add_argument("--lr-r", type=int, default=32)
@@ -647,6 +685,9 @@ def main():
         return
     if args.config == "lrmult":
         print(json.dumps(run_lrmult_config(args)), flush=True)
+        return
+    if args.config == "chain_recomp":
+        print(json.dumps(run_chain_recomp_config(args)), flush=True)
         return
     line = run_grouped(args)
     if not args.no_extras:

@@ -103,7 +103,11 @@ def summarize(args) -> str:
         mops = statistics.median(counter_per_dispatch(args.mfma, args.kernel, "SQ_INSTS_VALU_MFMA_MOPS_F64"))
         busy = statistics.median(counter_per_dispatch(args.mfma, args.kernel, "SQ_VALU_MFMA_BUSY_CYCLES"))
         active = statistics.median(counter_per_dispatch(args.mfma, args.kernel, "GRBM_GUI_ACTIVE"))
-        mfma = {"flops": mops * 512.0, "util": busy / (active * args.simds) if active else float("nan")}
+        # GRBM_GUI_ACTIVE is summed over the accelerator dies: per die it is the
+        # kernel's duration in shader-clock cycles, which also gives the clock
+        per_die = active / args.xcds
+        mfma = {"flops": mops * 512.0, "util": busy / (per_die * args.simds) if active else float("nan"),
+                "clock_ghz": per_die / (med_ms * 1e-3) / 1e9}
     lines = [
         f"# {args.kernel}: {args.workload}",
         "",
@@ -148,9 +152,11 @@ def summarize(args) -> str:
             "",
             f"Executed FP64 MFMA flops per launch: {mfma['flops'] / 1e9:.2f} GFLOP (counter x 512) against "
             f"{args.flops / 1e9:.2f} GFLOP useful (ratio {mfma['flops'] / args.flops:.3f}: the excess is padding "
-            f"of partial tiles); matrix cores busy {mfma['util'] * 100:.1f}% of SIMD-cycles "
-            f"(busy cycles summed over the {args.simds} SIMDs / (GRBM_GUI_ACTIVE x {args.simds})); executed rate "
-            f"{mfma['flops'] / (med_ms * 1e-3) / 1e12:.2f} TFLOP/s at the median timed dispatch.",
+            f"of partial tiles); executed rate {mfma['flops'] / (med_ms * 1e-3) / 1e12:.2f} TFLOP/s at the median "
+            f"timed dispatch.  Shader clock during the kernel {mfma['clock_ghz']:.2f} GHz (GRBM_GUI_ACTIVE / "
+            f"{args.xcds} dies / duration), so the FP64 matrix-core peak at that clock is "
+            f"{78.6 * mfma['clock_ghz'] / 2.4:.1f} TFLOP/s; matrix cores busy {mfma['util'] * 100:.1f}% of "
+            f"SIMD-cycles (SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / {args.xcds} x {args.simds} SIMDs)).",
             "",
         ]
     lines += [
@@ -169,7 +175,8 @@ def summarize(args) -> str:
         f"traffic_bytes_per_launch: {f_b + w_b:.6g}",
     ]
     if mfma:
-        lines += [f"mfma_f64_flops_per_launch: {mfma['flops']:.6g}", f"mfma_busy_frac: {mfma['util']:.4f}"]
+        lines += [f"mfma_f64_flops_per_launch: {mfma['flops']:.6g}", f"mfma_busy_frac: {mfma['util']:.4f}",
+                  f"shader_clock_ghz: {mfma['clock_ghz']:.3f}"]
     lines += [
         "```",
         "",
@@ -228,6 +235,7 @@ def main():
     sm.add_argument("--mfma", default=None, help="counter run with SQ_INSTS_VALU_MFMA_MOPS_F64, "
                     "SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE")
     sm.add_argument("--simds", type=int, default=1024, help="SIMDs on the chip (MI355X: 256 CUs x 4)")
+    sm.add_argument("--xcds", type=int, default=8, help="accelerator dies GRBM_GUI_ACTIVE is summed over")
     sm.add_argument("--skip", type=int, default=0, help="warm-up dispatches to leave out of the timed statistics")
     sm.add_argument("--cmd", action="append", default=[])
     sm.add_argument("--out", required=True)
