@@ -25,5 +25,20 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_sanitized(out: str, verbose: bool = False) -> str:
+    """The oracle built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (ROCm's clang, whose shared sanitizer runtime the GPU library's sanitized
+    host build uses too, so both load into one process), for CPU tests."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    cc = os.path.join(rocm, "llvm", "bin", "clang")
+    cmd = [cc, "-O1", "-g", "-fPIC", "-shared", "-std=c99", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-shared-libasan", SRC, "-o", out,
+           "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    return out
+
+
 if __name__ == "__main__":
     build(verbose="-v" in sys.argv)

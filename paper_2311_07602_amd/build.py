@@ -60,5 +60,40 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def sanitizer_runtime() -> str:
+    """The compiler's shared AddressSanitizer runtime (to LD_PRELOAD into a
+    process that loads a sanitized library)."""
+    import glob
+    hits = sorted(glob.glob(os.path.join(ROCM, "llvm", "lib", "clang", "*", "lib", "linux",
+                                         "libclang_rt.asan-x86_64.so")))
+    if not hits:
+        raise FileNotFoundError("no libclang_rt.asan-x86_64.so under " + ROCM)
+    return hits[-1]
+
+
+def build_sanitized(out_dir: str, verbose: bool = False) -> str:
+    """The host side of the library (validation, scheduling, layouts) built
+    with AddressSanitizer and UndefinedBehaviorSanitizer for CPU tests, linked
+    with the device objects of the last build(); returns the library path.
+    Only the host code is instrumented: no sanitizer reaches GPU code."""
+    os.makedirs(out_dir, exist_ok=True)
+    objs = [os.path.join(BUILD, s.rsplit(".", 1)[0] + ".o") for s in SOURCES if s.endswith(".hip")]
+    missing = [o for o in objs if not os.path.exists(o)]
+    if missing:
+        raise FileNotFoundError("run build() first; missing " + ", ".join(missing))
+    host = os.path.join(out_dir, "lrbg_host_san.o")
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=undefined"]
+    _run([HIPCC, "-O1", "-g", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include"), *san, "-c",
+          os.path.join(CSRC, "lrbg_host.cpp"), "-o", host], verbose)
+    lib = os.path.join(out_dir, "liblrbg_san.so")
+    clang = os.path.join(ROCM, "llvm", "bin", "clang++")
+    # the sanitizer runtime is not linked in: the process preloads it
+    # (sanitizer_runtime()), which resolves the instrumented object's hooks
+    _run([clang, "-shared", "-fPIC", host, *objs, "-o", lib, "-L", os.path.join(ROCM, "lib"), "-lamdhip64",
+          "-Wl,-rpath," + os.path.join(ROCM, "lib"), "-lstdc++", "-lm"], verbose)
+    return lib
+
+
 if __name__ == "__main__":
     build(verbose=True)
