@@ -382,6 +382,22 @@ def vendor_lrmult(w, steps, warmup, stream):
     return ms, diff
 
 
+def paper_rates(b, r):
+    """The CPU rates the paper tabulates at this (b, r), batch 20 000 (its
+    rank-96 and rank-128 tables, Sec. 7): context beside the MI355X rate,
+    not a target."""
+    path = os.path.join(ROOT, "tests", "golden", "paper_tables.json")
+    if not os.path.exists(path):
+        return {}
+    rows = []
+    for t in json.load(open(path))["tables"]:
+        if t["rank"] == r and b in t["block_size"]:
+            j = t["block_size"].index(b)
+            rows.append({"cpu": t["cpu"], "GFLOP/s": t["ours"][j], "vendor": t["vendor"],
+                         "vendor_GFLOP/s": t["vendor_gflops"][j], "cite": t["cite"]})
+    return {"paper_cpu": rows} if rows else {}
+
+
 def run_lrmult_paper(count=20000, bs=(512, 1024, 2048), rs=(8, 16, 32, 96, 128), steps=10, warmup=2):
     """The paper's batched low-rank product G = X_A (V_A^T U_B) X_B at its
     measured shapes (batch 20 000 per (b, r)); GFLOP/s by the paper's count
@@ -406,7 +422,7 @@ def run_lrmult_paper(count=20000, bs=(512, 1024, 2048), rs=(8, 16, 32, 96, 128),
             out.append({"b": b, "r": r, "ms_per_step": round(ms, 4), "GFLOP/s": round(f / ms / 1e6, 1),
                         "GB/s": round(by / ms / 1e6, 1), "frac_of_roofline_time": round(roof / ms, 4),
                         "vendor_ms": round(vms, 4), "speedup_vs_vendor": round(vms / ms, 2),
-                        "vendor_rel_diff": vdiff})
+                        "vendor_rel_diff": vdiff, **paper_rates(b, r)})
             log(f"[bench] lrmult b={b} r={r}: {ms:.4f} ms, {f / ms / 1e6:.0f} GFLOP/s, {by / ms / 1e6:.0f} GB/s; "
                 f"vendor {vms:.4f} ms")
     return {"workload": f"{count} x G = X_A (V_A^T U_B) X_B per (b, r), FP64, N(0,1), fused (one tile per "
