@@ -41,7 +41,10 @@
 namespace lrbg {
 
 // G = 64 / S stacked bases per wavefront, one per group of S lanes (group g
-// = lanes g S .. g S + S - 1, lane c of a group owns column c).  Loops run to
+// = lanes g S .. g S + S - 1, lane c of a group owns column c).  With several
+// groups the per-group LDS arrays are padded so that the groups sharing a
+// half-wave of an LDS access fall into different banks (an unpadded stride
+// that is a multiple of 32 doubles put every group on the same banks).  Loops run to
 // the widest case of the class and to the largest block count of the
 // wavefront; a column beyond a basis's width, a row beyond its end and a
 // group without a basis are zeros, whose reflections are the identity
@@ -55,11 +58,12 @@ __global__ void __launch_bounds__(64) lrbg_qr_factor_kernel(const QrDesc *__rest
     QrDesc d{};
     if (t < count) d = descs[t];
     const int c0 = d.c0, s = d.c0 + d.c1, b = d.b, s0 = s < b ? s : b;
-    __shared__ double R_[G][S * S];      // first rows, then the triangular factor; row-major, stride S
-    __shared__ double xs_[G][kQrRows];   // the current reflection's unscaled tail
+    constexpr int RSTR = S * S + (G > 1 ? 16 : 0), XSTR = kQrRows + (G > 1 ? 2 : 0);
+    __shared__ double R_[G * RSTR];      // first rows, then the triangular factor; row-major, stride S
+    __shared__ double xs_[G * XSTR];     // the current reflection's unscaled tail
     __shared__ double tau_[G], sc_[G];
     __shared__ int nb_[G];
-    double *R = R_[g], *xs = xs_[g];
+    double *R = R_ + g * RSTR, *xs = xs_ + g * XSTR;
     const bool mine = c < s;
     gcp cp = (gcp)(!mine ? d.w0 : c < c0 ? d.w0 + (size_t)c * d.ld0 : d.w1 + (size_t)(c - c0) * d.ld1);
     gp ws = (gp)d.ws;
@@ -120,8 +124,14 @@ __global__ void __launch_bounds__(64) lrbg_qr_factor_kernel(const QrDesc *__rest
         const int hb = kb < nblk ? (b - r0 < kQrRows ? b - r0 : kQrRows) : 0;
         double x[kQrRows];
         if (hb == kQrRows && mine) {
+            // 16-byte loads: a lane's rows are contiguous in its column
+            gcp2 p2 = (gcp2)(cp + r0);
 #pragma unroll
-            for (int i = 0; i < kQrRows; ++i) x[i] = cp[r0 + i];
+            for (int i = 0; i < kQrRows / 2; ++i) {
+                const d2u v = p2[i];
+                x[2 * i] = v.x;
+                x[2 * i + 1] = v.y;
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < kQrRows; ++i) x[i] = (mine && i < hb) ? cp[r0 + i] : 0.0;
@@ -168,6 +178,9 @@ __global__ void __launch_bounds__(64) lrbg_qr_factor_kernel(const QrDesc *__rest
                 const double tw = tau * (R[j * S + c] + scale * ((w0 + w1) + (w2 + w3)));
                 R[j * S + c] -= tw;
                 const double f = tw * scale;
+                // read the tail again for the update rather than keep 32 more
+                // values live: halves the registers, so more waves hide latency
+                __asm__ volatile("" ::: "memory");
 #pragma unroll
                 for (int i = 0; i < kQrRows; ++i) x[i] -= f * xs[i];
             }
@@ -175,9 +188,9 @@ __global__ void __launch_bounds__(64) lrbg_qr_factor_kernel(const QrDesc *__rest
         }
         if (mine && kb < nblk) {
             gp bp = blk + (size_t)kb * (s + (size_t)kQrRows * s);
-            gp Y = bp + s + (size_t)c * kQrRows;
+            gp2 Y = (gp2)(bp + s + (size_t)c * kQrRows);
 #pragma unroll
-            for (int i = 0; i < kQrRows; ++i) Y[i] = x[i] * my_sc;
+            for (int i = 0; i < kQrRows / 2; ++i) Y[i] = d2u{x[2 * i] * my_sc, x[2 * i + 1] * my_sc};
             bp[c] = my_t;
         }
     }
@@ -188,26 +201,35 @@ __global__ void __launch_bounds__(64) lrbg_qr_factor_kernel(const QrDesc *__rest
 // As the factorisation, G = 64 / S stacked bases per wavefront; lane c of a
 // group computes output column c < min(kmax, S) (a basis of width s has
 // rank <= s <= S, so any later columns are zero and are filled at the end).
-template <int S>
+// The top part Z is S x KZ with KZ = min(S, kmax rounded up to 16): LDS, not
+// registers, decides how many wavefronts a CU holds here.  The first s0
+// rows' reflection tails are staged packed (column j's s0 - 1 - j entries at
+// j (2 s0 - j - 1) / 2), so they fit the room of one block's tails.
+template <int S, int KZ>
 __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restrict__ descs, int count)
 {
+    static_assert(KZ <= S && KZ % 16 == 0, "top part width");
     constexpr int G = 64 / S;
     const int lane = threadIdx.x, g = lane / S, c = lane % S;
     const int t = (int)blockIdx.x * G + g;
     QrDesc d{};
     if (t < count) d = descs[t];
     const int s = d.c0 + d.c1, b = d.b, s0 = s < b ? s : b, km = d.kmax;
-    __shared__ double Z_[G][S * S];            // s x kmax top part, Z[j * S + c]
+    // per-group arrays, padded as in the factorisation
+    constexpr int ZSTR = S * KZ + (G > 1 ? 16 : 0);
     // a block's reflection tails (column j at j * kQrRows), later the first
-    // s0 rows' reduced matrix (s0 x s, s0 <= S): room for the larger
-    constexpr int YL = (kQrRows > S ? kQrRows : S) * S;
-    __shared__ double Yl_[G][YL];
-    __shared__ double tl_[G][S];
+    // s0 rows' packed tails (s0 (s0 - 1) / 2 <= S (S - 1) / 2 <= kQrRows S)
+    constexpr int YL = kQrRows * S, YSTR = YL + (G > 1 ? 2 : 0), TSTR = S + (G > 1 ? 2 : 0);
+    static_assert(S * (S - 1) / 2 <= YL, "packed tails fit");
+    __shared__ double Z_[G * ZSTR];            // s x kmax top part, Z[j * KZ + c]
+    __shared__ double Yl_[G * YSTR];
+    __shared__ double tl_[G * TSTR];
     __shared__ int nb_[G];
-    double *Z = Z_[g], *Yl = Yl_[g], *tl = tl_[g];
-    const bool mine = c < km;
+    double *Z = Z_ + g * ZSTR, *Yl = Yl_ + g * YSTR, *tl = tl_ + g * TSTR;
+    const bool mine = c < km && c < KZ;       // km <= S implies km <= KZ
     gcp xk = (gcp)d.xk;
-    for (int j = 0; j < S; ++j) Z[j * S + c] = (mine && j < s) ? xk[j + (size_t)c * s] : 0.0;
+    if (c < KZ)
+        for (int j = 0; j < S; ++j) Z[j * KZ + c] = (mine && j < s) ? xk[j + (size_t)c * s] : 0.0;
     gcp ws = (gcp)d.ws;
     gcp tau0 = ws + (size_t)s * s;
     gcp T = tau0 + s;
@@ -233,7 +255,7 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
             const double tau = tl[j];
             if (tau == 0.0) continue;
             const double *y = Yl + j * kQrRows;
-            double w0 = Z[j * S + c], w1 = 0.0, w2 = 0.0, w3 = 0.0;
+            double w0 = mine ? Z[j * KZ + c] : 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
 #pragma unroll
             for (int i = 0; i < kQrRows; i += 4) {
                 w0 += y[i] * u[i];
@@ -242,15 +264,17 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
                 w3 += y[i + 3] * u[i + 3];
             }
             const double tw = tau * ((w0 + w1) + (w2 + w3));
-            Z[j * S + c] -= tw;
+            if (mine) Z[j * KZ + c] -= tw;
+            __asm__ volatile("" ::: "memory");   // as in the factorisation: reload y
 #pragma unroll
             for (int i = 0; i < kQrRows; ++i) u[i] -= tw * y[i];
         }
         if (mine && live) {
             gp o = (gp)d.out + (size_t)c * d.ldo + r0;
             if (hb == kQrRows) {
+                gp2 o2 = (gp2)o;
 #pragma unroll
-                for (int i = 0; i < kQrRows; ++i) o[i] = u[i];
+                for (int i = 0; i < kQrRows / 2; ++i) o2[i] = d2u{u[2 * i], u[2 * i + 1]};
             } else {
 #pragma unroll
                 for (int i = 0; i < kQrRows; ++i)
@@ -260,21 +284,24 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
     }
     // the first s0 rows: reflections with pivots on the diagonal
     __syncthreads();
-    for (int e = c; e < s0 * s; e += S) Yl[e] = T[e];   // s0 * s <= S * S <= YL
+    auto pk = [s0](int j) { return j * (2 * s0 - j - 1) / 2; };
+    for (int j = 0; j < s0; ++j)
+        for (int i = j + 1 + c; i < s0; i += S) Yl[pk(j) + i - j - 1] = T[(size_t)i * s + j];
     tl[c] = c < s ? tau0[c] : 0.0;
     __syncthreads();
-    for (int j = S - 1; j >= 0; --j) {
-        const double tau = j < s0 ? tl[j] : 0.0;
-        if (tau == 0.0) continue;
-        double w = Z[j * S + c];
-        for (int i = j + 1; i < s0; ++i) w += Yl[i * s + j] * Z[i * S + c];
-        const double tw = tau * w;
-        Z[j * S + c] -= tw;
-        for (int i = j + 1; i < s0; ++i) Z[i * S + c] -= tw * Yl[i * s + j];
-    }
     if (mine) {
+        for (int j = S - 1; j >= 0; --j) {
+            const double tau = j < s0 ? tl[j] : 0.0;
+            if (tau == 0.0) continue;
+            const double *y = Yl + pk(j) - j - 1;   // y[i] for i > j
+            double w = Z[j * KZ + c];
+            for (int i = j + 1; i < s0; ++i) w += y[i] * Z[i * KZ + c];
+            const double tw = tau * w;
+            Z[j * KZ + c] -= tw;
+            for (int i = j + 1; i < s0; ++i) Z[i * KZ + c] -= tw * y[i];
+        }
         gp o = (gp)d.out + (size_t)c * d.ldo;
-        for (int i = 0; i < s0; ++i) o[i] = Z[i * S + c];
+        for (int i = 0; i < s0; ++i) o[i] = Z[i * KZ + c];
     }
     // output columns S .. kmax - 1 (kmax above the class width): zero
     for (int col = S + c; col < km; col += S) {
@@ -365,10 +392,17 @@ int launch_qr_factor(int cols, const QrDesc *descs, int count, void *stream)
                            lrbg_qr_factor_kernel<64>, {4, 2, 1});
 }
 
-int launch_qr_apply(int cols, const QrDesc *descs, int count, void *stream)
+int launch_qr_apply(int cols, int kmax, const QrDesc *descs, int count, void *stream)
 {
-    return launch_by_class(cols, descs, count, stream, lrbg_qr_apply_kernel<16>, lrbg_qr_apply_kernel<32>,
-                           lrbg_qr_apply_kernel<64>, {4, 2, 1});
+    const int kz = kmax <= 16 ? 16 : kmax <= 32 ? 32 : 64;
+    if (cols == 16 || kz == 16)
+        return launch_by_class(cols, descs, count, stream, lrbg_qr_apply_kernel<16, 16>,
+                               lrbg_qr_apply_kernel<32, 16>, lrbg_qr_apply_kernel<64, 16>, {4, 2, 1});
+    if (cols == 32 || kz == 32)
+        return launch_by_class(cols, descs, count, stream, lrbg_qr_apply_kernel<16, 16>,
+                               lrbg_qr_apply_kernel<32, 32>, lrbg_qr_apply_kernel<64, 32>, {4, 2, 1});
+    return launch_by_class(cols, descs, count, stream, lrbg_qr_apply_kernel<16, 16>, lrbg_qr_apply_kernel<32, 32>,
+                           lrbg_qr_apply_kernel<64, 64>, {4, 2, 1});
 }
 
 int launch_add_core(int cols, const AddCoreDesc *descs, int count, void *stream)

@@ -87,6 +87,7 @@ static std::string variant_name(int v)
     case K_LRM: snprintf(buf, sizeof buf, "lrm_ri%d_rj%d_ks%d_kg%d", vi.p1, vi.p2, vi.p3, vi.p4); break;
     case K_LRM4: snprintf(buf, sizeof buf, "lrm4_ri%d_rj%d_ks%d_kg%d", vi.p1, vi.p2, vi.p3, vi.p4); break;
     case K_LRMB: snprintf(buf, sizeof buf, "lrmb_ri%d_rj%d_kg%d", vi.p1, vi.p2, vi.p4); break;
+    case K_LRM96: snprintf(buf, sizeof buf, "lrm96_ri%d_rj%d_kg%d", vi.p1, vi.p2, vi.p4); break;
     default: snprintf(buf, sizeof buf, "v%d", v);
     }
     return buf;
@@ -113,7 +114,7 @@ static bool kind_matches(int kind, int op, int prec)
     if (kind == base) return base != K_NOP;
     if (prec == LRBG_FP64 && op == LRBG_OP_DENSE_TS) return kind == K_DTSL || kind == K_DTSS;
     if (prec == LRBG_FP64 && op == LRBG_OP_INNER) return kind == K_INNL;
-    if (prec == LRBG_FP64 && op == LRBG_OP_LRMULT) return kind == K_LRM4 || kind == K_LRMB;
+    if (prec == LRBG_FP64 && op == LRBG_OP_LRMULT) return kind == K_LRM4 || kind == K_LRMB || kind == K_LRM96;
     return false;
 }
 
@@ -133,6 +134,7 @@ static bool variant_fits(int v, const lrbg_desc &d)
     case K_INN3: return d.n <= 16 * vi.p2;
     case K_LRM: case K_LRM4: return d.m <= 16 * vi.p1 * (4 / vi.p3) && d.n <= 16 * vi.p2;
     case K_LRMB: return d.m <= 128 && d.n <= 128;
+    case K_LRM96: return d.m <= 96 && d.n <= 96;
     case K_REC64: {
         const int kp = (d.k + 15) / 16 * 16;
         return (size_t)kp * 16 * vi.p2 * 8 <= (size_t)kLdsBytes;
@@ -161,6 +163,8 @@ static void tiles_of(int v, const lrbg_desc &d, std::vector<int32_t> &p0s, std::
         step = 16 * vi.p1 * (4 / vi.p3); extent = d.m; kc = 4 * vi.p4; break;
     case K_LRMB:
         step = 128; extent = d.m; kc = 4 * vi.p4; break;
+    case K_LRM96:
+        step = 96; extent = d.m; kc = 4 * vi.p4; break;
     case K_INNL:
         step = 16 * vi.p1 * vi.p3; extent = d.m; kc = 4 * vi.p4; break;
     case K_REC64:
@@ -255,6 +259,7 @@ static int default_variant(const lrbg_desc &d)
         if (rr <= 16) return pick({42, 39});   // 4 workgroups per CU: memory-bound, latency-limited
         if (rr <= 32) return pick({40, 44});
         if (rr <= 64) return pick({41});
+        if (rr <= 96) return pick({53, 47});
         return pick({47});
     }
     if (kind == K_REC64) {
@@ -755,6 +760,7 @@ static int family_of(int v)
     case K_LRM: return F_LRM;
     case K_LRM4: return F_LRM4;
     case K_LRMB: return F_LRMB;
+    case K_LRM96: return F_LRM96;
     case K_DTSS: return F_SHORT;
     default: return F_GROUPED;
     }
@@ -1364,6 +1370,7 @@ static int width_class(int s) { return s <= 16 ? 0 : s <= 32 ? 1 : 2; }
 static const int kWidthClasses[3] = {16, 32, 64};
 
 struct AddBuild {
+    int kmax = 1;
     size_t total = 0;
     std::vector<size_t> owu, owv, og, ox, oy;
     std::vector<QrDesc> qr[3];
@@ -1450,6 +1457,7 @@ static lrbg_status add_validate(const RoundArgs &a)
 static void add_layout(const RoundArgs &a, AddBuild &ab)
 {
     const size_t n = (size_t)a.count;
+    ab.kmax = a.kmax;
     ab.total = 0;
     auto take = [&](size_t elems) {
         const size_t o = ab.total;
@@ -1580,7 +1588,8 @@ static lrbg_status add_launches(const AddBuild &ab, const AddTables &tb, const c
     for (int c = 0; c < 3 && !rc; ++c)
         rc = launch_core_svd(kWidthClasses[c], (const SvdDesc *)(dev + tb.os[c]), (int)ab.sv[c].size(), stream);
     for (int c = 0; c < 3 && !rc; ++c)
-        rc = launch_qr_apply(kWidthClasses[c], (const QrDesc *)(dev + tb.oq[c]), (int)ab.qr[c].size(), stream);
+        rc = launch_qr_apply(kWidthClasses[c], ab.kmax, (const QrDesc *)(dev + tb.oq[c]), (int)ab.qr[c].size(),
+                             stream);
     if (rc) return fail(LRBG_EDEVICE, "rounded-addition launch failed: %s", hipGetErrorString((hipError_t)rc));
     return LRBG_OK;
 }

@@ -47,6 +47,7 @@ enum Kind : int32_t {
     K_LRM4 = 9,    // as K_LRM in the high-occupancy fused kernel (32 KB LDS, <= 128 VGPRs)
     K_LRMB = 10,   // LRMULT, FP64, fused, ranks <= 128  params: RI, RJ, -, KG (8 waves, 128 KB LDS)
     K_DTSS = 11,   // DENSE_TS, FP64, short contraction (k <= 64)  params: RM, RN, KG (no LDS)
+    K_LRM96 = 12,  // LRMULT, FP64, fused, ranks <= 96  params: RI, RJ, -, KG (6 waves, 72 KB LDS)
 };
 
 // Kernel families: each family of variants is compiled into its own kernel
@@ -57,8 +58,11 @@ enum Family : int32_t {
     F_LRM4 = 2,      // lrbg_lrmult4_kernel: 32 KB LDS, 4 workgroups per CU
     F_LRMB = 3,      // lrbg_lrmultb_kernel: 8 waves, 128 KB LDS, 1 workgroup per CU
     F_SHORT = 4,     // lrbg_short_kernel: no LDS, up to 4 workgroups per CU
+    F_LRM96 = 5,     // lrbg_lrmult96_kernel: 6 waves, 72 KB LDS, 2 workgroups per CU
 };
-constexpr int kFamilies = 5;
+constexpr int kFamilies = 6;
+constexpr int kThreads96 = 384;
+constexpr int kLdsBytes96 = 96 * 96 * 8;
 constexpr int kLdsBytes4 = 32768;
 constexpr int kThreadsB = 512;
 constexpr int kLdsBytesB = 131072;
@@ -140,10 +144,18 @@ constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies
     X(51, K_DTSS, 2, 2, 2, 0)         \
     X(52, K_DTSS, 2, 4, 1, 0)
 
-#define LRBG_ALL_VARIANTS(X) \
-    LRBG_VARIANTS(X) LRBG_LRM_VARIANTS(X) LRBG_LRM4_VARIANTS(X) LRBG_LRMB_VARIANTS(X) LRBG_SHORT_VARIANTS(X)
+// Fused low-rank products of ranks 65..96 on a 96-wide tile (6 waves):
+// the 128-wide tile would spend 44% of its matrix-core work on padding.
+#define LRBG_LRM96_VARIANTS(X)        \
+    X(53, K_LRM96, 3, 2, 0, 4)        \
+    X(54, K_LRM96, 2, 3, 0, 4)        \
+    X(55, K_LRM96, 3, 2, 0, 2)
 
-constexpr int kNumVariants = 53;   // ids 0..52 (0 = no-op tile)
+#define LRBG_ALL_VARIANTS(X) \
+    LRBG_VARIANTS(X) LRBG_LRM_VARIANTS(X) LRBG_LRM4_VARIANTS(X) LRBG_LRMB_VARIANTS(X) LRBG_SHORT_VARIANTS(X) \
+    LRBG_LRM96_VARIANTS(X)
+
+constexpr int kNumVariants = 56;   // ids 0..55 (0 = no-op tile)
 
 struct VariantInfo {
     int32_t kind, p1, p2, p3, p4;
@@ -212,7 +224,7 @@ int launch_core_svd(int nmax, const SvdDesc *descs, int count, void *stream);
 int svd_max_dim();
 // Rounded addition: launches for one class of stacked widths (cols in {16, 32, 64}).
 int launch_qr_factor(int cols, const QrDesc *descs, int count, void *stream);
-int launch_qr_apply(int cols, const QrDesc *descs, int count, void *stream);
+int launch_qr_apply(int cols, int kmax, const QrDesc *descs, int count, void *stream);
 int launch_add_core(int cols, const AddCoreDesc *descs, int count, void *stream);
 // The fixed per-device scratch of the allocation-free entry point.
 size_t noalloc_scratch_bytes();

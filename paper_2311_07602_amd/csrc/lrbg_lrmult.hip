@@ -147,49 +147,52 @@ __device__ __forceinline__ void lrm_tile(const DevDesc &d, int i0, double *lds)
 }
 
 // ---------------------------------------------------------------------------
-// LRMULT for ranks up to 128, fused: one workgroup of 8 waves per CU, the
-// rank x rank intermediates in 128 KB of LDS (C, then E over it).
+// LRMULT for ranks up to R = 128 (8 waves, 128 KB of LDS, one workgroup per
+// CU) or R = 96 (6 waves, 72 KB, two workgroups per CU), fused: the
+// R x R intermediates in LDS (C, then E over it); one wave per 16 rows of E
+// and G.
 //   C phase: wave (wr, wc) of a WR x WC grid accumulates C rows
 //            [16 RI wr, +16 RI) x columns [16 RJ wc, +16 RJ) over all of k,
 //            each k chunk of V_A and U_B staged once in LDS for all 8 waves
 //            (inner_staged); C -> LDS row-major.
 //   E phase: wave w forms E rows [16 w, 16 w + 16) x all columns: its strip
-//            X_A(16 w + rho(c), 32 g + s), s < 32, sits in registers (lane
-//            group g takes 32 consecutive k), C(32 g + s, 16 J + c) comes
+//            X_A(16 w + rho(c), Q g + s), s < Q = R / 4, sits in registers
+//            (lane group g takes Q consecutive k), C(Q g + s, 16 J + c) comes
 //            from LDS (consecutive lanes, consecutive banks); E -> LDS
 //            column-major over C.
 //   G phase: wave w forms G rows [16 w, 16 w + 16): its E strip comes from
-//            LDS into registers, the X_B column strips X_B(32 g + s, 16 J + c)
-//            stream from L2 (32 contiguous doubles per lane), one column
+//            LDS into registers, the X_B column strips X_B(Q g + s, 16 J + c)
+//            stream from L2 (Q contiguous doubles per lane), one column
 //            block ahead, and G is stored block by block.
 // Rows and columns beyond the ranks hold finite filler or zeros: X_A columns
 // >= ra and X_B rows >= rb read as 0, so they never reach an output, and
 // output rows/columns beyond the ranks are not stored.
-template <int RI, int RJ, int KG, bool GUARD>
+template <int R, int RI, int RJ, int KG, bool GUARD>
 __device__ __forceinline__ void lrmb_tile(const DevDesc &d, double *lds)
 {
-    constexpr int R = 128;
+    constexpr int NTHR = R == 128 ? kThreadsB : kThreads96, LDSB = R == 128 ? kLdsBytesB : kLdsBytes96;
     constexpr int WR = R / (16 * RI), WC = R / (16 * RJ);
-    static_assert(WR * WC == kThreadsB / 64, "one C block per wave");
-    static_assert(R * R * 8 <= kLdsBytesB, "LRMULT core exceeds LDS");
-    constexpr int NBJ = R / 16;
+    static_assert(R == 128 || R == 96, "128- or 96-wide fused tile");
+    static_assert(WR * WC == NTHR / 64 && 16 * (NTHR / 64) == R, "one C block group and one E row block per wave");
+    static_assert(R * R * 8 <= LDSB, "LRMULT core exceeds LDS");
+    constexpr int NBJ = R / 16, Q = R / 4;
     const int tid = threadIdx.x, lane = tid & 63, c = lane & 15, g = lane >> 4, w = tid >> 6;
     const int ra = d.m, rb = d.n;
     const int wr = w / WC, wc = w % WC;
     const int row0 = 16 * RI * wr, col0 = 16 * RJ * wc;
 
     d4 acc[RI][RJ];
-    inner_staged<RI, RJ, WR, WC, KG, GUARD, kThreadsB, kLdsBytesB>(d, 0, lds, acc);
+    inner_staged<RI, RJ, WR, WC, KG, GUARD, NTHR, LDSB>(d, 0, lds, acc);
 
     // X_A strip of the E phase, issued before the C store
     const int erow = 16 * w + rho(c);
-    double xa[32];
+    double xa[Q];
     {
         gcp p = gin(d.s) + (erow < ra ? erow : 0);
         const size_t ldx = (size_t)d.lds;
 #pragma unroll
-        for (int s = 0; s < 32; ++s) {
-            const int kk = 32 * g + s;
+        for (int s = 0; s < Q; ++s) {
+            const int kk = Q * g + s;
             xa[s] = kk < ra ? p[kk * ldx] : 0.0;
         }
     }
@@ -210,20 +213,20 @@ __device__ __forceinline__ void lrmb_tile(const DevDesc &d, double *lds)
     for (int J = 0; J < NBJ; ++J) e[J] = d4{0.0, 0.0, 0.0, 0.0};
     if (rows_live) {
 #pragma unroll
-        for (int s = 0; s < 32; ++s) {
-            const double *crow = lds + (32 * g + s) * R + c;
+        for (int s = 0; s < Q; ++s) {
+            const double *crow = lds + (Q * g + s) * R + c;
 #pragma unroll
             for (int J = 0; J < NBJ; ++J)
                 if (J < nbj) e[J] = mfma64(xa[s], crow[16 * J], e[J]);
         }
     }
 
-    auto fetch_xb = [&](int J, double (&xb)[32]) {
+    auto fetch_xb = [&](int J, double (&xb)[Q]) {
         const int col = 16 * J + c;
-        gcp p = gin(d.e) + (size_t)(col < rb ? col : 0) * d.lde + 32 * g;
-        load_run<32, true>(xb, p, rb - 32 * g);   // rows >= rb read 0
+        gcp p = gin(d.e) + (size_t)(col < rb ? col : 0) * d.lde + Q * g;
+        load_run<Q, true>(xb, p, rb - Q * g);   // rows >= rb read 0
     };
-    double xb0[32], xb1[32];
+    double xb0[Q], xb1[Q];
     fetch_xb(0, xb0);
     __syncthreads();   // C is dead
 
@@ -236,15 +239,15 @@ __device__ __forceinline__ void lrmb_tile(const DevDesc &d, double *lds)
 
     // G = E X_B
     if (!rows_live) return;
-    double ea[32];
+    double ea[Q];
 #pragma unroll
-    for (int s = 0; s < 32; ++s) ea[s] = lds[erow + (32 * g + s) * R];
+    for (int s = 0; s < Q; ++s) ea[s] = lds[erow + (Q * g + s) * R];
     const size_t ldg = (size_t)d.ldc;
     const int orow = 16 * w + 4 * g;
-    auto block = [&](int J, const double (&xb)[32]) {
+    auto block = [&](int J, const double (&xb)[Q]) {
         d4 o = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int s = 0; s < 32; ++s) o = mfma64(ea[s], xb[s], o);
+        for (int s = 0; s < Q; ++s) o = mfma64(ea[s], xb[s], o);
         const int col = 16 * J + c;
         if (orow < ra && col < rb) {
             double out[4];
@@ -253,25 +256,38 @@ __device__ __forceinline__ void lrmb_tile(const DevDesc &d, double *lds)
             store_run<4, true>(gout(d.c) + orow + (size_t)col * ldg, out, ra - orow, false);
         }
     };
+    if constexpr (R == 128) {
+        // X_B strips one column block ahead (two register buffers)
 #pragma unroll
-    for (int J = 0; J < NBJ; J += 2) {
-        if (J >= nbj) break;
-        if (J + 1 < nbj) fetch_xb(J + 1, xb1);
-        block(J, xb0);
-        if (J + 1 >= nbj) break;
-        if (J + 2 < nbj) fetch_xb(J + 2, xb0);
-        block(J + 1, xb1);
+        for (int J = 0; J < NBJ; J += 2) {
+            if (J >= nbj) break;
+            if (J + 1 < nbj) fetch_xb(J + 1, xb1);
+            block(J, xb0);
+            if (J + 1 >= nbj) break;
+            if (J + 2 < nbj) fetch_xb(J + 2, xb0);
+            block(J + 1, xb1);
+        }
+    } else {
+        // one buffer: the 96-wide tile runs two workgroups per CU and keeps
+        // its registers within a third of the file
+#pragma unroll
+        for (int J = 0; J < NBJ; ++J) {
+            if (J >= nbj) break;
+            if (J > 0) fetch_xb(J, xb0);
+            block(J, xb0);
+        }
     }
 }
 
 template <int KIND, int P1, int P2, int P3, int P4>
 __device__ __forceinline__ void run_lrm_variant(const DevDesc &d, int p0, bool edge, double *lds)
 {
-    if constexpr (KIND == K_LRMB) {
+    if constexpr (KIND == K_LRMB || KIND == K_LRM96) {
+        constexpr int R = KIND == K_LRMB ? 128 : 96;
         if (edge)
-            lrmb_tile<P1, P2, P4, true>(d, lds);
+            lrmb_tile<R, P1, P2, P4, true>(d, lds);
         else
-            lrmb_tile<P1, P2, P4, false>(d, lds);
+            lrmb_tile<R, P1, P2, P4, false>(d, lds);
     } else {
         constexpr int LDSD = (KIND == K_LRM ? kLdsBytes : kLdsBytes4) / 8;
         if (edge)
@@ -299,6 +315,12 @@ __device__ __forceinline__ void run_lrm_tile(const DevDesc *__restrict__ descs, 
     } else if constexpr (FAMILY == F_LRMB) {
         switch (t.variant) {
             LRBG_LRMB_VARIANTS(LRBG_LRM_CASE)
+        default:
+            break;
+        }
+    } else if constexpr (FAMILY == F_LRM96) {
+        switch (t.variant) {
+            LRBG_LRM96_VARIANTS(LRBG_LRM_CASE)
         default:
             break;
         }
@@ -348,6 +370,17 @@ lrbg_lrmultb_kernel(const DevDesc *__restrict__ descs, const Tile *__restrict__ 
     run_lrm_tile<F_LRMB>(descs, tl, lds);
 }
 
+// Ranks up to 96: 6 waves and 72 KB of LDS, two workgroups per CU.
+__global__ void __launch_bounds__(kThreads96) __attribute__((amdgpu_waves_per_eu(3, 3)))
+lrbg_lrmult96_kernel(const DevDesc *__restrict__ descs, const Tile *__restrict__ tiles, int ntiles)
+{
+    __shared__ double lds[kLdsBytes96 / 8];
+    const int t = blockIdx.x;
+    if (t >= ntiles) return;
+    const Tile tl = tiles[t];
+    run_lrm_tile<F_LRM96>(descs, tl, lds);
+}
+
 int launch_lrm_family(int family, const DevDesc *descs, const Tile *tiles, int ntiles, void *stream)
 {
     if (ntiles <= 0) return 0;
@@ -359,6 +392,8 @@ int launch_lrm_family(int family, const DevDesc *descs, const Tile *tiles, int n
         hipLaunchKernelGGL(lrbg_lrmult4_kernel, grid, block, 0, s, descs, tiles, ntiles);
     else if (family == F_LRMB)
         hipLaunchKernelGGL(lrbg_lrmultb_kernel, grid, dim3(kThreadsB), 0, s, descs, tiles, ntiles);
+    else if (family == F_LRM96)
+        hipLaunchKernelGGL(lrbg_lrmult96_kernel, grid, dim3(kThreads96), 0, s, descs, tiles, ntiles);
     else
         return (int)hipErrorInvalidValue;
     return (int)hipGetLastError();

@@ -74,7 +74,8 @@ def _plan_case(k, ra, rb, integer, seed, pad=(0, 0, 0, 0, 0), tune=None, expect=
 SHAPES = [(512, 8, 8), (512, 16, 16), (512, 32, 32), (1024, 32, 32), (2048, 16, 16), (512, 64, 64),
           (100, 7, 9), (333, 17, 31), (65, 33, 12), (1000, 64, 47), (3, 5, 5), (1, 1, 1), (37, 2, 64),
           (600, 48, 48), (129, 20, 3), (512, 128, 128), (1024, 96, 96), (1000, 100, 77), (300, 65, 128),
-          (129, 128, 1), (77, 70, 120)]
+          (129, 128, 1), (77, 70, 120), (512, 96, 96), (2048, 96, 96), (333, 65, 96), (129, 96, 70),
+          (1000, 80, 81), (95, 66, 90)]
 
 
 @pytest.mark.parametrize("k,ra,rb", SHAPES)
@@ -113,7 +114,7 @@ def _lrm_variants():
 def test_every_lrmult_variant_forced(name):
     """Each fused tile at a rank below its limit (ragged), with a k tail."""
     rj = int(name.split("_rj")[1].split("_")[0])
-    r = 128 if name.startswith("lrmb") else 16 * rj
+    r = 128 if name.startswith("lrmb") else 96 if name.startswith("lrm96") else 16 * rj
     for ra, rb in ((r - 1, r - 3), (max(r // 2 - 1, 1), r)):
         k = 301
         tune = _forced_cache(name, k, max(ra, rb))
