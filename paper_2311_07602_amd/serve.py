@@ -245,7 +245,14 @@ class ResidentPool:
 
     def operand_offsets(self, shapes: np.ndarray, slots: np.ndarray) -> np.ndarray:
         """[n, 4] element offsets of A, U, V1, U2 for each (b, r) and slot."""
-        bi = np.array([self.index[(int(b), int(r))] for b, r in shapes], dtype=np.int64)
+        if getattr(self, "_lut", None) is None:   # (b, r) -> bucket, one vectorised lookup per request
+            bmax = max(b for b, _ in self.buckets); rmax = max(r for _, r in self.buckets)
+            self._lut = np.full((bmax + 1, rmax + 1), -1, dtype=np.int64)
+            for (b, r), i in self.index.items():
+                self._lut[b, r] = i
+        bi = self._lut[shapes[:, 0], shapes[:, 1]]
+        if np.any(bi < 0):
+            raise KeyError("a (b, r) outside the pool's buckets")
         return self.offsets[bi, slots]
 
     def host_operands(self, b: int, r: int, slot: int):
