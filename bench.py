@@ -217,6 +217,27 @@ def run_grouped(args):
     return line
 
 
+def run_grouped_bf16x3(count=20000, steps=10, warmup=2):
+    """The uneven batch with every product in the BF16x3 split precision
+    (FP32 operands, three bf16 terms, FP64 outputs), planned and replayed as
+    the headline FP64 batch; useful flops counted as FP64 (2 per
+    multiply-add), bytes at 4 per input element."""
+    import torch
+    from paper_2311_07602_amd import lrbg, workloads
+    stream = torch.cuda.current_stream()
+    w = workloads.grouped(count, seed=3, prec="bf16x3")
+    plan = lrbg.Plan(w.descs, tune_cache=DEFAULT_TUNE, flags=lrbg.LRBG_PLAN_SCHED_MIX)
+    st = plan.stats()
+    ms, _ = time_plan(plan, steps, warmup, stream)
+    plan.close()
+    del w
+    torch.cuda.empty_cache()
+    f, by = st["useful_flops"], st["hbm_bytes"]
+    return {"workload": f"uneven grouped batch, {count} instances, BF16x3 split precision (FP32 in, FP64 out)",
+            "ms_per_step": round(ms, 4), "GFLOP/s": round(f / ms / 1e6, 1), "GB/s": round(by / ms / 1e6, 1),
+            "hbm_frac": round(by / ms / 1e6 / PEAK_HBM_GBS, 4)}
+
+
 def run_dense_uniform(steps=200, warmup=20, sets=16):
     """64 x (256x256 . 256x16); `sets` independent buffer sets (> 2x the
     last-level cache in total) replayed round-robin."""
@@ -617,7 +638,7 @@ def run_blr(nbs=(32, 64, 128), b=512, r=8, nrhs=8, steps=20, warmup=3):
 
 
 def run_serving(budget=64e9, slots=8, sat_requests=400, warm=200, measured=2000, rhos=(0.5, 0.7, 0.9),
-                per_bucket=128, grouped_gflops=None):
+                per_bucket=128, grouped_gflops=None, mix_gflops=None):
     """Continuous-batching loop over a device-resident operand pool: the
     saturated request rate first (all requests queued at t=0), then Poisson
     arrivals at rho x that rate for each rho; latency is arrival ->
@@ -635,6 +656,8 @@ def run_serving(budget=64e9, slots=8, sat_requests=400, warm=200, measured=2000,
         serve.make_requests(sat_requests, float("inf"), seed=101)))
     if grouped_gflops:
         sat["of_grouped_kernel_rate"] = round(sat["GFLOP/s"] / grouped_gflops, 3)
+    if mix_gflops:
+        sat["of_grouped_rate_same_mix"] = round(sat["GFLOP/s"] / mix_gflops, 3)
     mu = sat["requests_per_s"]
     loads = []
     for j, rho in enumerate(rhos):
@@ -709,11 +732,15 @@ def main():
     if not args.no_extras:
         log("[bench] extra workloads ...")
         line["extra"] = {"dense_uniform": run_dense_uniform(), "chain_fp64": run_chain(),
-                         "chain_bf16x3": run_chain(prec="bf16x3")}
+                         "chain_bf16x3": run_chain(prec="bf16x3"), "uneven_batch_bf16x3": run_grouped_bf16x3()}
         # the serving loop allocates each request's outputs: run it before the large workloads
         # below so that the allocator's cache, not fresh device allocations, serves them
         log("[bench] serving ...")
-        line["extra"]["serving"] = run_serving(grouped_gflops=line["value"])
+        g3 = line["extra"]["uneven_batch_bf16x3"]["GFLOP/s"]
+        # requests are FP64 or BF16x3 with equal probability: the batch rate of
+        # that mix, by time, is the harmonic mean of the two batch rates
+        line["extra"]["serving"] = run_serving(grouped_gflops=line["value"],
+                                               mix_gflops=2.0 / (1.0 / line["value"] + 1.0 / g3))
         log("[bench] vendor batched DGEMM on the uneven batch ...")
         wv = None
         try:
