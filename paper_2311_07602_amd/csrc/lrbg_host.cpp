@@ -459,18 +459,42 @@ static void work_of(const lrbg_desc &d, double &flops, double &bytes)
 }
 
 // Relative time estimate of a product on the whole chip (seconds).
+// Rates of the scheduling cost model (FP64 matrix-core flop/s and HBM
+// bytes/s a tile reaches inside a mixed batch); LRBG_COST_MODEL="tf,tbs"
+// overrides them (e.g. "70,5.5").
+static void cost_rates(double &fr, double &br)
+{
+    static double f = 0, b = 0;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        f = 70e12;
+        b = 5.5e12;
+        if (const char *e = getenv("LRBG_COST_MODEL")) {
+            double x = 0, y = 0;
+            if (sscanf(e, "%lf,%lf", &x, &y) == 2 && x > 0 && y > 0) {
+                f = x * 1e12;
+                b = y * 1e12;
+            }
+        }
+    });
+    fr = f;
+    br = b;
+}
+
 static double est_time(const lrbg_desc &d)
 {
-    double f, b;
+    double f, b, fr, br;
     work_of(d, f, b);
-    return std::max(f / 70e12, b / 5.5e12) + 2e-9;
+    cost_rates(fr, br);
+    return std::max(f / fr, b / br) + 2e-9;
 }
 
 static bool compute_bound(const lrbg_desc &d)
 {
-    double f, b;
+    double f, b, fr, br;
     work_of(d, f, b);
-    return f / 70e12 > b / 5.5e12;
+    cost_rates(fr, br);
+    return f / fr > b / br;
 }
 
 // ------------------------------------------------------------- plans
