@@ -47,7 +47,7 @@ enum Kind : int32_t {
     K_LRM4 = 9,    // as K_LRM in the high-occupancy fused kernel (32 KB LDS, <= 128 VGPRs)
     K_LRMB = 10,   // LRMULT, FP64, fused, ranks <= 128  params: RI, RJ, -, KG (8 waves, 128 KB LDS)
     K_DTSS = 11,   // DENSE_TS, FP64, short contraction (k <= 64)  params: RM, RN, KG (no LDS)
-    K_LRM96 = 12,  // LRMULT, FP64, fused, ranks <= 96  params: RI, RJ, -, KG (6 waves, 72 KB LDS)
+    K_LRM96 = 12,  // LRMULT, FP64, fused, ranks <= 96  params: RI, RJ, -, KG (12 waves, 145 KB LDS)
 };
 
 // Kernel families: each family of variants is compiled into its own kernel
@@ -58,11 +58,11 @@ enum Family : int32_t {
     F_LRM4 = 2,      // lrbg_lrmult4_kernel: 32 KB LDS, 4 workgroups per CU
     F_LRMB = 3,      // lrbg_lrmultb_kernel: 8 waves, 128 KB LDS, 1 workgroup per CU
     F_SHORT = 4,     // lrbg_short_kernel: no LDS, up to 4 workgroups per CU
-    F_LRM96 = 5,     // lrbg_lrmult96_kernel: 6 waves, 72 KB LDS, 2 workgroups per CU
+    F_LRM96 = 5,     // lrbg_lrmult96_kernel: 12 waves, 145 KB LDS, 1 workgroup per CU
 };
 constexpr int kFamilies = 6;
-constexpr int kThreads96 = 384;
-constexpr int kLdsBytes96 = 96 * 96 * 8;
+constexpr int kThreads96 = 768;
+constexpr int kLdsBytes96 = (2 * 24 * 194 + 96 * 97) * 8;   // the KG = 6 staging (24 k x 2 x 97) + the factor region
 constexpr int kLdsBytes4 = 32768;
 constexpr int kThreadsB = 512;
 constexpr int kLdsBytesB = 131072;
@@ -144,12 +144,12 @@ constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies
     X(51, K_DTSS, 2, 2, 2, 0)         \
     X(52, K_DTSS, 2, 4, 1, 0)
 
-// Fused low-rank products of ranks 65..96 on a 96-wide tile (6 waves):
+// Fused low-rank products of ranks 65..96 on a 96-wide tile (12 waves):
 // the 128-wide tile would spend 44% of its matrix-core work on padding.
 #define LRBG_LRM96_VARIANTS(X)        \
-    X(53, K_LRM96, 3, 2, 0, 4)        \
-    X(54, K_LRM96, 2, 3, 0, 4)        \
-    X(55, K_LRM96, 3, 2, 0, 2)
+    X(53, K_LRM96, 1, 3, 0, 4)        \
+    X(54, K_LRM96, 3, 1, 0, 4)        \
+    X(55, K_LRM96, 1, 3, 0, 6)
 
 #define LRBG_ALL_VARIANTS(X) \
     LRBG_VARIANTS(X) LRBG_LRM_VARIANTS(X) LRBG_LRM4_VARIANTS(X) LRBG_LRMB_VARIANTS(X) LRBG_SHORT_VARIANTS(X) \

@@ -148,9 +148,8 @@ __device__ __forceinline__ void lrm_tile(const DevDesc &d, int i0, double *lds)
 
 // ---------------------------------------------------------------------------
 // LRMULT for ranks up to R = 128 (8 waves, 128 KB of LDS, one workgroup per
-// CU) or R = 96 (6 waves, 72 KB, two workgroups per CU), fused: the
-// R x R intermediates in LDS (C, then E over it); one wave per 16 rows of E
-// and G.
+// CU), fused: the R x R intermediates in LDS (C, then E over it); one wave
+// per 16 rows of E and G.
 //   C phase: wave (wr, wc) of a WR x WC grid accumulates C rows
 //            [16 RI wr, +16 RI) x columns [16 RJ wc, +16 RJ) over all of k,
 //            each k chunk of V_A and U_B staged once in LDS for all 8 waves
@@ -167,12 +166,11 @@ __device__ __forceinline__ void lrm_tile(const DevDesc &d, int i0, double *lds)
 // Rows and columns beyond the ranks hold finite filler or zeros: X_A columns
 // >= ra and X_B rows >= rb read as 0, so they never reach an output, and
 // output rows/columns beyond the ranks are not stored.
-template <int R, int RI, int RJ, int KG, bool GUARD>
+template <int RI, int RJ, int KG, bool GUARD>
 __device__ __forceinline__ void lrmb_tile(const DevDesc &d, double *lds)
 {
-    constexpr int NTHR = R == 128 ? kThreadsB : kThreads96, LDSB = R == 128 ? kLdsBytesB : kLdsBytes96;
+    constexpr int R = 128, NTHR = kThreadsB, LDSB = kLdsBytesB;
     constexpr int WR = R / (16 * RI), WC = R / (16 * RJ);
-    static_assert(R == 128 || R == 96, "128- or 96-wide fused tile");
     static_assert(WR * WC == NTHR / 64 && 16 * (NTHR / 64) == R, "one C block group and one E row block per wave");
     static_assert(R * R * 8 <= LDSB, "LRMULT core exceeds LDS");
     constexpr int NBJ = R / 16, Q = R / 4;
@@ -256,25 +254,141 @@ __device__ __forceinline__ void lrmb_tile(const DevDesc &d, double *lds)
             store_run<4, true>(gout(d.c) + orow + (size_t)col * ldg, out, ra - orow, false);
         }
     };
-    if constexpr (R == 128) {
-        // X_B strips one column block ahead (two register buffers)
+    // X_B strips one column block ahead (two register buffers)
 #pragma unroll
-        for (int J = 0; J < NBJ; J += 2) {
-            if (J >= nbj) break;
-            if (J + 1 < nbj) fetch_xb(J + 1, xb1);
-            block(J, xb0);
-            if (J + 1 >= nbj) break;
-            if (J + 2 < nbj) fetch_xb(J + 2, xb0);
-            block(J + 1, xb1);
+    for (int J = 0; J < NBJ; J += 2) {
+        if (J >= nbj) break;
+        if (J + 1 < nbj) fetch_xb(J + 1, xb1);
+        block(J, xb0);
+        if (J + 1 >= nbj) break;
+        if (J + 2 < nbj) fetch_xb(J + 2, xb0);
+        block(J + 1, xb1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// LRMULT for ranks up to R = 96, fused, on a 96-wide tile: 12 waves (three
+// per SIMD; a workgroup of 6 waves spreads 2-2-1-1 over the four SIMDs and
+// left the matrix cores of half of them waiting at every barrier) and 145 KB
+// of LDS, one workgroup per CU.  The small factors are staged in LDS, so
+// the E and G phases read no operand from L2 and hold no register strips.
+// LDS: region 0 holds the INNER staging, then C row-major, then E
+// column-major over it; region 1 (R x (R + 1), padded against bank
+// conflicts) holds X_A with column k at k (R + 1), then X_B with row k at
+// k (R + 1).
+//   C phase: wave (wr, wc) of a WR x WC grid accumulates C rows
+//            [16 RI wr, +16 RI) x columns [16 RJ wc, +16 RJ) (inner_staged);
+//            X_A is fetched into registers before it and parked in region 1
+//            with C.
+//   E phase: the two waves w and w + 6 share E rows [16 (w % 6), +16), each
+//            forming three of the six column blocks; X_B is in flight
+//            meanwhile and is parked in region 1 once X_A is dead.
+//   G phase: the same split; E rows from region 0, X_B rows from region 1,
+//            G stored block by block.
+// X_A columns >= ra and X_B rows >= rb are staged as zeros, so they never
+// reach an output; rows and columns of G beyond the ranks are not stored.
+template <int RI, int RJ, int KG, bool GUARD>
+__device__ __forceinline__ void lrm96_tile(const DevDesc &d, double *lds)
+{
+    constexpr int R = 96, NW = kThreads96 / 64, NTHR = kThreads96, P1 = R + 1;
+    constexpr int WR = R / (16 * RI), WC = R / (16 * RJ);
+    constexpr int NRB = R / 16, NBJ = R / 16, NBJW = NBJ / (NW / NRB), Q = R / 4;
+    static_assert(WR * WC == NW && NRB * (NW / NRB) == NW, "one C block group per wave, two waves per E row block");
+    constexpr int KC = 4 * KG, STG = 2 * KC * (2 * R + 2), REG0 = STG > R * R ? STG : R * R;
+    static_assert((REG0 + R * P1) * 8 <= kLdsBytes96, "96-wide fused tile exceeds LDS");
+    constexpr int NST = R * R / 2 / NTHR;   // 16-byte pairs per thread of an R x R factor
+    static_assert(NST * NTHR * 2 == R * R, "factor staging split");
+    const int tid = threadIdx.x, lane = tid & 63, c = lane & 15, g = lane >> 4, w = tid >> 6;
+    const int ra = d.m, rb = d.n;
+    const int wr = w / WC, wc = w % WC;
+    const int row0 = 16 * RI * wr, col0 = 16 * RJ * wc;
+    const int rbk = w % NRB, jb0 = (w / NRB) * NBJW;
+    double *reg1 = lds + REG0;
+
+    // an n x n factor (column-major, ld) into registers: pair p of a thread is
+    // rows i, i + 1 of column k; rows and columns >= n read as zeros
+    double xst[NST][2];
+    auto fetch_factor = [&](gcp base, size_t ld, int n) {
+#pragma unroll
+        for (int p = 0; p < NST; ++p) {
+            const int idx = tid + NTHR * p;
+            const int k = idx / (R / 2), i = 2 * (idx % (R / 2));
+            load_run<2, true>(xst[p], base + i + (size_t)(k < n ? k : 0) * ld, k < n ? n - i : 0);
         }
-    } else {
-        // one buffer: the 96-wide tile runs two workgroups per CU and keeps
-        // its registers within a third of the file
+    };
+    fetch_factor(gin(d.s), (size_t)d.lds, ra);
+
+    d4 acc[RI][RJ];
+    inner_staged<RI, RJ, WR, WC, KG, GUARD, NTHR, REG0 * 8>(d, 0, lds, acc);
+
 #pragma unroll
-        for (int J = 0; J < NBJ; ++J) {
-            if (J >= nbj) break;
-            if (J > 0) fetch_xb(J, xb0);
-            block(J, xb0);
+    for (int bi = 0; bi < RI; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < RJ; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) lds[(row0 + 16 * bi + 4 * g + v) * R + col0 + 16 * bj + c] = acc[bi][bj][v];
+#pragma unroll
+    for (int p = 0; p < NST; ++p) {   // X_A(i, k) at k P1 + i
+        const int idx = tid + NTHR * p;
+        const int k = idx / (R / 2), i = 2 * (idx % (R / 2));
+        reg1[k * P1 + i] = xst[p][0];
+        reg1[k * P1 + i + 1] = xst[p][1];
+    }
+    fetch_factor(gin(d.e), (size_t)d.lde, rb);   // X_B, in flight during the E phase
+    __syncthreads();
+
+    // E = X_A C
+    const int nbj = (rb + 15) / 16;
+    const bool rows_live = 16 * rbk < ra;
+    const int erow = 16 * rbk + rho(c);
+    d4 e[NBJW];
+#pragma unroll
+    for (int J = 0; J < NBJW; ++J) e[J] = d4{0.0, 0.0, 0.0, 0.0};
+    if (rows_live) {
+#pragma unroll
+        for (int s = 0; s < Q; ++s) {
+            const double a = reg1[(Q * g + s) * P1 + erow];
+            const double *crow = lds + (Q * g + s) * R + c;
+#pragma unroll
+            for (int J = 0; J < NBJW; ++J)
+                if (jb0 + J < nbj) e[J] = mfma64(a, crow[16 * (jb0 + J)], e[J]);
+        }
+    }
+    __syncthreads();   // C and X_A are dead
+
+#pragma unroll
+    for (int J = 0; J < NBJW; ++J)
+        if (jb0 + J < nbj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) lds[(16 * rbk + 4 * g + v) + (16 * (jb0 + J) + c) * R] = e[J][v];
+#pragma unroll
+    for (int p = 0; p < NST; ++p) {   // X_B(k, col) at k P1 + col
+        const int idx = tid + NTHR * p;
+        const int col = idx / (R / 2), k = 2 * (idx % (R / 2));
+        reg1[k * P1 + col] = xst[p][0];
+        reg1[(k + 1) * P1 + col] = xst[p][1];
+    }
+    __syncthreads();
+
+    // G = E X_B
+    if (!rows_live) return;
+    double ea[Q];
+#pragma unroll
+    for (int s = 0; s < Q; ++s) ea[s] = lds[erow + (Q * g + s) * R];
+    const size_t ldg = (size_t)d.ldc;
+    const int orow = 16 * rbk + 4 * g;
+#pragma unroll
+    for (int J = 0; J < NBJW; ++J) {
+        const int col = 16 * (jb0 + J) + c;
+        if (jb0 + J >= nbj) break;
+        d4 o = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < Q; ++s) o = mfma64(ea[s], reg1[(Q * g + s) * P1 + col], o);
+        if (orow < ra && col < rb) {
+            double out[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) out[v] = o[v];
+            store_run<4, true>(gout(d.c) + orow + (size_t)col * ldg, out, ra - orow, false);
         }
     }
 }
@@ -282,12 +396,16 @@ __device__ __forceinline__ void lrmb_tile(const DevDesc &d, double *lds)
 template <int KIND, int P1, int P2, int P3, int P4>
 __device__ __forceinline__ void run_lrm_variant(const DevDesc &d, int p0, bool edge, double *lds)
 {
-    if constexpr (KIND == K_LRMB || KIND == K_LRM96) {
-        constexpr int R = KIND == K_LRMB ? 128 : 96;
+    if constexpr (KIND == K_LRMB) {
         if (edge)
-            lrmb_tile<R, P1, P2, P4, true>(d, lds);
+            lrmb_tile<P1, P2, P4, true>(d, lds);
         else
-            lrmb_tile<R, P1, P2, P4, false>(d, lds);
+            lrmb_tile<P1, P2, P4, false>(d, lds);
+    } else if constexpr (KIND == K_LRM96) {
+        if (edge)
+            lrm96_tile<P1, P2, P4, true>(d, lds);
+        else
+            lrm96_tile<P1, P2, P4, false>(d, lds);
     } else {
         constexpr int LDSD = (KIND == K_LRM ? kLdsBytes : kLdsBytes4) / 8;
         if (edge)
@@ -370,7 +488,7 @@ lrbg_lrmultb_kernel(const DevDesc *__restrict__ descs, const Tile *__restrict__ 
     run_lrm_tile<F_LRMB>(descs, tl, lds);
 }
 
-// Ranks up to 96: 6 waves and 72 KB of LDS, two workgroups per CU.
+// Ranks up to 96: 12 waves and 145 KB of LDS, one workgroup per CU.
 __global__ void __launch_bounds__(kThreads96) __attribute__((amdgpu_waves_per_eu(3, 3)))
 lrbg_lrmult96_kernel(const DevDesc *__restrict__ descs, const Tile *__restrict__ tiles, int ntiles)
 {
