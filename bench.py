@@ -300,8 +300,8 @@ def run_lrmult_config(args):
     w = workloads.lrmult(args.count, b, r)
     plan = lrbg.Plan(w.descs, tune_cache=args.tune_cache)
     st = plan.stats()
-    kernel = {"lrm_": "lrbg_lrmult_kernel", "lrm4": "lrbg_lrmult4_kernel",
-              "lrmb": "lrbg_lrmultb_kernel"}[lrbg.lrbg_schedule_variants(w.descs[:1], args.tune_cache)[0][:4]]
+    kernel = {"lrm": "lrbg_lrmult_kernel", "lrm4": "lrbg_lrmult4_kernel", "lrmb": "lrbg_lrmultb_kernel",
+              "lrm96": "lrbg_lrmult96_kernel"}[lrbg.lrbg_schedule_variants(w.descs[:1], args.tune_cache)[0].split("_")[0]]
     ms, per = time_plan(plan, args.steps, args.warmup, stream)
     plan.close()
     f, by = st["useful_flops"], st["hbm_bytes"]
