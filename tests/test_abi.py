@@ -87,6 +87,10 @@ def status(descs):
     (dict(a=BASE + 4), lrbg.LRBG_EINVAL),          # misaligned FP64
     (dict(n=129), lrbg.LRBG_EUNSUPPORTED),         # rank > 128
     (dict(m=70000, lda=70000, ldc=70000), lrbg.LRBG_EUNSUPPORTED),
+    (dict(m=65537, lda=65537, ldc=65537), lrbg.LRBG_EUNSUPPORTED),   # one above the block limit
+    (dict(m=100, k=65537, lda=100, ldb=65537, ldc=100), lrbg.LRBG_EUNSUPPORTED),
+    (dict(m=65536, lda=65536, ldc=65536), 0),                          # the limit itself
+    (dict(m=100, k=65536, lda=100, ldb=65536, ldc=100), 0),
     (dict(prec=7), lrbg.LRBG_EINVAL),
     (dict(c=BASE + 8), lrbg.LRBG_EINVAL),          # output overlaps A
 ])
