@@ -70,25 +70,31 @@ __device__ __forceinline__ gp gout(void *p) { return (gp)(p); }
 
 // NV contiguous doubles from p.  With GUARD, elements at or beyond `valid`
 // read 0 (ragged edges); otherwise all NV are in range and the load is
-// straight-line 16-byte vector loads.
-template <int NV, bool GUARD>
+// straight-line 16-byte vector loads.  NT: non-temporal loads, for an
+// operand that no other tile reads (it then does not push the shared
+// operands of the tiles around it out of L2).
+template <int NV, bool GUARD, bool NT = false>
 __device__ __forceinline__ void load_run(double (&dst)[NV], gcp p, int valid)
 {
     if (!GUARD || valid >= NV) {
         if constexpr (NV % 2 == 0) {
 #pragma unroll
             for (int t = 0; t < NV; t += 2) {
-                const d2u v = *reinterpret_cast<gcp2>(p + t);
+                d2u v;
+                if constexpr (NT)
+                    v = __builtin_nontemporal_load(reinterpret_cast<gcp2>(p + t));
+                else
+                    v = *reinterpret_cast<gcp2>(p + t);
                 dst[t] = v.x;
                 dst[t + 1] = v.y;
             }
         } else {
 #pragma unroll
-            for (int t = 0; t < NV; ++t) dst[t] = p[t];
+            for (int t = 0; t < NV; ++t) dst[t] = NT ? __builtin_nontemporal_load(p + t) : p[t];
         }
     } else {
 #pragma unroll
-        for (int t = 0; t < NV; ++t) dst[t] = (t < valid) ? p[t] : 0.0;
+        for (int t = 0; t < NV; ++t) dst[t] = (t < valid) ? (NT ? __builtin_nontemporal_load(p + t) : p[t]) : 0.0;
     }
 }
 
@@ -120,19 +126,19 @@ __device__ __forceinline__ void store_run(gp p, const double (&src)[NV], int val
 
 // The lane's RM rows of one column (col = row 0 of the wave's span); with
 // GUARD, rows at or beyond `valid` (relative to the span) read 0.
-template <int RM, bool GUARD>
+template <int RM, bool GUARD, bool NT = false>
 __device__ __forceinline__ void load_rows(double (&dst)[RM], gcp col, int c, int valid)
 {
     if constexpr (RM == 1) {
         double t[1];
-        load_run<1, GUARD>(t, col + rho(c), valid - rho(c));
+        load_run<1, GUARD, NT>(t, col + rho(c), valid - rho(c));
         dst[0] = t[0];
     } else {
 #pragma unroll
         for (int h = 0; h < RM / 2; ++h) {
             const int r0 = 32 * h + 2 * rho(c);
             double t[2];
-            load_run<2, GUARD>(t, col + r0, valid - r0);
+            load_run<2, GUARD, NT>(t, col + r0, valid - r0);
             dst[2 * h] = t[0];
             dst[2 * h + 1] = t[1];
         }
@@ -209,8 +215,12 @@ struct StageK {
 // ---------------------------------------------------------------------------
 // DENSE_TS, FP64.  Workgroup tile: rows [i0, i0 + 64 RM) x all n (<= 16 RN)
 // columns, full contraction.  Wave w owns rows i0 + 16 RM w + [0, 16 RM).
-// A streams from HBM exactly once (each element feeds RN MFMAs in registers);
-// U chunks are re-read from L2 by every wave.  No barriers.
+// A streams from HBM exactly once (each element feeds RN MFMAs in registers)
+// through non-temporal loads; U chunks are re-read from L2 by every wave and
+// by the product's other row tiles.  No barriers.  (With A loaded normally,
+// a mixed batch's streaming A evicted U between the row tiles of a product:
+// 8% more HBM reads than the compulsory bytes, against 0.5% when each
+// bucket runs alone; with non-temporal A loads, 0.9%.)
 template <int RM, int RN, int KG, bool GUARD>
 __device__ __forceinline__ void dts64_tile(const DevDesc &d, int i0)
 {
@@ -244,7 +254,7 @@ __device__ __forceinline__ void dts64_tile(const DevDesc &d, int i0)
 #pragma unroll
         for (int s = 0; s < KG; ++s) {
             if (!GUARD || s < kvalid)
-                load_rows<RM, GUARD>(aa[s], Ap + (size_t)(kb + s) * lda, c, rvalid);
+                load_rows<RM, GUARD, true>(aa[s], Ap + (size_t)(kb + s) * lda, c, rvalid);
             else
 #pragma unroll
                 for (int mm = 0; mm < RM; ++mm) aa[s][mm] = 0.0;
@@ -297,7 +307,7 @@ __device__ __forceinline__ void dts64_tile(const DevDesc &d, int i0)
 // ---------------------------------------------------------------------------
 // DENSE_TS, FP64, U staged in LDS (for the matrix-core-bound buckets): the 4
 // waves share each U chunk from LDS instead of each re-reading it from L2;
-// A streams from HBM straight into registers.  Tile: rows [i0, i0 + 64 RM) x
+// A streams from HBM straight into registers (non-temporal, as in dts64_tile).  Tile: rows [i0, i0 + 64 RM) x
 // all n (<= 16 RN) columns.  Two LDS buffers, one barrier per chunk.
 template <int RM, int RN, int KG, bool GUARD>
 __device__ __forceinline__ void dtsl_tile(const DevDesc &d, int i0, double *lds)
@@ -329,7 +339,7 @@ __device__ __forceinline__ void dtsl_tile(const DevDesc &d, int i0, double *lds)
 #pragma unroll
         for (int s = 0; s < KG; ++s) {
             if (!GUARD || (active && kb + s < K))
-                load_rows<RM, GUARD>(aa[s], Ap + (size_t)(kb + s) * lda, c, rvalid);
+                load_rows<RM, GUARD, true>(aa[s], Ap + (size_t)(kb + s) * lda, c, rvalid);
             else
 #pragma unroll
                 for (int mm = 0; mm < RM; ++mm) aa[s][mm] = 0.0;
