@@ -235,7 +235,7 @@ def run_grouped_bf16x3(count=20000, steps=10, warmup=2):
     f, by = st["useful_flops"], st["hbm_bytes"]
     return {"workload": f"uneven grouped batch, {count} instances, BF16x3 split precision (FP32 in, FP64 out)",
             "ms_per_step": round(ms, 4), "GFLOP/s": round(f / ms / 1e6, 1), "GB/s": round(by / ms / 1e6, 1),
-            "hbm_frac": round(by / ms / 1e6 / PEAK_HBM_GBS, 4)}
+            "hbm_frac": round(by / ms / 1e6 / PEAK_HBM_GBS, 4), "algorithmic_flops": f, "algorithmic_bytes": by}
 
 
 def run_dense_uniform(steps=200, warmup=20, sets=16):
@@ -692,9 +692,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="grouped", choices=["grouped", "lrmult", "chain_recomp"],
+    ap.add_argument("--config", default="grouped", choices=["grouped", "lrmult", "chain_recomp", "grouped_bf16x3",
+                                                            "lrmult_round", "lradd"],
                     help="grouped: the uneven batch (default); lrmult: one (b, r) of the paper's fused product; "
-                         "chain_recomp: the recompression level of the low-rank chain alone")
+                         "chain_recomp: the recompression level of the low-rank chain alone; grouped_bf16x3, "
+                         "lrmult_round, lradd: one workload of the extras (the last two at --lr-b, --lr-r)")
     ap.add_argument("--count", type=int, default=20000)
     ap.add_argument("--lr-b", type=int, default=2048)
     ap.add_argument("--lr-r", type=int, default=32)
@@ -727,6 +729,16 @@ def main():
         return
     if args.config == "chain_recomp":
         print(json.dumps(run_chain_recomp_config(args)), flush=True)
+        return
+    # single workloads of the extras, for profiling one at a time
+    if args.config == "grouped_bf16x3":
+        print(json.dumps(run_grouped_bf16x3(args.count, args.steps, args.warmup)), flush=True)
+        return
+    if args.config == "lrmult_round":
+        print(json.dumps(run_round(args.count, args.lr_b, (args.lr_r,), steps=args.steps, warmup=args.warmup)), flush=True)
+        return
+    if args.config == "lradd":
+        print(json.dumps(run_add(args.count, args.lr_b, (args.lr_r,), steps=args.steps, warmup=args.warmup)), flush=True)
         return
     line = run_grouped(args)
     if not args.no_extras:

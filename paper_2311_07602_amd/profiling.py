@@ -187,6 +187,40 @@ def summarize(args) -> str:
     return text
 
 
+def kernels_table(args) -> str:
+    """A pipeline of several kernels (one call = several launches): per
+    kernel, the dispatches in the kernel trace, their average duration and
+    share of the traced kernel time, and the median scaled HBM traffic per
+    dispatch from the two counter runs."""
+    rows = []
+    for row in csv.DictReader(open(_csv(args.kt, "kernel_stats.csv"))):
+        if args.prefix in row["Name"]:
+            rows.append((row["Name"], int(row["Calls"]), float(row["AverageNs"]), float(row["TotalDurationNs"])))
+    total = sum(r[3] for r in rows) or 1.0
+    cal_f = statistics.median(counter_per_dispatch(args.cal_fetch, args.cal_kernel))
+    cal_w = statistics.median(counter_per_dispatch(args.cal_write, args.cal_kernel))
+    fs, ws = args.cal_bytes / (cal_f * 1024.0), args.cal_bytes / (cal_w * 1024.0)
+    lines = [f"# {args.title}", "", "rocprofv3 summaries of the kernels one call launches, in the benchmark "
+             "command below.", "", "## Commands", ""] + [f"    {c}" for c in args.cmd] + [
+        "", "## Kernels (--kernel-trace --stats; --pmc FETCH_SIZE, then WRITE_SIZE, scaled by a 1 GiB copy)", "",
+        "| kernel | dispatches | average ms | share of kernel time | read GB per dispatch | written GB per dispatch |",
+        "|---|---|---|---|---|---|"]
+    for name, calls, avg, tot in sorted(rows, key=lambda r: -r[3]):
+        short = name.split("(")[0].replace("void ", "")
+        try:
+            f = statistics.median(counter_per_dispatch(args.fetch, name)) * 1024.0 * fs
+            w = statistics.median(counter_per_dispatch(args.write, name)) * 1024.0 * ws
+            tr = f"| {f / 1e9:.4f} | {w / 1e9:.4f} |"
+        except (KeyError, statistics.StatisticsError):
+            tr = "| - | - |"
+        lines.append(f"| {short} | {calls} | {avg * 1e-6:.4f} | {tot / total * 100:.1f}% {tr}")
+    lines += ["", "```", f"source_digest: {source_digest(args.sources.split(',') if args.sources else None)}", "```", ""]
+    text = "\n".join(lines)
+    with open(args.out, "w") as fh:
+        fh.write(text)
+    return text
+
+
 def read_summary(path: str) -> Optional[dict]:
     if not os.path.exists(path):
         return None
@@ -239,10 +273,20 @@ def main():
     sm.add_argument("--skip", type=int, default=0, help="warm-up dispatches to leave out of the timed statistics")
     sm.add_argument("--cmd", action="append", default=[])
     sm.add_argument("--out", required=True)
+    kt = sub.add_parser("kernels")
+    for opt in ("--kt", "--fetch", "--write", "--cal-fetch", "--cal-write", "--out", "--title"):
+        kt.add_argument(opt, required=True)
+    kt.add_argument("--prefix", default="lrbg_")
+    kt.add_argument("--cal-kernel", default="copyBuffer")
+    kt.add_argument("--cal-bytes", type=float, default=float(1 << 30))
+    kt.add_argument("--sources", default=None)
+    kt.add_argument("--cmd", action="append", default=[])
     sub.add_parser("digest")
     a = ap.parse_args()
     if a.what == "digest":
         print(source_digest())
+    elif a.what == "kernels":
+        print(kernels_table(a))
     else:
         print(summarize(a))
 
