@@ -49,8 +49,15 @@ namespace lrbg {
 // wavefront; a column beyond a basis's width, a row beyond its end and a
 // group without a basis are zeros, whose reflections are the identity
 // (tau = 0), so every group follows the same control flow.
+//
+// The factorisation runs as two kernels.  The head kernel reduces the first
+// s0 = min(s, b) rows, which needs the whole s0 x s block in LDS, and leaves
+// R (zeros below the diagonal) in the scratch; the block kernel, which does
+// all later rows, keeps only R's upper triangle in LDS, packed row by row,
+// so that a CU holds twice as many of its wavefronts (64-wide bases: 17 KB
+// against 33 KB).
 template <int S>
-__global__ void __launch_bounds__(64) lrbg_qr_factor_kernel(const QrDesc *__restrict__ descs, int count)
+__global__ void __launch_bounds__(64) lrbg_qr_head_kernel(const QrDesc *__restrict__ descs, int count)
 {
     constexpr int G = 64 / S;
     const int lane = threadIdx.x, g = lane / S, c = lane % S;
@@ -58,22 +65,17 @@ __global__ void __launch_bounds__(64) lrbg_qr_factor_kernel(const QrDesc *__rest
     QrDesc d{};
     if (t < count) d = descs[t];
     const int c0 = d.c0, s = d.c0 + d.c1, b = d.b, s0 = s < b ? s : b;
-    constexpr int RSTR = S * S + (G > 1 ? 16 : 0), XSTR = kQrRows + (G > 1 ? 2 : 0);
-    __shared__ double R_[G * RSTR];      // first rows, then the triangular factor; row-major, stride S
-    __shared__ double xs_[G * XSTR];     // the current reflection's unscaled tail
-    __shared__ double tau_[G], sc_[G];
-    __shared__ int nb_[G];
-    double *R = R_ + g * RSTR, *xs = xs_ + g * XSTR;
+    constexpr int RSTR = S * S + (G > 1 ? 16 : 0);
+    __shared__ double R_[G * RSTR];      // the first rows, row-major, stride S
+    __shared__ double tau_[G];
+    double *R = R_ + g * RSTR;
     const bool mine = c < s;
     gcp cp = (gcp)(!mine ? d.w0 : c < c0 ? d.w0 + (size_t)c * d.ld0 : d.w1 + (size_t)(c - c0) * d.ld1);
     gp ws = (gp)d.ws;
     gp tau0 = ws + (size_t)s * s;
     gp T = tau0 + s;
-    gp blk = T + (size_t)s0 * s;
-    const int nblk = b > s0 ? (b - s0 + kQrRows - 1) / kQrRows : 0;
-    if (c == 0) nb_[g] = nblk;
 
-    // ---- first s0 rows: Householder QR in LDS, pivots on the diagonal
+    // Householder QR in LDS, pivots on the diagonal
     for (int i = 0; i < S; ++i) R[i * S + c] = (mine && i < s0) ? cp[i] : 0.0;
     __syncthreads();
     double my_tau = 0.0;
@@ -108,17 +110,46 @@ __global__ void __launch_bounds__(64) lrbg_qr_factor_kernel(const QrDesc *__rest
     if (mine) {
         for (int i = 0; i < s0; ++i) T[(size_t)i * s + c] = R[i * S + c];
         tau0[c] = my_tau;
+        // R so far: the triangle, zeros below it (rows s0 .. s - 1 too)
+        for (int i = 0; i < s; ++i) ws[(size_t)i * s + c] = (i <= c && i < s0) ? R[i * S + c] : 0.0;
     }
-    // keep the triangle: R below the diagonal becomes zero
-    for (int i = c + 1; i < S; ++i) R[i * S + c] = 0.0;
+}
+
+// The later blocks: reflections [e_j; y_j] against R, columns in registers.
+// The pivot lane publishes its column unscaled with the scale 1 / (alpha -
+// beta); every lane scales its own column once, when the block is stored.
+// R(j, c), c >= j, sits at j S - j (j - 1) / 2 + c - j of the packed triangle.
+template <int S>
+__global__ void __launch_bounds__(64) lrbg_qr_blocks_kernel(const QrDesc *__restrict__ descs, int count)
+{
+    constexpr int G = 64 / S;
+    const int lane = threadIdx.x, g = lane / S, c = lane % S;
+    const int t = (int)blockIdx.x * G + g;
+    QrDesc d{};
+    if (t < count) d = descs[t];
+    const int c0 = d.c0, s = d.c0 + d.c1, b = d.b, s0 = s < b ? s : b;
+    constexpr int TRI = S * (S + 1) / 2;
+    constexpr int RSTR = TRI + (G > 1 ? 16 : 0), XSTR = kQrRows + (G > 1 ? 2 : 0);
+    __shared__ double R_[G * RSTR];      // R's upper triangle, packed by rows
+    __shared__ double xs_[G * XSTR];     // the current reflection's unscaled tail
+    __shared__ double tau_[G], sc_[G];
+    __shared__ int nb_[G];
+    double *R = R_ + g * RSTR, *xs = xs_ + g * XSTR;
+    auto rp = [](int j) { return j * S - j * (j - 1) / 2; };   // start of row j
+    const bool mine = c < s;
+    gcp cp = (gcp)(!mine ? d.w0 : c < c0 ? d.w0 + (size_t)c * d.ld0 : d.w1 + (size_t)(c - c0) * d.ld1);
+    gp ws = (gp)d.ws;
+    gp tau0 = ws + (size_t)s * s;
+    gp T = tau0 + s;
+    gp blk = T + (size_t)s0 * s;
+    const int nblk = b > s0 ? (b - s0 + kQrRows - 1) / kQrRows : 0;
+    if (c == 0) nb_[g] = nblk;
+    for (int i = 0; i <= c; ++i) R[rp(i) + c - i] = (mine && nblk > 0) ? ws[(size_t)i * s + c] : 0.0;
     __syncthreads();
     int nbmax = 0;
 #pragma unroll
     for (int q = 0; q < G; ++q) nbmax = nb_[q] > nbmax ? nb_[q] : nbmax;
 
-    // ---- later blocks: reflections [e_j; y_j] against R, columns in registers.
-    // The pivot lane publishes its column unscaled with the scale 1 / (alpha -
-    // beta); every lane scales its own column once, when the block is stored.
     for (int kb = 0; kb < nbmax; ++kb) {
         const int r0 = s0 + kb * kQrRows;
         const int hb = kb < nblk ? (b - r0 < kQrRows ? b - r0 : kQrRows) : 0;
@@ -148,13 +179,13 @@ __global__ void __launch_bounds__(64) lrbg_qr_factor_kernel(const QrDesc *__rest
                     n3 += x[i + 3] * x[i + 3];
                 }
                 const double nrm2 = (n0 + n1) + (n2 + n3);
-                const double alpha = R[j * S + j];
+                const double alpha = R[rp(j)];
                 double tau = 0.0, scale = 0.0;
                 if (nrm2 > 0.0) {
                     const double beta = -copysign(sqrt(alpha * alpha + nrm2), alpha);
                     tau = (beta - alpha) / beta;
                     scale = 1.0 / (alpha - beta);
-                    R[j * S + j] = beta;
+                    R[rp(j)] = beta;
                 }
 #pragma unroll
                 for (int i = 0; i < kQrRows; ++i) xs[i] = x[i];
@@ -175,8 +206,9 @@ __global__ void __launch_bounds__(64) lrbg_qr_factor_kernel(const QrDesc *__rest
                     w2 += xs[i + 2] * x[i + 2];
                     w3 += xs[i + 3] * x[i + 3];
                 }
-                const double tw = tau * (R[j * S + c] + scale * ((w0 + w1) + (w2 + w3)));
-                R[j * S + c] -= tw;
+                double *rjc = R + rp(j) + c - j;
+                const double tw = tau * (*rjc + scale * ((w0 + w1) + (w2 + w3)));
+                *rjc -= tw;
                 const double f = tw * scale;
                 // read the tail again for the update rather than keep 32 more
                 // values live: halves the registers, so more waves hide latency
@@ -194,8 +226,8 @@ __global__ void __launch_bounds__(64) lrbg_qr_factor_kernel(const QrDesc *__rest
             bp[c] = my_t;
         }
     }
-    if (mine)
-        for (int i = 0; i < s; ++i) ws[(size_t)i * s + c] = R[i * S + c];
+    if (mine && nblk > 0)
+        for (int i = 0; i <= c; ++i) ws[(size_t)i * s + c] = R[rp(i) + c - i];
 }
 
 // As the factorisation, G = 64 / S stacked bases per wavefront; lane c of a
@@ -205,12 +237,22 @@ __global__ void __launch_bounds__(64) lrbg_qr_factor_kernel(const QrDesc *__rest
 // registers, decides how many wavefronts a CU holds here.  The first s0
 // rows' reflection tails are staged packed (column j's s0 - 1 - j entries at
 // j (2 s0 - j - 1) / 2), so they fit the room of one block's tails.
+// When a 64-wide basis keeps at most 32 columns (the usual case: two rank-r
+// blocks added and rounded back to rank r), lanes c and c + 32 share output
+// column c, each holding half of a block's rows; their partial dot products
+// meet through one lane-half swap, so each reflection costs a lane half the
+// multiply-adds and tail reads.
 template <int S, int KZ>
 __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restrict__ descs, int count)
 {
     static_assert(KZ <= S && KZ % 16 == 0, "top part width");
     constexpr int G = 64 / S;
-    const int lane = threadIdx.x, g = lane / S, c = lane % S;
+    constexpr bool SPLIT = G == 1 && 2 * KZ <= S;   // two lanes per output column
+    constexpr int RH = SPLIT ? kQrRows / 2 : kQrRows;   // block rows per lane
+    const int lane = threadIdx.x, g = SPLIT ? 0 : lane / S, c = SPLIT ? lane & 31 : lane % S;
+    const int h = SPLIT ? lane >> 5 : 0;   // row half of a block
+    const int li = SPLIT ? lane : c;       // loader index within the group
+    constexpr int NL = SPLIT ? 64 : S;     // loaders per group
     const int t = (int)blockIdx.x * G + g;
     QrDesc d{};
     if (t < count) d = descs[t];
@@ -227,15 +269,16 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
     __shared__ int nb_[G];
     double *Z = Z_ + g * ZSTR, *Yl = Yl_ + g * YSTR, *tl = tl_ + g * TSTR;
     const bool mine = c < km && c < KZ;       // km <= S implies km <= KZ
+    const bool top = h == 0;                  // the lane that owns Z(., c)
     gcp xk = (gcp)d.xk;
-    if (c < KZ)
+    if (c < KZ && top)
         for (int j = 0; j < S; ++j) Z[j * KZ + c] = (mine && j < s) ? xk[j + (size_t)c * s] : 0.0;
     gcp ws = (gcp)d.ws;
     gcp tau0 = ws + (size_t)s * s;
     gcp T = tau0 + s;
     gcp blk = T + (size_t)s0 * s;
     const int nblk = b > s0 ? (b - s0 + kQrRows - 1) / kQrRows : 0;
-    if (c == 0) nb_[g] = nblk;
+    if (li == 0) nb_[g] = nblk;
     __syncthreads();
     int nbmax = 0;
 #pragma unroll
@@ -245,40 +288,50 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
         gcp bp = blk + (size_t)kb * (s + (size_t)kQrRows * s);
         const int r0 = s0 + kb * kQrRows, hb = live ? (b - r0 < kQrRows ? b - r0 : kQrRows) : 0;
         __syncthreads();                       // the previous block's reads of Yl are done
-        for (int e = c; e < S * kQrRows; e += S) Yl[e] = (live && e < s * kQrRows) ? bp[s + e] : 0.0;
-        tl[c] = (live && c < s) ? bp[c] : 0.0;
+        for (int e = li; e < S * kQrRows; e += NL) Yl[e] = (live && e < s * kQrRows) ? bp[s + e] : 0.0;
+        for (int e = li; e < S; e += NL) tl[e] = (live && e < s) ? bp[e] : 0.0;
         __syncthreads();
-        double u[kQrRows];
+        double u[RH];
 #pragma unroll
-        for (int i = 0; i < kQrRows; ++i) u[i] = 0.0;
+        for (int i = 0; i < RH; ++i) u[i] = 0.0;
         for (int j = S - 1; j >= 0; --j) {
             const double tau = tl[j];
             if (tau == 0.0) continue;
-            const double *y = Yl + j * kQrRows;
-            double w0 = mine ? Z[j * KZ + c] : 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+            const double *y = Yl + j * kQrRows + RH * h;
+            double w0 = (mine && top) ? Z[j * KZ + c] : 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
 #pragma unroll
-            for (int i = 0; i < kQrRows; i += 4) {
+            for (int i = 0; i < RH; i += 4) {
                 w0 += y[i] * u[i];
                 w1 += y[i + 1] * u[i + 1];
                 w2 += y[i + 2] * u[i + 2];
                 w3 += y[i + 3] * u[i + 3];
             }
-            const double tw = tau * ((w0 + w1) + (w2 + w3));
-            if (mine) Z[j * KZ + c] -= tw;
+            double w = (w0 + w1) + (w2 + w3);
+            if constexpr (SPLIT) {
+                // add the other half's partial: after the swap one result holds
+                // this lane's value and the other its partner's, in either order
+                const unsigned lo = __double2loint(w), hi = __double2hiint(w);
+                const auto sl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+                const auto sh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+                w = __hiloint2double((int)sh[0], (int)sl[0]) + __hiloint2double((int)sh[1], (int)sl[1]);
+            }
+            const double tw = tau * w;
+            if (mine && top) Z[j * KZ + c] -= tw;
             __asm__ volatile("" ::: "memory");   // as in the factorisation: reload y
 #pragma unroll
-            for (int i = 0; i < kQrRows; ++i) u[i] -= tw * y[i];
+            for (int i = 0; i < RH; ++i) u[i] -= tw * y[i];
         }
         if (mine && live) {
-            gp o = (gp)d.out + (size_t)c * d.ldo + r0;
-            if (hb == kQrRows) {
+            gp o = (gp)d.out + (size_t)c * d.ldo + r0 + RH * h;
+            const int hv = hb - RH * h;        // valid rows of this lane's half
+            if (hv >= RH) {
                 gp2 o2 = (gp2)o;
 #pragma unroll
-                for (int i = 0; i < kQrRows / 2; ++i) o2[i] = d2u{u[2 * i], u[2 * i + 1]};
+                for (int i = 0; i < RH / 2; ++i) o2[i] = d2u{u[2 * i], u[2 * i + 1]};
             } else {
 #pragma unroll
-                for (int i = 0; i < kQrRows; ++i)
-                    if (i < hb) o[i] = u[i];
+                for (int i = 0; i < RH; ++i)
+                    if (i < hv) o[i] = u[i];
             }
         }
     }
@@ -286,10 +339,10 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
     __syncthreads();
     auto pk = [s0](int j) { return j * (2 * s0 - j - 1) / 2; };
     for (int j = 0; j < s0; ++j)
-        for (int i = j + 1 + c; i < s0; i += S) Yl[pk(j) + i - j - 1] = T[(size_t)i * s + j];
-    tl[c] = c < s ? tau0[c] : 0.0;
+        for (int i = j + 1 + li; i < s0; i += NL) Yl[pk(j) + i - j - 1] = T[(size_t)i * s + j];
+    for (int e = li; e < S; e += NL) tl[e] = e < s ? tau0[e] : 0.0;
     __syncthreads();
-    if (mine) {
+    if (mine && top) {
         for (int j = S - 1; j >= 0; --j) {
             const double tau = j < s0 ? tl[j] : 0.0;
             if (tau == 0.0) continue;
@@ -304,10 +357,11 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
         for (int i = 0; i < s0; ++i) o[i] = Z[i * KZ + c];
     }
     // output columns S .. kmax - 1 (kmax above the class width): zero
-    for (int col = S + c; col < km; col += S) {
-        gp o = (gp)d.out + (size_t)col * d.ldo;
-        for (int i = 0; i < b; ++i) o[i] = 0.0;
-    }
+    if (top)
+        for (int col = S + c; col < km; col += S) {
+            gp o = (gp)d.out + (size_t)col * d.ldo;
+            for (int i = 0; i < b; ++i) o[i] = 0.0;
+        }
 }
 
 template <int S>
@@ -388,8 +442,11 @@ static int launch_by_class(int cols, const D *descs, int count, void *stream, K1
 
 int launch_qr_factor(int cols, const QrDesc *descs, int count, void *stream)
 {
-    return launch_by_class(cols, descs, count, stream, lrbg_qr_factor_kernel<16>, lrbg_qr_factor_kernel<32>,
-                           lrbg_qr_factor_kernel<64>, {4, 2, 1});
+    const int rc = launch_by_class(cols, descs, count, stream, lrbg_qr_head_kernel<16>, lrbg_qr_head_kernel<32>,
+                                   lrbg_qr_head_kernel<64>, {4, 2, 1});
+    if (rc != 0) return rc;
+    return launch_by_class(cols, descs, count, stream, lrbg_qr_blocks_kernel<16>, lrbg_qr_blocks_kernel<32>,
+                           lrbg_qr_blocks_kernel<64>, {4, 2, 1});
 }
 
 int launch_qr_apply(int cols, int kmax, const QrDesc *descs, int count, void *stream)

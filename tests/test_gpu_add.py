@@ -124,6 +124,36 @@ def test_lradd_planted_spectrum(b, ra, rb):
             _check(g, ref, ref[1][0])
 
 
+@pytest.mark.parametrize("b,ra,rb,kmax", [(1000, 24, 40, 32), (777, 20, 30, 16), (2047, 32, 32, 32),
+                                           (96, 17, 47, 20), (33, 40, 24, 32)])
+def test_lradd_wide_stack_rounded_to_at_most_half(b, ra, rb, kmax):
+    """Stacks wider than 32 rounded to at most 32 columns (adding two rank-r
+    blocks and keeping rank r), with ragged last row blocks and b below the
+    stack width: a planted spectrum with a clear gap after kmax, tol = 0."""
+    rng = np.random.default_rng(5 * b + ra + kmax)
+    s_ = ra + rb
+    if b < s_:
+        # at most b directions: N(0,1) factors; singular values and orthonormality only
+        insts = [_instance(rng, b, ra, rb) for _ in range(3)]
+        for ins, g in zip(insts, _run(insts, kmax, 0.0)):
+            ref = oracle.lr_add_round(*ins, kmax, 0.0)
+            _check(g, ref, ref[1][0], gap=False)
+        return
+    spec = np.concatenate([np.linspace(5.0, 3.0, kmax), 10.0 ** rng.uniform(-3, -1, s_ - kmax)])
+    insts = []
+    for _ in range(3):
+        P = inputs.orthonormal_f(rng, b, s_)
+        Q = inputs.orthonormal_f(rng, b, s_)
+        perm = rng.permutation(s_)
+        Pp, Qp, sp = P[:, perm], Q[:, perm], spec[perm]
+        insts.append((np.asfortranarray(Pp[:, :ra]), np.asfortranarray(Qp[:, :ra]),
+                      np.asfortranarray(np.diag(sp[:ra])), np.asfortranarray(Pp[:, ra:]),
+                      np.asfortranarray(np.diag(sp[ra:])), np.asfortranarray(Qp[:, ra:])))
+    for ins, g in zip(insts, _run(insts, kmax, 0.0)):
+        ref = oracle.lr_add_round(*ins, kmax, 0.0)
+        _check(g, ref, ref[1][0])
+
+
 def test_lradd_shared_bases_rank_deficient_stack():
     """B on the same orthonormal bases as A: each stacked basis is exactly
     rank deficient (two copies of one basis); the sum is A_U (A_X + B_X)
