@@ -13,9 +13,9 @@
 //
 // QR (one wavefront per stacked basis, s <= 64, lane c owns column c): the
 // basis is read from HBM once, top to bottom.  Its first s0 = min(s, b) rows
-// are reduced in LDS by Householder reflections with pivots on the diagonal;
-// every later block of kQrRows rows is then reduced against the running
-// triangular factor R.  Reflection j of a block acts on row j of R and on
+// are reduced in LDS by Householder reflections with pivots on the diagonal
+// (the head kernel); every later block of kQrRows rows is then reduced
+// against the running triangular factor R (the block kernel).  Reflection j of a block acts on row j of R and on
 // the block's rows only, v = [e_j; y_j] (R is triangular), so the block's
 // columns stay in the lanes' registers: the lane owning column j forms the
 // reflection from its own registers and R_jj, publishes y_j through LDS,
@@ -32,7 +32,8 @@
 // in registers, then M = E R_V^T.
 //
 // New bases (one wavefront per stacked basis, lane c owns output column c <
-// kmax): U = Q [X_k; 0], applying the stored reflections in reverse order:
+// kmax, or lanes c and c + 32 when a 64-wide basis keeps at most 32 columns):
+// U = Q [X_k; 0], applying the stored reflections in reverse order:
 // blocks from the last to the first, each producing its kQrRows output rows
 // in registers while updating the s x kmax top part Z in LDS, then the
 // reflections of the first s0 rows on Z, which gives the top s0 rows.

@@ -94,7 +94,7 @@ def test_dense_uniform_every_instance():
     plan.close()
 
 
-@pytest.mark.parametrize("b,r", [(2048, 32), (2048, 128), (512, 8)])
+@pytest.mark.parametrize("b,r", [(2048, 32), (2048, 128), (512, 8), (2048, 96), (512, 96)])
 def test_lrmult_paper_shape_sampled(b, r):
     """The paper's fused product at its batch of 20 000 (the bench's
     lrmult_paper_shapes configuration): sampled instances against Alg. 1 in
