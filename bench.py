@@ -489,6 +489,24 @@ def run_vendor_grouped(w, steps=5, warmup=2):
             "ms_per_step": round(ms, 4)}
 
 
+def round_args(pin, per, count, b, r, kmax, tol, U, V, sigma, kout):
+    """Host arrays (numpy: the binding passes them without conversion) of the
+    pointer-array entry points of the recompressed product and the rounded
+    addition, for `count` instances laid out in `pin` as A_U, A_V, B_U, B_V
+    (b x r each), then A_X, B_X (r x r), `per` doubles apart; outputs U, V
+    are (count, kmax, b) tensors."""
+    import numpy as np
+    t = np.arange(count, dtype=np.uint64)
+    base = np.uint64(pin.data_ptr())
+    off = lambda j: base + np.uint64(8) * (t * np.uint64(per) + np.uint64(j * b * r))
+    offs = lambda j: base + np.uint64(8) * (t * np.uint64(per) + np.uint64(4 * b * r + j * r * r))
+    full = lambda v: np.full(count, v, dtype=np.int32)
+    uo = np.uint64(U.data_ptr()) + np.uint64(8 * kmax * b) * t
+    vo = np.uint64(V.data_ptr()) + np.uint64(8 * kmax * b) * t
+    return (full(b), full(r), full(r), off(0), full(b), off(1), full(b), offs(0), full(r), off(2), full(b),
+            offs(1), full(r), off(3), full(b), kmax, tol, uo, full(b), vo, full(b), sigma.data_ptr(), kout.data_ptr())
+
+
 def run_round(count=20000, b=1024, rs=(8, 16, 32), tol=1e-8, steps=10, warmup=2):
     """The product of two low-rank blocks recompressed to rank <= r / 2 (fused
     core, batched truncated SVD, new bases) on device-resident N(0,1)
@@ -506,16 +524,7 @@ def run_round(count=20000, b=1024, rs=(8, 16, 32), tol=1e-8, steps=10, warmup=2)
         V = torch.empty_like(U)
         sigma = torch.empty(count * kmax, dtype=torch.float64, device="cuda")
         kout = torch.empty(count, dtype=torch.int32, device="cuda")
-        base = pin.data_ptr()
-        off = lambda t, j: base + 8 * (t * per + j * b * r)
-        offs = lambda t, j: base + 8 * (t * per + 4 * b * r + j * r * r)
-        ts = range(count)
-        args = ([b] * count, [r] * count, [r] * count,
-                [off(t, 0) for t in ts], [b] * count, [off(t, 1) for t in ts], [b] * count,
-                [offs(t, 0) for t in ts], [r] * count, [off(t, 2) for t in ts], [b] * count,
-                [offs(t, 1) for t in ts], [r] * count, [off(t, 3) for t in ts], [b] * count,
-                kmax, tol, [U[t].data_ptr() for t in ts], [b] * count, [V[t].data_ptr() for t in ts], [b] * count,
-                sigma.data_ptr(), kout.data_ptr())
+        args = round_args(pin, per, count, b, r, kmax, tol, U, V, sigma, kout)
         call = lambda: lrbg.lr_batched_lrmult_round(*args, stream=stream)
         ms = time_calls(call, steps, warmup, stream)        # host-inclusive: schedules built per call
         # device time: hold the stream in a device-side sleep while the host enqueues, then
@@ -575,16 +584,7 @@ def run_add(count=20000, b=1024, rs=(8, 16, 32), tol=1e-8, steps=5, warmup=2):
         V = torch.empty_like(U)
         sigma = torch.empty(count * kmax, dtype=torch.float64, device="cuda")
         kout = torch.empty(count, dtype=torch.int32, device="cuda")
-        base = pin.data_ptr()
-        off = lambda t, j: base + 8 * (t * per + j * b * r)
-        offs = lambda t, j: base + 8 * (t * per + 4 * b * r + j * r * r)
-        ts = range(count)
-        args = ([b] * count, [r] * count, [r] * count,
-                [off(t, 0) for t in ts], [b] * count, [off(t, 1) for t in ts], [b] * count,
-                [offs(t, 0) for t in ts], [r] * count, [off(t, 2) for t in ts], [b] * count,
-                [offs(t, 1) for t in ts], [r] * count, [off(t, 3) for t in ts], [b] * count,
-                kmax, tol, [U[t].data_ptr() for t in ts], [b] * count, [V[t].data_ptr() for t in ts], [b] * count,
-                sigma.data_ptr(), kout.data_ptr())
+        args = round_args(pin, per, count, b, r, kmax, tol, U, V, sigma, kout)
         call = lambda: lrbg.lr_batched_lradd_round(*args, stream=stream)
         ms = time_calls(call, steps, warmup, stream)
         dev = []

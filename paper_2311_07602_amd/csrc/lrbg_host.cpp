@@ -143,18 +143,19 @@ static bool variant_fits(int v, const lrbg_desc &d)
     return false;
 }
 
-// Tiles of product d under variant v: p0 of each tile and whether it needs
-// the guarded (ragged-edge) code path.
-static void tiles_of(int v, const lrbg_desc &d, std::vector<int32_t> &p0s, std::vector<int32_t> &edge)
+// Tile geometry of product d under variant v: tiles start every `step`
+// along `extent`; `kc` is the k chunk (a contraction tail needs the guarded
+// path) and `rows_full` says whether a tile's block-type rows must be full.
+static bool tile_geometry(int v, const lrbg_desc &d, int &step, int &extent, int &kc, bool &rows_full)
 {
     const VariantInfo &vi = kVariants[v];
-    int step = 0, extent = 0, kc = 1;
-    bool rows_full_needed = false;   // block-type rows must fill the tile
+    kc = 1;
+    rows_full = false;   // block-type rows must fill the tile
     switch (vi.kind) {
     case K_DTS64: case K_DTSL: case K_DTSS:
-        step = 64 * vi.p1; extent = d.m; kc = 4 * vi.p3; rows_full_needed = true; break;
+        step = 64 * vi.p1; extent = d.m; kc = 4 * vi.p3; rows_full = true; break;
     case K_DTS3:
-        step = 64 * vi.p1; extent = d.m; kc = 32; rows_full_needed = true; break;
+        step = 64 * vi.p1; extent = d.m; kc = 32; rows_full = true; break;
     case K_INN64:
         step = 16 * vi.p1 * (4 / vi.p3); extent = d.m; kc = 4 * vi.p4; break;
     case K_INN3:
@@ -169,15 +170,34 @@ static void tiles_of(int v, const lrbg_desc &d, std::vector<int32_t> &p0s, std::
         step = 16 * vi.p1 * vi.p3; extent = d.m; kc = 4 * vi.p4; break;
     case K_REC64:
         step = 16 * vi.p2; extent = d.n; kc = 4 * vi.p3; break;
-    default: return;
+    default: return false;
     }
+    return true;
+}
+
+static int64_t tile_count(int v, const lrbg_desc &d)
+{
+    int step, extent, kc;
+    bool rows_full;
+    if (!tile_geometry(v, d, step, extent, kc, rows_full) || extent <= 0) return 0;
+    return (extent + step - 1) / step;
+}
+
+// Tiles of product d under variant v: p0 of each tile and whether it needs
+// the guarded (ragged-edge) code path.
+static void tiles_of(int v, const lrbg_desc &d, std::vector<int32_t> &p0s, std::vector<int32_t> &edge)
+{
+    int step, extent, kc;
+    bool rows_full;
+    if (!tile_geometry(v, d, step, extent, kc, rows_full)) return;
+    const VariantInfo &vi = kVariants[v];
     const bool ktail = d.k % kc != 0 || d.k == 0;
     // RECOMP: every row group of 32 RB rows must be full, and so must the
     // tile's columns (block-type W columns).
     const bool rec_rows_ragged = vi.kind == K_REC64 && d.m % (32 * vi.p1) != 0;
     for (int p = 0; p < extent; p += step) {
         bool e = ktail || rec_rows_ragged;
-        if ((rows_full_needed || vi.kind == K_REC64) && p + step > extent) e = true;
+        if ((rows_full || vi.kind == K_REC64) && p + step > extent) e = true;
         p0s.push_back(p);
         edge.push_back(e ? kTileEdge : 0);
     }
@@ -567,35 +587,47 @@ static lrbg_status compute_levels(const lrbg_desc *ds, int64_t n, std::vector<in
         uintptr_t lo, hi;
         int64_t idx;
     };
-    struct Cluster {
-        uintptr_t lo, hi;
-        size_t first, count;      // members: outs[first, first + count)
-        std::vector<Seg> segs;    // sorted columns of all members (count > 1)
-    };
-    std::vector<Cluster> cl;
+    // clusters as parallel arrays (the input search touches only clo / chi):
+    // members outs[cfirst, cfirst + ccount); a multi-member cluster's sorted
+    // columns are segs[sbeg, send)
+    std::vector<uintptr_t> clo, chi;
+    std::vector<size_t> cfirst, ccount, sbeg, send;
+    clo.reserve(outs.size());
+    chi.reserve(outs.size());
+    cfirst.reserve(outs.size());
+    ccount.reserve(outs.size());
     for (size_t t = 0; t < outs.size(); ++t) {
         const Range r = outs[t].range();
-        if (!cl.empty() && r.lo < cl.back().hi) {
-            cl.back().hi = std::max(cl.back().hi, r.hi);
-            ++cl.back().count;
+        if (!clo.empty() && r.lo < chi.back()) {
+            chi.back() = std::max(chi.back(), r.hi);
+            ++ccount.back();
         } else {
-            cl.push_back(Cluster{r.lo, r.hi, t, 1, {}});
+            clo.push_back(r.lo);
+            chi.push_back(r.hi);
+            cfirst.push_back(t);
+            ccount.push_back(1);
         }
     }
-    for (Cluster &c : cl) {
-        if (c.count < 2) continue;
-        for (size_t t = c.first; t < c.first + c.count; ++t) {
+    const size_t ncl = clo.size();
+    sbeg.assign(ncl, 0);
+    send.assign(ncl, 0);
+    std::vector<Seg> segs;
+    for (size_t c = 0; c < ncl; ++c) {
+        if (ccount[c] < 2) continue;
+        sbeg[c] = segs.size();
+        for (size_t t = cfirst[c]; t < cfirst[c] + ccount[c]; ++t) {
             const Mat &m = outs[t];
             for (int64_t j = 0; j < m.cols; ++j) {
                 const uintptr_t lo = m.p + (uintptr_t)j * m.ld_bytes;
-                c.segs.push_back(Seg{lo, lo + m.row_bytes, m.idx});
+                segs.push_back(Seg{lo, lo + m.row_bytes, m.idx});
             }
         }
-        std::sort(c.segs.begin(), c.segs.end(), [](const Seg &x, const Seg &y) { return x.lo < y.lo; });
-        for (size_t t = 1; t < c.segs.size(); ++t)
-            if (c.segs[t].lo < c.segs[t - 1].hi)
-                return fail(LRBG_EINVAL, "outputs of products %lld and %lld overlap", (long long)c.segs[t - 1].idx,
-                            (long long)c.segs[t].idx);
+        send[c] = segs.size();
+        std::sort(segs.begin() + (ptrdiff_t)sbeg[c], segs.end(), [](const Seg &x, const Seg &y) { return x.lo < y.lo; });
+        for (size_t t = sbeg[c] + 1; t < send[c]; ++t)
+            if (segs[t].lo < segs[t - 1].hi)
+                return fail(LRBG_EINVAL, "outputs of products %lld and %lld overlap", (long long)segs[t - 1].idx,
+                            (long long)segs[t].idx);
     }
 
     // deps[i]: products whose output product i reads
@@ -622,21 +654,20 @@ static lrbg_status compute_levels(const lrbg_desc *ds, int64_t n, std::vector<in
             if (in.empty()) continue;
             const Range ir = in.range();
             // clusters starting before ir.hi; walk back while they may meet it (clusters are disjoint)
-            auto it = std::lower_bound(cl.begin(), cl.end(), ir.hi,
-                                       [](const Cluster &c, uintptr_t v) { return c.lo < v; });
-            while (it != cl.begin()) {
-                --it;
-                if (it->hi <= ir.lo) break;
-                if (it->count == 1) {
-                    const Mat &m = outs[it->first];
+            size_t c = (size_t)(std::lower_bound(clo.begin(), clo.end(), ir.hi) - clo.begin());
+            while (c > 0) {
+                --c;
+                if (chi[c] <= ir.lo) break;
+                if (ccount[c] == 1) {
+                    const Mat &m = outs[cfirst[c]];
                     if (mats_overlap(in, m)) add_dep(i, m.idx);
                     continue;
                 }
                 for (int64_t j = 0; j < in.cols; ++j) {
                     const uintptr_t lo = in.p + (uintptr_t)j * in.ld_bytes, hi = lo + in.row_bytes;
-                    auto sg = std::lower_bound(it->segs.begin(), it->segs.end(), hi,
+                    auto sg = std::lower_bound(segs.begin() + (ptrdiff_t)sbeg[c], segs.begin() + (ptrdiff_t)send[c], hi,
                                                [](const Seg &x, uintptr_t v) { return x.lo < v; });
-                    while (sg != it->segs.begin()) {
+                    while (sg != segs.begin() + (ptrdiff_t)sbeg[c]) {
                         --sg;
                         if (sg->hi <= lo) break;   // segments are disjoint and sorted
                         add_dep(i, sg->idx);
@@ -742,6 +773,11 @@ static void lay_tiles(const std::vector<int64_t> &prods, const lrbg_desc *ds, co
         }
     }
     std::vector<std::vector<Tile>> bt(kXcds);
+    for (int b = 0; b < kXcds; ++b) {
+        size_t nt = 0;   // exact tile count of the bin, so that its vector is allocated once
+        for (int64_t i : bins[b]) nt += (size_t)tile_count(variant[(size_t)i], ds[i]);
+        bt[b].reserve(nt);
+    }
     for (int b = 0; b < kXcds; ++b)
         for (int64_t i : bins[b]) {
             p0s.clear();
@@ -767,9 +803,10 @@ static void lay_tiles(const std::vector<int64_t> &prods, const lrbg_desc *ds, co
         sch.qinfo.push_back(off);
         ntiles = off;
     } else {
-        for (size_t slot = 0; slot < maxlen; ++slot)
-            for (int b = 0; b < kXcds; ++b)
-                sch.tiles.push_back(slot < bt[b].size() ? bt[b][slot] : Tile{0, 0, 0, 0});
+        sch.tiles.resize((size_t)tile_off + maxlen * kXcds, Tile{0, 0, 0, 0});
+        Tile *out = sch.tiles.data() + tile_off;
+        for (int b = 0; b < kXcds; ++b)
+            for (size_t slot = 0; slot < bt[b].size(); ++slot) out[slot * kXcds + (size_t)b] = bt[b][slot];
         ntiles = (int32_t)(maxlen * kXcds);
         if (queues)
             for (int b = 0; b <= kXcds; ++b) sch.qinfo.push_back(0);

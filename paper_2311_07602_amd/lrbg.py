@@ -154,8 +154,20 @@ def _stream_ptr(stream) -> Optional[int]:
 
 
 def _arr(ctype, vals):
-    vals = list(vals)
-    return (ctype * max(len(vals), 1))(*vals)
+    """vals (a sequence, or a numpy array used in place when it already has
+    the C type's width and is contiguous) as a host array; returns its
+    address as a c_void_p that keeps the array alive."""
+    import numpy as np
+    dt = np.int32 if ctype is ctypes.c_int32 else np.uint64
+    try:
+        a = np.ascontiguousarray(vals, dtype=dt)
+    except TypeError:   # null pointers given as None
+        a = np.ascontiguousarray([0 if v is None else v for v in vals], dtype=dt)
+    if a.size == 0:
+        a = np.zeros(1, dtype=dt)
+    p = ctypes.c_void_p(a.ctypes.data)
+    p._keep = a
+    return p
 
 
 # ------------------------------------------------------------ raw entry points
@@ -169,8 +181,7 @@ def lr_batched_gemm(op: int, prec: int, m: Sequence[int], n: Sequence[int], k: S
     args = [_arr(i32, m), _arr(i32, n), _arr(i32, k), _arr(vp, A), _arr(i32, lda), _arr(vp, B), _arr(i32, ldb),
             _arr(vp, S) if S is not None else None, _arr(i32, lds) if lds is not None else None,
             _arr(vp, C), _arr(i32, ldc)]
-    ptrs = [ctypes.cast(a, vp) if a is not None else None for a in args]
-    st = load().lr_batched_gemm(op, prec, count, *ptrs, _stream_ptr(stream))
+    st = load().lr_batched_gemm(op, prec, count, *args, _stream_ptr(stream))
     return _check(st, "lr_batched_gemm")
 
 
@@ -183,8 +194,7 @@ def lr_batched_lrmult(b: Sequence[int], ra: Sequence[int], rb: Sequence[int],
     args = [_arr(i32, b), _arr(i32, ra), _arr(i32, rb), _arr(vp, AV), _arr(i32, ldav), _arr(vp, BU),
             _arr(i32, ldbu), _arr(vp, AX), _arr(i32, ldax), _arr(vp, BX), _arr(i32, ldbx),
             _arr(vp, G), _arr(i32, ldg)]
-    ptrs = [ctypes.cast(a, vp) for a in args]
-    st = load().lr_batched_lrmult(count, *ptrs, _stream_ptr(stream))
+    st = load().lr_batched_lrmult(count, *args, _stream_ptr(stream))
     return _check(st, "lr_batched_lrmult")
 
 
@@ -194,7 +204,7 @@ def _round_arrays(b, ra, rb, AU, ldau, AV, ldav, AX, ldax, BU, ldbu, BX, ldbx, B
             _arr(i32, ldav), _arr(vp, AX), _arr(i32, ldax), _arr(vp, BU), _arr(i32, ldbu), _arr(vp, BX),
             _arr(i32, ldbx), _arr(vp, BV), _arr(i32, ldbv)]
     outs = [_arr(vp, U), _arr(i32, ldu), _arr(vp, V), _arr(i32, ldv)]
-    return [ctypes.cast(x, vp) for x in arrs], [ctypes.cast(x, vp) for x in outs]
+    return arrs, outs
 
 
 def lr_batched_lrmult_round(b: Sequence[int], ra: Sequence[int], rb: Sequence[int],
