@@ -85,12 +85,14 @@ __global__ void __launch_bounds__(64) lrbg_qr_head_kernel(const QrDesc *__restri
         if (act && c == j) {
             const double alpha = R[j * S + j];
             double nrm2 = 0.0;
+#pragma unroll 4
             for (int i = j + 1; i < s0; ++i) nrm2 += R[i * S + j] * R[i * S + j];
             double tau = 0.0;
             if (nrm2 > 0.0) {
                 const double beta = -copysign(sqrt(alpha * alpha + nrm2), alpha);
                 tau = (beta - alpha) / beta;
                 const double scale = 1.0 / (alpha - beta);
+#pragma unroll 4
                 for (int i = j + 1; i < s0; ++i) R[i * S + j] *= scale;
                 R[j * S + j] = beta;
             }
@@ -101,9 +103,11 @@ __global__ void __launch_bounds__(64) lrbg_qr_head_kernel(const QrDesc *__restri
         const double tau = act ? tau_[g] : 0.0;
         if (tau != 0.0 && c > j && mine) {
             double w = R[j * S + c];
+#pragma unroll 4
             for (int i = j + 1; i < s0; ++i) w += R[i * S + j] * R[i * S + c];
             const double tw = tau * w;
             R[j * S + c] -= tw;
+#pragma unroll 4
             for (int i = j + 1; i < s0; ++i) R[i * S + c] -= tw * R[i * S + j];
         }
         __syncthreads();
