@@ -124,22 +124,35 @@ __global__ void __launch_bounds__(64) lrbg_qr_head_kernel(const QrDesc *__restri
 // The pivot lane publishes its column unscaled with the scale 1 / (alpha -
 // beta); every lane scales its own column once, when the block is stored.
 // R(j, c), c >= j, sits at j S - j (j - 1) / 2 + c - j of the packed triangle.
+//
+// For 64-wide bases two wavefronts share one triangle and take alternate
+// blocks: wavefront w reduces blocks w, w + 2, w + 4, ..., wavefront 1 one
+// reflection behind wavefront 0.  Reflection j of block kb needs row j of R
+// as reflection j of block kb - 1 left it, and at any time step the two
+// wavefronts work on different rows of R, so one workgroup barrier per step
+// orders them.  This doubles the wavefronts a CU holds for the same
+// triangles in LDS (which otherwise limit it): a reflection is a dependent
+// chain (norm, square root, division, broadcast, dot product), and more
+// wavefronts hide its latency.
 template <int S>
-__global__ void __launch_bounds__(64) lrbg_qr_blocks_kernel(const QrDesc *__restrict__ descs, int count)
+__global__ void __launch_bounds__(64 * qr_waves(S)) lrbg_qr_blocks_kernel(const QrDesc *__restrict__ descs, int count)
 {
-    constexpr int G = 64 / S;
-    const int lane = threadIdx.x, g = lane / S, c = lane % S;
+    constexpr int G = 64 / S, NW = qr_waves(S);
+    // the wavefront index, known to the compiler to be uniform
+    const int wv = NW > 1 ? __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6) : 0;
+    const int lane = (int)threadIdx.x & 63, g = lane / S, c = lane % S;
     const int t = (int)blockIdx.x * G + g;
     QrDesc d{};
     if (t < count) d = descs[t];
     const int c0 = d.c0, s = d.c0 + d.c1, b = d.b, s0 = s < b ? s : b;
     constexpr int TRI = S * (S + 1) / 2;
     constexpr int RSTR = TRI + (G > 1 ? 16 : 0), XSTR = kQrRows + (G > 1 ? 2 : 0);
-    __shared__ double R_[G * RSTR];      // R's upper triangle, packed by rows
-    __shared__ double xs_[G * XSTR];     // the current reflection's unscaled tail
-    __shared__ double tau_[G], sc_[G];
+    __shared__ double R_[G * RSTR];          // R's upper triangle, packed by rows
+    __shared__ double xs_[NW * G * XSTR];    // each wavefront's current reflection tail
+    __shared__ double tau_[NW * G], sc_[NW * G];
     __shared__ int nb_[G];
-    double *R = R_ + g * RSTR, *xs = xs_ + g * XSTR;
+    double *R = R_ + g * RSTR, *xs = xs_ + (wv * G + g) * XSTR;
+    double *tw_ = tau_ + wv * G, *sw_ = sc_ + wv * G;
     auto rp = [](int j) { return j * S - j * (j - 1) / 2; };   // start of row j
     const bool mine = c < s;
     gcp cp = (gcp)(!mine ? d.w0 : c < c0 ? d.w0 + (size_t)c * d.ld0 : d.w1 + (size_t)(c - c0) * d.ld1);
@@ -148,32 +161,90 @@ __global__ void __launch_bounds__(64) lrbg_qr_blocks_kernel(const QrDesc *__rest
     gp T = tau0 + s;
     gp blk = T + (size_t)s0 * s;
     const int nblk = b > s0 ? (b - s0 + kQrRows - 1) / kQrRows : 0;
-    if (c == 0) nb_[g] = nblk;
-    for (int i = 0; i <= c; ++i) R[rp(i) + c - i] = (mine && nblk > 0) ? ws[(size_t)i * s + c] : 0.0;
+    if (wv == 0) {
+        if (c == 0) nb_[g] = nblk;
+        for (int i = 0; i <= c; ++i) R[rp(i) + c - i] = (mine && nblk > 0) ? ws[(size_t)i * s + c] : 0.0;
+    }
     __syncthreads();
     int nbmax = 0;
 #pragma unroll
     for (int q = 0; q < G; ++q) nbmax = nb_[q] > nbmax ? nb_[q] : nbmax;
+    const int steps = (nbmax + NW - 1) / NW * S;   // reflections per wavefront
 
-    for (int kb = 0; kb < nbmax; ++kb) {
-        const int r0 = s0 + kb * kQrRows;
-        const int hb = kb < nblk ? (b - r0 < kQrRows ? b - r0 : kQrRows) : 0;
-        double x[kQrRows];
-        if (hb == kQrRows && mine) {
-            // 16-byte loads: a lane's rows are contiguous in its column
-            gcp2 p2 = (gcp2)(cp + r0);
+    double x[kQrRows];
+    double my_t = 0.0, my_sc = 0.0;
+    int kb = wv - NW, j = S - 1;
+    for (int tt = 0; tt < steps + NW - 1; ++tt) {
+        const bool on = tt >= wv && tt - wv < steps;   // uniform over the wavefront
+        if (on) {
+            if (++j == S) {
+                j = 0;
+                kb += NW;
+                const int r0 = s0 + kb * kQrRows;
+                const int hb = kb < nblk ? (b - r0 < kQrRows ? b - r0 : kQrRows) : 0;
+                if (hb == kQrRows && mine) {
+                    // 16-byte loads: a lane's rows are contiguous in its column
+                    gcp2 p2 = (gcp2)(cp + r0);
 #pragma unroll
-            for (int i = 0; i < kQrRows / 2; ++i) {
-                const d2u v = p2[i];
-                x[2 * i] = v.x;
-                x[2 * i + 1] = v.y;
+                    for (int i = 0; i < kQrRows / 2; ++i) {
+                        const d2u v = p2[i];
+                        x[2 * i] = v.x;
+                        x[2 * i + 1] = v.y;
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < kQrRows; ++i) x[i] = (mine && i < hb) ? cp[r0 + i] : 0.0;
+                }
             }
-        } else {
+            if constexpr (G == 1) {
+                // One basis per wavefront: the pivot column's tail comes from
+                // lane j's registers (j is uniform) into scalar registers,
+                // and every lane forms the reflection itself.  LDS broadcasts
+                // of the tail would move 32 doubles to every lane twice per
+                // reflection, more than the CU's LDS bandwidth keeps up with.
+                double y[kQrRows];
 #pragma unroll
-            for (int i = 0; i < kQrRows; ++i) x[i] = (mine && i < hb) ? cp[r0 + i] : 0.0;
-        }
-        double my_t = 0.0, my_sc = 0.0;
-        for (int j = 0; j < S; ++j) {
+                for (int i = 0; i < kQrRows; ++i)
+                    y[i] = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x[i]), j),
+                                            __builtin_amdgcn_readlane(__double2loint(x[i]), j));
+                double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0;
+#pragma unroll
+                for (int i = 0; i < kQrRows; i += 4) {
+                    n0 += y[i] * y[i];
+                    n1 += y[i + 1] * y[i + 1];
+                    n2 += y[i + 2] * y[i + 2];
+                    n3 += y[i + 3] * y[i + 3];
+                }
+                const double nrm2 = (n0 + n1) + (n2 + n3);
+                const double alpha = R[rp(j)];
+                double tau = 0.0, scale = 0.0, beta = alpha;
+                if (nrm2 > 0.0) {
+                    beta = -copysign(sqrt(alpha * alpha + nrm2), alpha);
+                    tau = (beta - alpha) / beta;
+                    scale = 1.0 / (alpha - beta);
+                }
+                if (c == j) {
+                    R[rp(j)] = beta;
+                    my_t = tau;
+                    my_sc = scale;
+                }
+                if (tau != 0.0 && c > j) {
+                    double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+#pragma unroll
+                    for (int i = 0; i < kQrRows; i += 4) {
+                        w0 += y[i] * x[i];
+                        w1 += y[i + 1] * x[i + 1];
+                        w2 += y[i + 2] * x[i + 2];
+                        w3 += y[i + 3] * x[i + 3];
+                    }
+                    double *rjc = R + rp(j) + c - j;
+                    const double tw = tau * (*rjc + scale * ((w0 + w1) + (w2 + w3)));
+                    *rjc -= tw;
+                    const double f = tw * scale;
+#pragma unroll
+                    for (int i = 0; i < kQrRows; ++i) x[i] -= f * y[i];
+                }
+            } else {
             if (c == j) {
                 double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0;
 #pragma unroll
@@ -194,15 +265,19 @@ __global__ void __launch_bounds__(64) lrbg_qr_blocks_kernel(const QrDesc *__rest
                 }
 #pragma unroll
                 for (int i = 0; i < kQrRows; ++i) xs[i] = x[i];
-                tau_[g] = tau;
-                sc_[g] = scale;
+                tw_[g] = tau;
+                sw_[g] = scale;
                 my_t = tau;
                 my_sc = scale;
             }
-            __syncthreads();
-            const double tau = tau_[g];
+            // the pivot's stores reach the rest of its own wavefront: LDS
+            // operations of one wavefront complete in order
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const double tau = tw_[g];
             if (tau != 0.0 && c > j) {
-                const double scale = sc_[g];
+                const double scale = sw_[g];
                 double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
 #pragma unroll
                 for (int i = 0; i < kQrRows; i += 4) {
@@ -221,17 +296,18 @@ __global__ void __launch_bounds__(64) lrbg_qr_blocks_kernel(const QrDesc *__rest
 #pragma unroll
                 for (int i = 0; i < kQrRows; ++i) x[i] -= f * xs[i];
             }
-            __syncthreads();
-        }
-        if (mine && kb < nblk) {
-            gp bp = blk + (size_t)kb * (s + (size_t)kQrRows * s);
-            gp2 Y = (gp2)(bp + s + (size_t)c * kQrRows);
+            }
+            if (j == S - 1 && mine && kb < nblk) {
+                gp bp = blk + (size_t)kb * (s + (size_t)kQrRows * s);
+                gp2 Y = (gp2)(bp + s + (size_t)c * kQrRows);
 #pragma unroll
-            for (int i = 0; i < kQrRows / 2; ++i) Y[i] = d2u{x[2 * i] * my_sc, x[2 * i + 1] * my_sc};
-            bp[c] = my_t;
+                for (int i = 0; i < kQrRows / 2; ++i) Y[i] = d2u{x[2 * i] * my_sc, x[2 * i + 1] * my_sc};
+                bp[c] = my_t;
+            }
         }
+        __syncthreads();
     }
-    if (mine && nblk > 0)
+    if (wv == 0 && mine && nblk > 0)
         for (int i = 0; i <= c; ++i) ws[(size_t)i * s + c] = R[rp(i) + c - i];
 }
 
@@ -299,17 +375,34 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
         double u[RH];
 #pragma unroll
         for (int i = 0; i < RH; ++i) u[i] = 0.0;
-        for (int j = S - 1; j >= 0; --j) {
+        // Reflections past the basis's width are the identity (tau = 0), and
+        // so is any other with tau = 0: it is applied as such rather than
+        // skipped, so that no branch waits on the LDS read of tau.  The tail
+        // stays in registers for the update and the next reflection's tail is
+        // read a step ahead (LDS, not registers, limits the wavefronts here).
+        const int jtop = (G == 1 ? s : S) - 1;
+        double yc[RH];
+        {
+            const double *y = Yl + (jtop > 0 ? jtop : 0) * kQrRows + RH * h;
+#pragma unroll
+            for (int i = 0; i < RH; ++i) yc[i] = y[i];
+        }
+        for (int j = jtop; j >= 0; --j) {
             const double tau = tl[j];
-            if (tau == 0.0) continue;
-            const double *y = Yl + j * kQrRows + RH * h;
-            double w0 = (mine && top) ? Z[j * KZ + c] : 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+            const double zj = (mine && top) ? Z[j * KZ + c] : 0.0;
+            double yn[RH];
+            {
+                const double *y = Yl + (j > 0 ? j - 1 : 0) * kQrRows + RH * h;
+#pragma unroll
+                for (int i = 0; i < RH; ++i) yn[i] = y[i];
+            }
+            double w0 = zj, w1 = 0.0, w2 = 0.0, w3 = 0.0;
 #pragma unroll
             for (int i = 0; i < RH; i += 4) {
-                w0 += y[i] * u[i];
-                w1 += y[i + 1] * u[i + 1];
-                w2 += y[i + 2] * u[i + 2];
-                w3 += y[i + 3] * u[i + 3];
+                w0 += yc[i] * u[i];
+                w1 += yc[i + 1] * u[i + 1];
+                w2 += yc[i + 2] * u[i + 2];
+                w3 += yc[i + 3] * u[i + 3];
             }
             double w = (w0 + w1) + (w2 + w3);
             if constexpr (SPLIT) {
@@ -321,10 +414,12 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
                 w = __hiloint2double((int)sh[0], (int)sl[0]) + __hiloint2double((int)sh[1], (int)sl[1]);
             }
             const double tw = tau * w;
-            if (mine && top) Z[j * KZ + c] -= tw;
-            __asm__ volatile("" ::: "memory");   // as in the factorisation: reload y
+            if (mine && top) Z[j * KZ + c] = zj - tw;
 #pragma unroll
-            for (int i = 0; i < RH; ++i) u[i] -= tw * y[i];
+            for (int i = 0; i < RH; ++i) {
+                u[i] -= tw * yc[i];
+                yc[i] = yn[i];
+            }
         }
         if (mine && live) {
             gp o = (gp)d.out + (size_t)c * d.ldo + r0 + RH * h;
@@ -353,9 +448,11 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
             if (tau == 0.0) continue;
             const double *y = Yl + pk(j) - j - 1;   // y[i] for i > j
             double w = Z[j * KZ + c];
+#pragma unroll 4
             for (int i = j + 1; i < s0; ++i) w += y[i] * Z[i * KZ + c];
             const double tw = tau * w;
             Z[j * KZ + c] -= tw;
+#pragma unroll 4
             for (int i = j + 1; i < s0; ++i) Z[i * KZ + c] -= tw * y[i];
         }
         gp o = (gp)d.out + (size_t)c * d.ldo;
@@ -429,17 +526,17 @@ __global__ void __launch_bounds__(64) lrbg_add_core_kernel(const AddCoreDesc *__
 // per: descriptors per workgroup of each class (16, 32, 64 wide)
 template <typename D, typename K16, typename K32, typename K64>
 static int launch_by_class(int cols, const D *descs, int count, void *stream, K16 k16, K32 k32, K64 k64,
-                           const int (&per)[3])
+                           const int (&per)[3], int threads = 64)
 {
     if (count <= 0) return 0;
     hipStream_t st = (hipStream_t)stream;
     auto grid = [&](int q) { return dim3((unsigned)((count + per[q] - 1) / per[q])); };
     if (cols == 16)
-        hipLaunchKernelGGL(k16, grid(0), dim3(64), 0, st, descs, count);
+        hipLaunchKernelGGL(k16, grid(0), dim3(threads), 0, st, descs, count);
     else if (cols == 32)
-        hipLaunchKernelGGL(k32, grid(1), dim3(64), 0, st, descs, count);
+        hipLaunchKernelGGL(k32, grid(1), dim3(threads), 0, st, descs, count);
     else if (cols == 64)
-        hipLaunchKernelGGL(k64, grid(2), dim3(64), 0, st, descs, count);
+        hipLaunchKernelGGL(k64, grid(2), dim3(threads), 0, st, descs, count);
     else
         return (int)hipErrorInvalidValue;
     return (int)hipGetLastError();
@@ -451,7 +548,7 @@ int launch_qr_factor(int cols, const QrDesc *descs, int count, void *stream)
                                    lrbg_qr_head_kernel<64>, {4, 2, 1});
     if (rc != 0) return rc;
     return launch_by_class(cols, descs, count, stream, lrbg_qr_blocks_kernel<16>, lrbg_qr_blocks_kernel<32>,
-                           lrbg_qr_blocks_kernel<64>, {4, 2, 1});
+                           lrbg_qr_blocks_kernel<64>, {4, 2, 1}, 64 * qr_waves(cols));
 }
 
 int launch_qr_apply(int cols, int kmax, const QrDesc *descs, int count, void *stream)
