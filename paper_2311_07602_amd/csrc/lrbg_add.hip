@@ -311,29 +311,22 @@ __global__ void __launch_bounds__(64 * qr_waves(S)) lrbg_qr_blocks_kernel(const 
         for (int i = 0; i <= c; ++i) ws[(size_t)i * s + c] = R[rp(i) + c - i];
 }
 
-// As the factorisation, G = 64 / S stacked bases per wavefront; lane c of a
-// group computes output column c < min(kmax, S) (a basis of width s has
-// rank <= s <= S, so any later columns are zero and are filled at the end).
-// The top part Z is S x KZ with KZ = min(S, kmax rounded up to 16): LDS, not
-// registers, decides how many wavefronts a CU holds here.  The first s0
-// rows' reflection tails are staged packed (column j's s0 - 1 - j entries at
-// j (2 s0 - j - 1) / 2), so they fit the room of one block's tails.
-// When a 64-wide basis keeps at most 32 columns (the usual case: two rank-r
-// blocks added and rounded back to rank r), lanes c and c + 32 share output
-// column c, each holding half of a block's rows; their partial dot products
-// meet through one lane-half swap, so each reflection costs a lane half the
-// multiply-adds and tail reads.
+// Bases 16 or 32 wide.  As the factorisation, G = 64 / S stacked bases per
+// wavefront; lane c of a group computes output column c < min(kmax, S) (a
+// basis of width s has rank <= s <= S, so any later columns are zero and are
+// filled at the end).  The top part Z is S x KZ with KZ = min(S, kmax
+// rounded up to 16): LDS, not registers, decides how many wavefronts a CU
+// holds here.  The first s0 rows' reflection tails are staged packed
+// (column j's s0 - 1 - j entries at j (2 s0 - j - 1) / 2), so they fit the
+// room of one block's tails.
 template <int S, int KZ>
 __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restrict__ descs, int count)
 {
-    static_assert(KZ <= S && KZ % 16 == 0, "top part width");
-    constexpr int G = 64 / S;
-    constexpr bool SPLIT = G == 1 && 2 * KZ <= S;   // two lanes per output column
-    constexpr int RH = SPLIT ? kQrRows / 2 : kQrRows;   // block rows per lane
-    const int lane = threadIdx.x, g = SPLIT ? 0 : lane / S, c = SPLIT ? lane & 31 : lane % S;
-    const int h = SPLIT ? lane >> 5 : 0;   // row half of a block
-    const int li = SPLIT ? lane : c;       // loader index within the group
-    constexpr int NL = SPLIT ? 64 : S;     // loaders per group
+    static_assert(KZ <= S && KZ % 16 == 0 && S < 64, "top part width, several bases per wavefront");
+    constexpr int G = 64 / S, RH = kQrRows;
+    const int lane = threadIdx.x, g = lane / S, c = lane % S;
+    const int li = c;                      // loader index within the group
+    constexpr int NL = S;                  // loaders per group
     const int t = (int)blockIdx.x * G + g;
     QrDesc d{};
     if (t < count) d = descs[t];
@@ -350,9 +343,8 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
     __shared__ int nb_[G];
     double *Z = Z_ + g * ZSTR, *Yl = Yl_ + g * YSTR, *tl = tl_ + g * TSTR;
     const bool mine = c < km && c < KZ;       // km <= S implies km <= KZ
-    const bool top = h == 0;                  // the lane that owns Z(., c)
     gcp xk = (gcp)d.xk;
-    if (c < KZ && top)
+    if (c < KZ)
         for (int j = 0; j < S; ++j) Z[j * KZ + c] = (mine && j < s) ? xk[j + (size_t)c * s] : 0.0;
     gcp ws = (gcp)d.ws;
     gcp tau0 = ws + (size_t)s * s;
@@ -380,19 +372,19 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
         // skipped, so that no branch waits on the LDS read of tau.  The tail
         // stays in registers for the update and the next reflection's tail is
         // read a step ahead (LDS, not registers, limits the wavefronts here).
-        const int jtop = (G == 1 ? s : S) - 1;
+        const int jtop = S - 1;
         double yc[RH];
         {
-            const double *y = Yl + (jtop > 0 ? jtop : 0) * kQrRows + RH * h;
+            const double *y = Yl + jtop * kQrRows;
 #pragma unroll
             for (int i = 0; i < RH; ++i) yc[i] = y[i];
         }
         for (int j = jtop; j >= 0; --j) {
             const double tau = tl[j];
-            const double zj = (mine && top) ? Z[j * KZ + c] : 0.0;
+            const double zj = mine ? Z[j * KZ + c] : 0.0;
             double yn[RH];
             {
-                const double *y = Yl + (j > 0 ? j - 1 : 0) * kQrRows + RH * h;
+                const double *y = Yl + (j > 0 ? j - 1 : 0) * kQrRows;
 #pragma unroll
                 for (int i = 0; i < RH; ++i) yn[i] = y[i];
             }
@@ -404,17 +396,8 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
                 w2 += yc[i + 2] * u[i + 2];
                 w3 += yc[i + 3] * u[i + 3];
             }
-            double w = (w0 + w1) + (w2 + w3);
-            if constexpr (SPLIT) {
-                // add the other half's partial: after the swap one result holds
-                // this lane's value and the other its partner's, in either order
-                const unsigned lo = __double2loint(w), hi = __double2hiint(w);
-                const auto sl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-                const auto sh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-                w = __hiloint2double((int)sh[0], (int)sl[0]) + __hiloint2double((int)sh[1], (int)sl[1]);
-            }
-            const double tw = tau * w;
-            if (mine && top) Z[j * KZ + c] = zj - tw;
+            const double tw = tau * ((w0 + w1) + (w2 + w3));
+            if (mine) Z[j * KZ + c] = zj - tw;
 #pragma unroll
             for (int i = 0; i < RH; ++i) {
                 u[i] -= tw * yc[i];
@@ -422,16 +405,15 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
             }
         }
         if (mine && live) {
-            gp o = (gp)d.out + (size_t)c * d.ldo + r0 + RH * h;
-            const int hv = hb - RH * h;        // valid rows of this lane's half
-            if (hv >= RH) {
+            gp o = (gp)d.out + (size_t)c * d.ldo + r0;
+            if (hb >= RH) {
                 gp2 o2 = (gp2)o;
 #pragma unroll
                 for (int i = 0; i < RH / 2; ++i) o2[i] = d2u{u[2 * i], u[2 * i + 1]};
             } else {
 #pragma unroll
                 for (int i = 0; i < RH; ++i)
-                    if (i < hv) o[i] = u[i];
+                    if (i < hb) o[i] = u[i];
             }
         }
     }
@@ -442,7 +424,7 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
         for (int i = j + 1 + li; i < s0; i += NL) Yl[pk(j) + i - j - 1] = T[(size_t)i * s + j];
     for (int e = li; e < S; e += NL) tl[e] = e < s ? tau0[e] : 0.0;
     __syncthreads();
-    if (mine && top) {
+    if (mine) {
         for (int j = S - 1; j >= 0; --j) {
             const double tau = j < s0 ? tl[j] : 0.0;
             if (tau == 0.0) continue;
@@ -459,11 +441,184 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
         for (int i = 0; i < s0; ++i) o[i] = Z[i * KZ + c];
     }
     // output columns S .. kmax - 1 (kmax above the class width): zero
-    if (top)
-        for (int col = S + c; col < km; col += S) {
-            gp o = (gp)d.out + (size_t)col * d.ldo;
-            for (int i = 0; i < b; ++i) o[i] = 0.0;
+    for (int col = S + c; col < km; col += S) {
+        gp o = (gp)d.out + (size_t)col * d.ldo;
+        for (int i = 0; i < b; ++i) o[i] = 0.0;
+    }
+}
+
+// The same application for 64-wide bases (one basis per wavefront), with the
+// tails staged CH = 16 reflections at a time instead of a whole block and
+// the taus in registers (lane j holds tau_j, read out by the uniform j): LDS
+// then holds Z and 4 KB of tails (20 KB against 33 KB at kmax <= 32, eight
+// wavefronts per CU instead of four), to hide each reflection's dependent
+// chain.  The next piece of tails is loaded into registers while the
+// current one is applied and written to LDS at the piece boundary, so no
+// wavefront waits on HBM there.  The first s0 rows' tails are staged in
+// pieces of at most the same size, packed by columns as above.
+template <int KZ>
+__global__ void __launch_bounds__(64) lrbg_qr_apply64_kernel(const QrDesc *__restrict__ descs, int count)
+{
+    constexpr int S = 64;
+    static_assert(KZ <= S && KZ % 16 == 0, "top part width");
+    constexpr bool SPLIT = 2 * KZ <= S;                 // two lanes per output column
+    constexpr int RH = SPLIT ? kQrRows / 2 : kQrRows;   // block rows per lane
+    constexpr int CH = 16, YC = CH * kQrRows, PF = YC / 64;
+    const int lane = threadIdx.x, c = SPLIT ? lane & 31 : lane;
+    const int h = SPLIT ? lane >> 5 : 0;   // row half of a block
+    if ((int)blockIdx.x >= count) return;
+    const QrDesc d = descs[blockIdx.x];
+    const int s = d.c0 + d.c1, b = d.b, s0 = s < b ? s : b, km = d.kmax;
+    __shared__ double Z[S * KZ];    // s x kmax top part, Z[j * KZ + c]
+    __shared__ double Yl[YC];       // tails of reflections jlo .. jlo + CH - 1 (column j at (j - jlo) kQrRows)
+    auto bcast = [](double v, int l) {    // lane l's v, l uniform
+        return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                                __builtin_amdgcn_readlane(__double2loint(v), l));
+    };
+    const bool mine = c < km && c < KZ;
+    const bool top = h == 0;        // the lane that owns Z(., c)
+    gcp xk = (gcp)d.xk;
+    if (c < KZ && top)
+        for (int j = 0; j < S; ++j) Z[j * KZ + c] = (mine && j < s) ? xk[j + (size_t)c * s] : 0.0;
+    gcp ws = (gcp)d.ws;
+    gcp tau0 = ws + (size_t)s * s;
+    gcp T = tau0 + s;
+    gcp blk = T + (size_t)s0 * s;
+    const int nblk = b > s0 ? (b - s0 + kQrRows - 1) / kQrRows : 0;
+    const int jtop = s - 1, qtop = jtop > 0 ? jtop / CH : 0;
+
+    // piece q of block kb's tails (reflections q CH .. q CH + CH - 1) and the
+    // block's taus, into registers
+    double pf[PF], pt = 0.0;
+    auto fetch = [&](int kb, int q) {
+        gcp bp = blk + (size_t)kb * (s + (size_t)kQrRows * s);
+        const int base = q * YC;
+#pragma unroll
+        for (int p = 0; p < PF; ++p) {
+            const int e = lane + 64 * p;
+            pf[p] = base + e < s * kQrRows ? bp[s + base + e] : 0.0;
         }
+        pt = lane < s ? bp[lane] : 0.0;
+    };
+    if (nblk > 0) fetch(nblk - 1, qtop);
+    double tc = 0.0;                           // this block's tau of the lane's index
+    for (int kb = nblk - 1; kb >= 0; --kb) {
+        const int r0 = s0 + kb * kQrRows, hb = b - r0 < kQrRows ? b - r0 : kQrRows;
+        double u[RH];
+#pragma unroll
+        for (int i = 0; i < RH; ++i) u[i] = 0.0;
+        for (int q = qtop; q >= 0; --q) {
+            __syncthreads();                   // the previous piece's reads are done
+#pragma unroll
+            for (int p = 0; p < PF; ++p) Yl[lane + 64 * p] = pf[p];
+            if (q == qtop) tc = pt;
+            __syncthreads();
+            if (q > 0)
+                fetch(kb, q - 1);
+            else if (kb > 0)
+                fetch(kb - 1, qtop);
+            // as in the general kernel: every reflection applied (tau = 0 is
+            // the identity), the tail kept in registers and the next one
+            // read a step ahead
+            const int jlo = q * CH, jhi = jtop < jlo + CH - 1 ? jtop : jlo + CH - 1;
+            double yc[RH];
+            {
+                const double *y = Yl + (jhi > jlo ? jhi - jlo : 0) * kQrRows + RH * h;
+#pragma unroll
+                for (int i = 0; i < RH; ++i) yc[i] = y[i];
+            }
+            for (int j = jhi; j >= jlo; --j) {
+                const double tau = bcast(tc, j);
+                const double zj = (mine && top) ? Z[j * KZ + c] : 0.0;
+                double yn[RH];
+                {
+                    const double *y = Yl + (j > jlo ? j - 1 - jlo : 0) * kQrRows + RH * h;
+#pragma unroll
+                    for (int i = 0; i < RH; ++i) yn[i] = y[i];
+                }
+                double w0 = zj, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+#pragma unroll
+                for (int i = 0; i < RH; i += 4) {
+                    w0 += yc[i] * u[i];
+                    w1 += yc[i + 1] * u[i + 1];
+                    w2 += yc[i + 2] * u[i + 2];
+                    w3 += yc[i + 3] * u[i + 3];
+                }
+                double w = (w0 + w1) + (w2 + w3);
+                if constexpr (SPLIT) {
+                    const unsigned lo = __double2loint(w), hi = __double2hiint(w);
+                    const auto sl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+                    const auto sh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+                    w = __hiloint2double((int)sh[0], (int)sl[0]) + __hiloint2double((int)sh[1], (int)sl[1]);
+                }
+                const double tw = tau * w;
+                if (mine && top) Z[j * KZ + c] = zj - tw;
+#pragma unroll
+                for (int i = 0; i < RH; ++i) {
+                    u[i] -= tw * yc[i];
+                    yc[i] = yn[i];
+                }
+            }
+        }
+        if (mine) {
+            gp o = (gp)d.out + (size_t)c * d.ldo + r0 + RH * h;
+            const int hv = hb - RH * h;        // valid rows of this lane's half
+            if (hv >= RH) {
+                gp2 o2 = (gp2)o;
+#pragma unroll
+                for (int i = 0; i < RH / 2; ++i) o2[i] = d2u{u[2 * i], u[2 * i + 1]};
+            } else {
+#pragma unroll
+                for (int i = 0; i < RH; ++i)
+                    if (i < hv) o[i] = u[i];
+            }
+        }
+    }
+
+    // the first s0 rows: reflections with pivots on the diagonal, j = s0 - 1
+    // down to 0; column j's tail (rows j + 1 .. s0 - 1) at pk(j) of the
+    // packed order, staged in pieces of consecutive columns of at most YC
+    // entries
+    auto pk = [s0](int j) { return j * (2 * s0 - j - 1) / 2; };
+    tc = lane < s ? tau0[lane] : 0.0;
+    for (int jhi = s0 - 1; jhi >= 0;) {
+        int jlo = jhi;
+        while (jlo > 0 && pk(jhi + 1) - pk(jlo - 1) <= YC) --jlo;
+        const int e0 = pk(jlo), ne = pk(jhi + 1) - e0;
+        double g[PF];
+        int jj = jlo;
+#pragma unroll
+        for (int p = 0; p < PF; ++p) {
+            const int e = lane + 64 * p;
+            g[p] = 0.0;
+            if (e < ne) {
+                while (pk(jj + 1) <= e0 + e) ++jj;
+                g[p] = T[(size_t)(e0 + e - pk(jj) + jj + 1) * s + jj];
+            }
+        }
+        __syncthreads();                       // the previous piece's reads are done
+#pragma unroll
+        for (int p = 0; p < PF; ++p) Yl[lane + 64 * p] = g[p];
+        __syncthreads();
+        for (int j = jhi; j >= jlo; --j) {
+            const double tau = bcast(tc, j);
+            if (mine && top) {
+                const double *y = Yl + pk(j) - e0 - j - 1;   // y[i] for i > j
+                double w = Z[j * KZ + c];
+#pragma unroll 4
+                for (int i = j + 1; i < s0; ++i) w += y[i] * Z[i * KZ + c];
+                const double tw = tau * w;
+                Z[j * KZ + c] -= tw;
+#pragma unroll 4
+                for (int i = j + 1; i < s0; ++i) Z[i * KZ + c] -= tw * y[i];
+            }
+        }
+        jhi = jlo - 1;
+    }
+    if (mine && top) {
+        gp o = (gp)d.out + (size_t)c * d.ldo;
+        for (int i = 0; i < s0; ++i) o[i] = Z[i * KZ + c];
+    }
 }
 
 template <int S>
@@ -553,15 +708,24 @@ int launch_qr_factor(int cols, const QrDesc *descs, int count, void *stream)
 
 int launch_qr_apply(int cols, int kmax, const QrDesc *descs, int count, void *stream)
 {
+    if (count <= 0) return 0;
+    hipStream_t st = (hipStream_t)stream;
     const int kz = kmax <= 16 ? 16 : kmax <= 32 ? 32 : 64;
-    if (cols == 16 || kz == 16)
-        return launch_by_class(cols, descs, count, stream, lrbg_qr_apply_kernel<16, 16>,
-                               lrbg_qr_apply_kernel<32, 16>, lrbg_qr_apply_kernel<64, 16>, {4, 2, 1});
-    if (cols == 32 || kz == 32)
-        return launch_by_class(cols, descs, count, stream, lrbg_qr_apply_kernel<16, 16>,
-                               lrbg_qr_apply_kernel<32, 32>, lrbg_qr_apply_kernel<64, 32>, {4, 2, 1});
-    return launch_by_class(cols, descs, count, stream, lrbg_qr_apply_kernel<16, 16>, lrbg_qr_apply_kernel<32, 32>,
-                           lrbg_qr_apply_kernel<64, 64>, {4, 2, 1});
+    if (cols == 16)
+        hipLaunchKernelGGL((lrbg_qr_apply_kernel<16, 16>), dim3((count + 3) / 4), dim3(64), 0, st, descs, count);
+    else if (cols == 32 && kz == 16)
+        hipLaunchKernelGGL((lrbg_qr_apply_kernel<32, 16>), dim3((count + 1) / 2), dim3(64), 0, st, descs, count);
+    else if (cols == 32)
+        hipLaunchKernelGGL((lrbg_qr_apply_kernel<32, 32>), dim3((count + 1) / 2), dim3(64), 0, st, descs, count);
+    else if (cols == 64 && kz == 16)
+        hipLaunchKernelGGL(lrbg_qr_apply64_kernel<16>, dim3(count), dim3(64), 0, st, descs, count);
+    else if (cols == 64 && kz == 32)
+        hipLaunchKernelGGL(lrbg_qr_apply64_kernel<32>, dim3(count), dim3(64), 0, st, descs, count);
+    else if (cols == 64)
+        hipLaunchKernelGGL(lrbg_qr_apply64_kernel<64>, dim3(count), dim3(64), 0, st, descs, count);
+    else
+        return (int)hipErrorInvalidValue;
+    return (int)hipGetLastError();
 }
 
 int launch_add_core(int cols, const AddCoreDesc *descs, int count, void *stream)
