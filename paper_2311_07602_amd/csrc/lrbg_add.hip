@@ -66,9 +66,10 @@ __global__ void __launch_bounds__(64) lrbg_qr_head_kernel(const QrDesc *__restri
     QrDesc d{};
     if (t < count) d = descs[t];
     const int c0 = d.c0, s = d.c0 + d.c1, b = d.b, s0 = s < b ? s : b;
-    constexpr int RSTR = S * S + (G > 1 ? 16 : 0);
-    __shared__ double R_[G * RSTR];      // the first rows, row-major, stride S
-    __shared__ double tau_[G];
+    // rows padded to an odd stride: lane i reading column j (row i) and lane
+    // c reading row i (column c) both stay off each other's banks
+    constexpr int SP = S + 1, RSTR = S * SP + (G > 1 ? 16 : 0);
+    __shared__ double R_[G * RSTR];      // the first rows, row-major, stride SP
     double *R = R_ + g * RSTR;
     const bool mine = c < s;
     gcp cp = (gcp)(!mine ? d.w0 : c < c0 ? d.w0 + (size_t)c * d.ld0 : d.w1 + (size_t)(c - c0) * d.ld1);
@@ -76,47 +77,51 @@ __global__ void __launch_bounds__(64) lrbg_qr_head_kernel(const QrDesc *__restri
     gp tau0 = ws + (size_t)s * s;
     gp T = tau0 + s;
 
-    // Householder QR in LDS, pivots on the diagonal
-    for (int i = 0; i < S; ++i) R[i * S + c] = (mine && i < s0) ? cp[i] : 0.0;
+    // Householder QR in LDS, pivots on the diagonal.  The group forms each
+    // reflection together: lane i holds row i of the pivot column, the
+    // squared norm is a sum over the group's lanes, and every lane derives
+    // beta, tau and the scale itself; lane i scales its own entry.
+    for (int i = 0; i < S; ++i) R[i * SP + c] = (mine && i < s0) ? cp[i] : 0.0;
     __syncthreads();
     double my_tau = 0.0;
     for (int j = 0; j < S; ++j) {
         const bool act = j < s0;
-        if (act && c == j) {
-            const double alpha = R[j * S + j];
-            double nrm2 = 0.0;
-#pragma unroll 4
-            for (int i = j + 1; i < s0; ++i) nrm2 += R[i * S + j] * R[i * S + j];
-            double tau = 0.0;
-            if (nrm2 > 0.0) {
-                const double beta = -copysign(sqrt(alpha * alpha + nrm2), alpha);
-                tau = (beta - alpha) / beta;
-                const double scale = 1.0 / (alpha - beta);
-#pragma unroll 4
-                for (int i = j + 1; i < s0; ++i) R[i * S + j] *= scale;
-                R[j * S + j] = beta;
-            }
-            tau_[g] = tau;
-            my_tau = tau;
+        const double xi = (c > j && c < s0) ? R[c * SP + j] : 0.0;
+        double nrm2 = xi * xi;
+#pragma unroll
+        for (int m = 1; m < S; m <<= 1) nrm2 += __shfl_xor(nrm2, m);
+        const double alpha = R[j * SP + j];
+        double tau = 0.0;
+        if (act && nrm2 > 0.0) {
+            const double beta = -copysign(sqrt(alpha * alpha + nrm2), alpha);
+            tau = (beta - alpha) / beta;
+            const double scale = 1.0 / (alpha - beta);
+            if (c > j && c < s0) R[c * SP + j] = xi * scale;
+            if (c == j) R[j * SP + j] = beta;
         }
+        if (c == j) my_tau = tau;
         __syncthreads();
-        const double tau = act ? tau_[g] : 0.0;
         if (tau != 0.0 && c > j && mine) {
-            double w = R[j * S + c];
+            double w0 = R[j * SP + c], w1 = 0.0;
+            int i = j + 1;
 #pragma unroll 4
-            for (int i = j + 1; i < s0; ++i) w += R[i * S + j] * R[i * S + c];
-            const double tw = tau * w;
-            R[j * S + c] -= tw;
+            for (; i + 1 < s0; i += 2) {
+                w0 += R[i * SP + j] * R[i * SP + c];
+                w1 += R[(i + 1) * SP + j] * R[(i + 1) * SP + c];
+            }
+            if (i < s0) w0 += R[i * SP + j] * R[i * SP + c];
+            const double tw = tau * (w0 + w1);
+            R[j * SP + c] -= tw;
 #pragma unroll 4
-            for (int i = j + 1; i < s0; ++i) R[i * S + c] -= tw * R[i * S + j];
+            for (int i = j + 1; i < s0; ++i) R[i * SP + c] -= tw * R[i * SP + j];
         }
         __syncthreads();
     }
     if (mine) {
-        for (int i = 0; i < s0; ++i) T[(size_t)i * s + c] = R[i * S + c];
+        for (int i = 0; i < s0; ++i) T[(size_t)i * s + c] = R[i * SP + c];
         tau0[c] = my_tau;
         // R so far: the triangle, zeros below it (rows s0 .. s - 1 too)
-        for (int i = 0; i < s; ++i) ws[(size_t)i * s + c] = (i <= c && i < s0) ? R[i * S + c] : 0.0;
+        for (int i = 0; i < s; ++i) ws[(size_t)i * s + c] = (i <= c && i < s0) ? R[i * SP + c] : 0.0;
     }
 }
 
