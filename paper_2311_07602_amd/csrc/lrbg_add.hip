@@ -323,14 +323,18 @@ __global__ void __launch_bounds__(64 * qr_waves(S)) lrbg_qr_blocks_kernel(const 
 // rounded up to 16): LDS, not registers, decides how many wavefronts a CU
 // holds here.  The first s0 rows' reflection tails are staged packed
 // (column j's s0 - 1 - j entries at j (2 s0 - j - 1) / 2), so they fit the
-// room of one block's tails.
+// room of one block's tails.  A 32-wide basis keeping at most 16 columns
+// splits each block's rows between lanes c and c + 16 of its group, whose
+// partial dot products meet through one swap of 16-lane rows.
 template <int S, int KZ>
 __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restrict__ descs, int count)
 {
     static_assert(KZ <= S && KZ % 16 == 0 && S < 64, "top part width, several bases per wavefront");
-    constexpr int G = 64 / S, RH = kQrRows;
-    const int lane = threadIdx.x, g = lane / S, c = lane % S;
-    const int li = c;                      // loader index within the group
+    constexpr int G = 64 / S;
+    constexpr bool SPLIT = S == 32 && 2 * KZ <= S;      // two lanes per output column
+    constexpr int RH = SPLIT ? kQrRows / 2 : kQrRows;   // block rows per lane
+    const int lane = threadIdx.x, g = lane / S, li = lane % S;   // li: loader index within the group
+    const int c = SPLIT ? li & 15 : li, h = SPLIT ? li >> 4 : 0;   // output column, row half
     constexpr int NL = S;                  // loaders per group
     const int t = (int)blockIdx.x * G + g;
     QrDesc d{};
@@ -348,8 +352,9 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
     __shared__ int nb_[G];
     double *Z = Z_ + g * ZSTR, *Yl = Yl_ + g * YSTR, *tl = tl_ + g * TSTR;
     const bool mine = c < km && c < KZ;       // km <= S implies km <= KZ
+    const bool top = h == 0;                  // the lane that owns Z(., c)
     gcp xk = (gcp)d.xk;
-    if (c < KZ)
+    if (c < KZ && top)
         for (int j = 0; j < S; ++j) Z[j * KZ + c] = (mine && j < s) ? xk[j + (size_t)c * s] : 0.0;
     gcp ws = (gcp)d.ws;
     gcp tau0 = ws + (size_t)s * s;
@@ -380,16 +385,16 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
         const int jtop = S - 1;
         double yc[RH];
         {
-            const double *y = Yl + jtop * kQrRows;
+            const double *y = Yl + jtop * kQrRows + RH * h;
 #pragma unroll
             for (int i = 0; i < RH; ++i) yc[i] = y[i];
         }
         for (int j = jtop; j >= 0; --j) {
             const double tau = tl[j];
-            const double zj = mine ? Z[j * KZ + c] : 0.0;
+            const double zj = (mine && top) ? Z[j * KZ + c] : 0.0;
             double yn[RH];
             {
-                const double *y = Yl + (j > 0 ? j - 1 : 0) * kQrRows;
+                const double *y = Yl + (j > 0 ? j - 1 : 0) * kQrRows + RH * h;
 #pragma unroll
                 for (int i = 0; i < RH; ++i) yn[i] = y[i];
             }
@@ -401,8 +406,17 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
                 w2 += yc[i + 2] * u[i + 2];
                 w3 += yc[i + 3] * u[i + 3];
             }
-            const double tw = tau * ((w0 + w1) + (w2 + w3));
-            if (mine) Z[j * KZ + c] = zj - tw;
+            double w = (w0 + w1) + (w2 + w3);
+            if constexpr (SPLIT) {
+                // after the swap one result holds this lane's partial and the
+                // other its partner's (lane ^ 16), in either order
+                const unsigned lo = __double2loint(w), hi = __double2hiint(w);
+                const auto sl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+                const auto sh = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+                w = __hiloint2double((int)sh[0], (int)sl[0]) + __hiloint2double((int)sh[1], (int)sl[1]);
+            }
+            const double tw = tau * w;
+            if (mine && top) Z[j * KZ + c] = zj - tw;
 #pragma unroll
             for (int i = 0; i < RH; ++i) {
                 u[i] -= tw * yc[i];
@@ -410,15 +424,16 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
             }
         }
         if (mine && live) {
-            gp o = (gp)d.out + (size_t)c * d.ldo + r0;
-            if (hb >= RH) {
+            gp o = (gp)d.out + (size_t)c * d.ldo + r0 + RH * h;
+            const int hv = hb - RH * h;        // valid rows of this lane's part
+            if (hv >= RH) {
                 gp2 o2 = (gp2)o;
 #pragma unroll
                 for (int i = 0; i < RH / 2; ++i) o2[i] = d2u{u[2 * i], u[2 * i + 1]};
             } else {
 #pragma unroll
                 for (int i = 0; i < RH; ++i)
-                    if (i < hb) o[i] = u[i];
+                    if (i < hv) o[i] = u[i];
             }
         }
     }
@@ -429,7 +444,7 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
         for (int i = j + 1 + li; i < s0; i += NL) Yl[pk(j) + i - j - 1] = T[(size_t)i * s + j];
     for (int e = li; e < S; e += NL) tl[e] = e < s ? tau0[e] : 0.0;
     __syncthreads();
-    if (mine) {
+    if (mine && top) {
         for (int j = S - 1; j >= 0; --j) {
             const double tau = j < s0 ? tl[j] : 0.0;
             if (tau == 0.0) continue;
@@ -446,7 +461,7 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
         for (int i = 0; i < s0; ++i) o[i] = Z[i * KZ + c];
     }
     // output columns S .. kmax - 1 (kmax above the class width): zero
-    for (int col = S + c; col < km; col += S) {
+    for (int col = S + li; col < km; col += S) {
         gp o = (gp)d.out + (size_t)col * d.ldo;
         for (int i = 0; i < b; ++i) o[i] = 0.0;
     }
