@@ -706,8 +706,12 @@ static void lay_tiles(const std::vector<int64_t> &prods, const lrbg_desc *ds, co
     };
     std::vector<P> ps;
     ps.reserve(prods.size());
-    for (int64_t i : prods) ps.push_back(P{i, est_time(ds[i])});
-    std::stable_sort(ps.begin(), ps.end(), [](const P &x, const P &y) { return x.t > y.t; });
+    bool uniform = true;   // a batch of one shape needs no sorting
+    for (int64_t i : prods) {
+        ps.push_back(P{i, est_time(ds[i])});
+        uniform = uniform && ps.back().t == ps.front().t;
+    }
+    if (!uniform) std::stable_sort(ps.begin(), ps.end(), [](const P &x, const P &y) { return x.t > y.t; });
     std::vector<int32_t> p0s, edge;
     if ((flags & LRBG_PLAN_DUAL) && queues) {
         // 16 queues, role-major: q = role * 8 + xcd; role 0 = matrix-core-bound
@@ -840,8 +844,11 @@ static void layout_level(const std::vector<int64_t> &prods, const lrbg_desc *ds,
                   sch, lv.off[f], lv.n[f], f == F_GROUPED);
 }
 
+// `private_out`: every output is the library's own scratch, distinct per
+// product and unreachable by any input, so there is no dependency to find
+// (one level) and no overlap of outputs to reject.
 static lrbg_status build_schedule(const lrbg_desc *ds, int64_t n, const TuneTable &tt, uint32_t flags,
-                                  const int *force_variant, Schedule &sch)
+                                  const int *force_variant, Schedule &sch, bool private_out = false)
 {
     if (n < 0) return fail(LRBG_EINVAL, "negative count");
     if (n > (int64_t)INT32_MAX / 2) return fail(LRBG_EUNSUPPORTED, "too many products");
@@ -851,8 +858,12 @@ static lrbg_status build_schedule(const lrbg_desc *ds, int64_t n, const TuneTabl
         if (st != LRBG_OK) return st;
     }
     std::vector<int> level;
-    lrbg_status st = compute_levels(ds, n, level);
-    if (st != LRBG_OK) return st;
+    if (private_out) {
+        level.assign((size_t)n, 0);
+    } else {
+        lrbg_status st = compute_levels(ds, n, level);
+        if (st != LRBG_OK) return st;
+    }
     std::vector<int> variant((size_t)n, 0);
     sch.descs.resize((size_t)n);
     double flops = 0, bytes = 0;
@@ -1300,7 +1311,8 @@ static lrbg_status round_build(const RoundArgs &a, char *base, RoundBuild &rb)
     }
     TuneTable tt;
     load_tune_cache(getenv("LRBG_TUNE_CACHE"), tt);
-    lrbg_status st = build_schedule(d1.data(), n, tt, 0, nullptr, rb.s1);
+    // the cores G go to this call's own scratch
+    lrbg_status st = build_schedule(d1.data(), n, tt, 0, nullptr, rb.s1, true);
     if (st == LRBG_OK) st = build_schedule(d2.data(), 2 * n, tt, 0, nullptr, rb.s2);
     if (st != LRBG_OK) return st;
     // group the cores by size class (one SVD launch per class)
