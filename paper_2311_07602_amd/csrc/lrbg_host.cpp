@@ -183,9 +183,11 @@ static int64_t tile_count(int v, const lrbg_desc &d)
     return (extent + step - 1) / step;
 }
 
-// Tiles of product d under variant v: p0 of each tile and whether it needs
-// the guarded (ragged-edge) code path.
-static void tiles_of(int v, const lrbg_desc &d, std::vector<int32_t> &p0s, std::vector<int32_t> &edge)
+// Tiles of product d under variant v, in order: f(p0, edge) for each, with
+// p0 its first row (or column) and edge whether it needs the guarded
+// (ragged-edge) code path.
+template <class F>
+static void for_tiles(int v, const lrbg_desc &d, F &&f)
 {
     int step, extent, kc;
     bool rows_full;
@@ -198,8 +200,7 @@ static void tiles_of(int v, const lrbg_desc &d, std::vector<int32_t> &p0s, std::
     for (int p = 0; p < extent; p += step) {
         bool e = ktail || rec_rows_ragged;
         if ((rows_full || vi.kind == K_REC64) && p + step > extent) e = true;
-        p0s.push_back(p);
-        edge.push_back(e ? kTileEdge : 0);
+        f((int32_t)p, (int32_t)(e ? kTileEdge : 0));
     }
 }
 
@@ -570,7 +571,9 @@ struct Schedule {
 // be disjoint.  An input is then tested against the members of the clusters
 // its span meets: one exact test for a single-output cluster, a binary
 // search over the sorted columns otherwise.
-static lrbg_status compute_levels(const lrbg_desc *ds, int64_t n, std::vector<int> &level)
+// `private_b`: every B operand is the library's own scratch, which no output
+// can reach, so only the other inputs are tested.
+static lrbg_status compute_levels(const lrbg_desc *ds, int64_t n, std::vector<int> &level, bool private_b = false)
 {
     level.assign((size_t)n, 0);
     std::vector<Mat> outs;
@@ -648,6 +651,7 @@ static lrbg_status compute_levels(const lrbg_desc *ds, int64_t n, std::vector<in
         const int si[4] = {0, 1, 2, 4};
         const size_t es[4] = {elem_size(d.prec), elem_size(d.prec), 8, 8};
         for (int t = 0; t < 4; ++t) {
+            if (t == 1 && private_b) continue;
             if (t == 2 && d.op != LRBG_OP_RECOMP && d.op != LRBG_OP_LRMULT) continue;
             if (t == 3 && d.op != LRBG_OP_LRMULT) continue;
             const Mat in = mat_of(ptr[t], sh[si[t]][0], sh[si[t]][1], ld[t], es[t], i);
@@ -712,7 +716,6 @@ static void lay_tiles(const std::vector<int64_t> &prods, const lrbg_desc *ds, co
         uniform = uniform && ps.back().t == ps.front().t;
     }
     if (!uniform) std::stable_sort(ps.begin(), ps.end(), [](const P &x, const P &y) { return x.t > y.t; });
-    std::vector<int32_t> p0s, edge;
     if ((flags & LRBG_PLAN_DUAL) && queues) {
         // 16 queues, role-major: q = role * 8 + xcd; role 0 = matrix-core-bound
         // products, role 1 = memory-bound; each role LPT-balanced over the 8
@@ -732,12 +735,11 @@ static void lay_tiles(const std::vector<int64_t> &prods, const lrbg_desc *ds, co
         for (auto &q : qs) {
             sch.qinfo.push_back(off);
             for (int64_t i : q) {
-                p0s.clear();
-                edge.clear();
-                tiles_of(variant[(size_t)i], ds[i], p0s, edge);
-                for (size_t t = 0; t < p0s.size(); ++t)
-                    sch.tiles.push_back(Tile{(int32_t)i, variant[(size_t)i], p0s[t], edge[t]});
-                off += (int32_t)p0s.size();
+                const int v = variant[(size_t)i];
+                for_tiles(v, ds[i], [&](int32_t p0, int32_t e) {
+                    sch.tiles.push_back(Tile{(int32_t)i, v, p0, e});
+                    ++off;
+                });
             }
         }
         sch.qinfo.push_back(off);
@@ -776,46 +778,47 @@ static void lay_tiles(const std::vector<int64_t> &prods, const lrbg_desc *ds, co
             bin.swap(merged);
         }
     }
-    std::vector<std::vector<Tile>> bt(kXcds);
+    // exact tile count of each bin; the tiles are then written straight into
+    // their slots
+    size_t nbt[kXcds], maxlen = 0, total = 0;
     for (int b = 0; b < kXcds; ++b) {
-        size_t nt = 0;   // exact tile count of the bin, so that its vector is allocated once
-        for (int64_t i : bins[b]) nt += (size_t)tile_count(variant[(size_t)i], ds[i]);
-        bt[b].reserve(nt);
-    }
-    for (int b = 0; b < kXcds; ++b)
-        for (int64_t i : bins[b]) {
-            p0s.clear();
-            edge.clear();
-            tiles_of(variant[(size_t)i], ds[i], p0s, edge);
-            for (size_t t = 0; t < p0s.size(); ++t)
-                bt[b].push_back(Tile{(int32_t)i, variant[(size_t)i], p0s[t], edge[t]});
-        }
-    size_t maxlen = 0, total = 0;
-    for (auto &v : bt) {
-        maxlen = std::max(maxlen, v.size());
-        total += v.size();
+        nbt[b] = 0;
+        for (int64_t i : bins[b]) nbt[b] += (size_t)tile_count(variant[(size_t)i], ds[i]);
+        maxlen = std::max(maxlen, nbt[b]);
+        total += nbt[b];
     }
     tile_off = (int64_t)sch.tiles.size();
     if (flags & LRBG_PLAN_PERSISTENT) {
         // queue q = bins[q], contiguous
+        sch.tiles.resize((size_t)tile_off + total);
+        Tile *out = sch.tiles.data() + tile_off;
         int32_t off = 0;
         for (int b = 0; b < kXcds; ++b) {
             sch.qinfo.push_back(off);
-            for (const Tile &t : bt[b]) sch.tiles.push_back(t);
-            off += (int32_t)bt[b].size();
+            for (int64_t i : bins[b]) {
+                const int v = variant[(size_t)i];
+                for_tiles(v, ds[i], [&](int32_t p0, int32_t e) { out[off++] = Tile{(int32_t)i, v, p0, e}; });
+            }
         }
         sch.qinfo.push_back(off);
         ntiles = off;
     } else {
+        // slot-major: bin b's tile j at j kXcds + b, the gaps no-op tiles
         sch.tiles.resize((size_t)tile_off + maxlen * kXcds, Tile{0, 0, 0, 0});
         Tile *out = sch.tiles.data() + tile_off;
-        for (int b = 0; b < kXcds; ++b)
-            for (size_t slot = 0; slot < bt[b].size(); ++slot) out[slot * kXcds + (size_t)b] = bt[b][slot];
+        for (int b = 0; b < kXcds; ++b) {
+            size_t slot = 0;
+            for (int64_t i : bins[b]) {
+                const int v = variant[(size_t)i];
+                for_tiles(v, ds[i], [&](int32_t p0, int32_t e) {
+                    out[slot++ * kXcds + (size_t)b] = Tile{(int32_t)i, v, p0, e};
+                });
+            }
+        }
         ntiles = (int32_t)(maxlen * kXcds);
         if (queues)
             for (int b = 0; b <= kXcds; ++b) sch.qinfo.push_back(0);
     }
-    (void)total;
 }
 
 static int family_of(int v)
@@ -844,11 +847,13 @@ static void layout_level(const std::vector<int64_t> &prods, const lrbg_desc *ds,
                   sch, lv.off[f], lv.n[f], f == F_GROUPED);
 }
 
-// `private_out`: every output is the library's own scratch, distinct per
-// product and unreachable by any input, so there is no dependency to find
-// (one level) and no overlap of outputs to reject.
+// Scratch the library owns, which no caller buffer can reach:
+// kPrivateOut, every output (distinct per product), so there is no
+// dependency to find (one level) and no overlap of outputs to reject;
+// kPrivateB, every B operand, which then needs no test against outputs.
+enum : unsigned { kPrivateOut = 1, kPrivateB = 2 };
 static lrbg_status build_schedule(const lrbg_desc *ds, int64_t n, const TuneTable &tt, uint32_t flags,
-                                  const int *force_variant, Schedule &sch, bool private_out = false)
+                                  const int *force_variant, Schedule &sch, unsigned priv = 0)
 {
     if (n < 0) return fail(LRBG_EINVAL, "negative count");
     if (n > (int64_t)INT32_MAX / 2) return fail(LRBG_EUNSUPPORTED, "too many products");
@@ -858,10 +863,10 @@ static lrbg_status build_schedule(const lrbg_desc *ds, int64_t n, const TuneTabl
         if (st != LRBG_OK) return st;
     }
     std::vector<int> level;
-    if (private_out) {
+    if (priv & kPrivateOut) {
         level.assign((size_t)n, 0);
     } else {
-        lrbg_status st = compute_levels(ds, n, level);
+        lrbg_status st = compute_levels(ds, n, level, (priv & kPrivateB) != 0);
         if (st != LRBG_OK) return st;
     }
     std::vector<int> variant((size_t)n, 0);
@@ -1311,9 +1316,10 @@ static lrbg_status round_build(const RoundArgs &a, char *base, RoundBuild &rb)
     }
     TuneTable tt;
     load_tune_cache(getenv("LRBG_TUNE_CACHE"), tt);
-    // the cores G go to this call's own scratch
-    lrbg_status st = build_schedule(d1.data(), n, tt, 0, nullptr, rb.s1, true);
-    if (st == LRBG_OK) st = build_schedule(d2.data(), 2 * n, tt, 0, nullptr, rb.s2);
+    // the cores G, and the singular vectors X, Y the basis updates read, are
+    // this call's own scratch
+    lrbg_status st = build_schedule(d1.data(), n, tt, 0, nullptr, rb.s1, kPrivateOut);
+    if (st == LRBG_OK) st = build_schedule(d2.data(), 2 * n, tt, 0, nullptr, rb.s2, kPrivateB);
     if (st != LRBG_OK) return st;
     // group the cores by size class (one SVD launch per class)
     rb.sv.clear();
