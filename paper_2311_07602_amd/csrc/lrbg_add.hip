@@ -41,6 +41,11 @@
 
 namespace lrbg {
 
+// Wavefronts sharing one triangle in the QR's block kernel (alternate
+// blocks): two for 64-wide bases, whose triangles in LDS limit how many
+// wavefronts a CU holds; one for narrower bases, which registers limit.
+constexpr int qr_waves(int cols) { return cols == 64 ? 2 : 1; }
+
 // G = 64 / S stacked bases per wavefront, one per group of S lanes (group g
 // = lanes g S .. g S + S - 1, lane c of a group owns column c).  With several
 // groups the per-group LDS arrays are padded so that the groups sharing a

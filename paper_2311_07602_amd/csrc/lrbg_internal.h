@@ -195,10 +195,6 @@ struct AddCoreDesc {
 
 // Rows per block of the QR after the first s0 = min(s, b) rows.
 constexpr int kQrRows = 32;
-// Wavefronts sharing one triangle in the QR's block kernel (alternate
-// blocks): two for 64-wide bases, whose triangles in LDS limit how many
-// wavefronts a CU holds; one for narrower bases, which registers limit.
-constexpr int qr_waves(int cols) { return cols == 64 ? 2 : 1; }
 constexpr int kQrMaxCols = 64;
 
 // Scratch of one stacked basis (doubles): the triangular factor R (s x s,
