@@ -11,15 +11,16 @@
 // to k terms gives A + B ~ (Q_U X_k) S_k (Q_V Y_k)^T.  This is the rounded
 // addition whose first step Sec. 2 names the low-rank product to be.
 //
-// QR (one wavefront per stacked basis, s <= 64, lane c owns column c): the
-// basis is read from HBM once, top to bottom.  Its first s0 = min(s, b) rows
-// are reduced in LDS by Householder reflections with pivots on the diagonal
-// (the head kernel); every later block of kQrRows rows is then reduced
-// against the running triangular factor R (the block kernel).  Reflection j of a block acts on row j of R and on
-// the block's rows only, v = [e_j; y_j] (R is triangular), so the block's
-// columns stay in the lanes' registers: the lane owning column j forms the
-// reflection from its own registers and R_jj, publishes y_j through LDS,
-// and every lane to its right applies it to its column.  Reflections follow
+// QR (s <= 64, lane c of a basis's lane group owns column c): the basis is
+// read from HBM once, top to bottom.  Its first s0 = min(s, b) rows are
+// reduced in LDS by Householder reflections with pivots on the diagonal (the
+// head kernel); every later block of kQrRows rows is then reduced against
+// the running triangular factor R (the block kernel).  Reflection j of a
+// block acts on row j of R and on the block's rows only, v = [e_j; y_j] (R
+// is triangular), so the block's columns stay in the lanes' registers: the
+// tail y_j comes from the registers of the lane owning column j (through
+// LDS, or for a 64-wide basis by lane reads into scalar registers), and
+// every lane to its right applies the reflection to its column.  Reflections follow
 // LAPACK's convention: beta = -sign(alpha) sqrt(alpha^2 + |x|^2),
 // tau = (beta - alpha) / beta, y = x / (alpha - beta); tau = 0 when x = 0.
 // The reflectors and taus go to scratch; Q is never formed.  Every
@@ -31,9 +32,10 @@
 // Core (one wavefront per instance): E = R_U diag(A_X, B_X) column by column
 // in registers, then M = E R_V^T.
 //
-// New bases (one wavefront per stacked basis, lane c owns output column c <
-// kmax, or lanes c and c + 32 when a 64-wide basis keeps at most 32 columns):
-// U = Q [X_k; 0], applying the stored reflections in reverse order:
+// New bases (lane c of a basis's lane group owns output column c < kmax, or
+// lanes c and c + S / 2 when an S-wide basis (S = 32, 64) keeps at most
+// S / 2 columns): U = Q [X_k; 0], applying the stored reflections in reverse
+// order:
 // blocks from the last to the first, each producing its kQrRows output rows
 // in registers while updating the s x kmax top part Z in LDS, then the
 // reflections of the first s0 rows on Z, which gives the top s0 rows.
