@@ -227,7 +227,7 @@ def test_round_plan_at_bench_scale_matches_one_shot(r):
     assert int(outs[0][3].min()) == kmax
 
 
-@pytest.mark.parametrize("r", [8, 32])
+@pytest.mark.parametrize("r", [8, 16, 32])
 def test_lradd_at_bench_scale_sampled(r):
     """The rounded addition at the benchmark's size (20000 instances, b =
     1024, both ranks r, kept rank <= r, N(0,1) factors): sampled instances
