@@ -655,12 +655,15 @@ __global__ void __launch_bounds__(64) lrbg_add_core_kernel(const AddCoreDesc *__
     const AddCoreDesc d = descs[blockIdx.x];
     const int lane = threadIdx.x, ra = d.ra, rb = d.rb, s = d.ra + d.rb;
     __shared__ double RU[S * S];    // R_U, then E = R_U diag(A_X, B_X); row-major, stride S
-    __shared__ double RVt[S * S];   // R_V transposed: RVt[l * S + c] = R_V(c, l)
+    // R_V transposed, rows padded to an odd stride so that the transposing
+    // stores (consecutive lanes, consecutive rows) fall into different banks:
+    // RVt[l * (S + 1) + c] = R_V(c, l)
+    __shared__ double RVt[S * (S + 1)];
     gcp ru = (gcp)d.ru, rv = (gcp)d.rv;
     for (int e = lane; e < s * s; e += 64) {
         const int i = e / s, c = e % s;
         RU[i * S + c] = ru[e];
-        RVt[c * S + i] = rv[e];
+        RVt[c * (S + 1) + i] = rv[e];
     }
     __syncthreads();
     // E(:, l) = R_U(:, block of l) * D(block of l, l), lane l
@@ -694,7 +697,7 @@ __global__ void __launch_bounds__(64) lrbg_add_core_kernel(const AddCoreDesc *__
 #pragma unroll
         for (int i = 0; i < S; ++i) mc[i] = 0.0;
         for (int l = 0; l < s; ++l) {
-            const double v = RVt[l * S + lane];
+            const double v = RVt[l * (S + 1) + lane];
 #pragma unroll
             for (int i = 0; i < S; ++i) mc[i] += RU[i * S + l] * v;
         }
