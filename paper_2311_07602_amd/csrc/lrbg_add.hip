@@ -219,15 +219,19 @@ __global__ void __launch_bounds__(64 * qr_waves(S)) lrbg_qr_blocks_kernel(const 
                 for (int i = 0; i < kQrRows; ++i)
                     y[i] = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x[i]), j),
                                             __builtin_amdgcn_readlane(__double2loint(x[i]), j));
-                double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0;
+                // every lane's dot product with the tail; the pivot lane's is
+                // the tail's squared norm, read out like the tail
+                double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
 #pragma unroll
                 for (int i = 0; i < kQrRows; i += 4) {
-                    n0 += y[i] * y[i];
-                    n1 += y[i + 1] * y[i + 1];
-                    n2 += y[i + 2] * y[i + 2];
-                    n3 += y[i + 3] * y[i + 3];
+                    w0 += y[i] * x[i];
+                    w1 += y[i + 1] * x[i + 1];
+                    w2 += y[i + 2] * x[i + 2];
+                    w3 += y[i + 3] * x[i + 3];
                 }
-                const double nrm2 = (n0 + n1) + (n2 + n3);
+                const double w = (w0 + w1) + (w2 + w3);
+                const double nrm2 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(w), j),
+                                                     __builtin_amdgcn_readlane(__double2loint(w), j));
                 const double alpha = R[rp(j)];
                 double tau = 0.0, scale = 0.0, beta = alpha;
                 if (nrm2 > 0.0) {
@@ -241,16 +245,8 @@ __global__ void __launch_bounds__(64 * qr_waves(S)) lrbg_qr_blocks_kernel(const 
                     my_sc = scale;
                 }
                 if (tau != 0.0 && c > j) {
-                    double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
-#pragma unroll
-                    for (int i = 0; i < kQrRows; i += 4) {
-                        w0 += y[i] * x[i];
-                        w1 += y[i + 1] * x[i + 1];
-                        w2 += y[i + 2] * x[i + 2];
-                        w3 += y[i + 3] * x[i + 3];
-                    }
                     double *rjc = R + rp(j) + c - j;
-                    const double tw = tau * (*rjc + scale * ((w0 + w1) + (w2 + w3)));
+                    const double tw = tau * (*rjc + scale * w);
                     *rjc -= tw;
                     const double f = tw * scale;
 #pragma unroll
