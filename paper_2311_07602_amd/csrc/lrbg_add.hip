@@ -386,16 +386,11 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
         // stays in registers for the update and the next reflection's tail is
         // read a step ahead (LDS, not registers, limits the wavefronts here).
         const int jtop = S - 1;
-        double yc[RH];
-        {
-            const double *y = Yl + jtop * kQrRows + RH * h;
-#pragma unroll
-            for (int i = 0; i < RH; ++i) yc[i] = y[i];
-        }
-        for (int j = jtop; j >= 0; --j) {
+        // reflection j with its tail in yc, loading the next one into yn;
+        // two at a time with the buffers' roles swapped, so no copies
+        auto reflect = [&](int j, const double (&yc)[RH], double (&yn)[RH]) {
             const double tau = tl[j];
             const double zj = (mine && top) ? Z[j * KZ + c] : 0.0;
-            double yn[RH];
             {
                 const double *y = Yl + (j > 0 ? j - 1 : 0) * kQrRows + RH * h;
 #pragma unroll
@@ -421,11 +416,20 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
             const double tw = tau * w;
             if (mine && top) Z[j * KZ + c] = zj - tw;
 #pragma unroll
-            for (int i = 0; i < RH; ++i) {
-                u[i] -= tw * yc[i];
-                yc[i] = yn[i];
-            }
+            for (int i = 0; i < RH; ++i) u[i] -= tw * yc[i];
+        };
+        double ya[RH], yb[RH];
+        {
+            const double *y = Yl + jtop * kQrRows + RH * h;
+#pragma unroll
+            for (int i = 0; i < RH; ++i) ya[i] = y[i];
         }
+        int j = jtop;
+        for (; j > 0; j -= 2) {
+            reflect(j, ya, yb);
+            reflect(j - 1, yb, ya);
+        }
+        if (j == 0) reflect(0, ya, yb);
         if (mine && live) {
             gp o = (gp)d.out + (size_t)c * d.ldo + r0 + RH * h;
             const int hv = hb - RH * h;        // valid rows of this lane's part
@@ -544,16 +548,11 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply64_kernel(const QrDesc *__res
             // the identity), the tail kept in registers and the next one
             // read a step ahead
             const int jlo = q * CH, jhi = jtop < jlo + CH - 1 ? jtop : jlo + CH - 1;
-            double yc[RH];
-            {
-                const double *y = Yl + (jhi > jlo ? jhi - jlo : 0) * kQrRows + RH * h;
-#pragma unroll
-                for (int i = 0; i < RH; ++i) yc[i] = y[i];
-            }
-            for (int j = jhi; j >= jlo; --j) {
+            // reflection j with its tail in yc, loading the next one into yn;
+            // two at a time with the buffers' roles swapped, so no copies
+            auto reflect = [&](int j, const double (&yc)[RH], double (&yn)[RH]) {
                 const double tau = bcast(tc, j);
                 const double zj = (mine && top) ? Z[j * KZ + c] : 0.0;
-                double yn[RH];
                 {
                     const double *y = Yl + (j > jlo ? j - 1 - jlo : 0) * kQrRows + RH * h;
 #pragma unroll
@@ -577,11 +576,20 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply64_kernel(const QrDesc *__res
                 const double tw = tau * w;
                 if (mine && top) Z[j * KZ + c] = zj - tw;
 #pragma unroll
-                for (int i = 0; i < RH; ++i) {
-                    u[i] -= tw * yc[i];
-                    yc[i] = yn[i];
-                }
+                for (int i = 0; i < RH; ++i) u[i] -= tw * yc[i];
+            };
+            double ya[RH], yb[RH];
+            {
+                const double *y = Yl + (jhi > jlo ? jhi - jlo : 0) * kQrRows + RH * h;
+#pragma unroll
+                for (int i = 0; i < RH; ++i) ya[i] = y[i];
             }
+            int j = jhi;
+            for (; j > jlo; j -= 2) {
+                reflect(j, ya, yb);
+                reflect(j - 1, yb, ya);
+            }
+            if (j == jlo) reflect(j, ya, yb);
         }
         if (mine) {
             gp o = (gp)d.out + (size_t)c * d.ldo + r0 + RH * h;
