@@ -251,9 +251,10 @@ def run_dense_uniform(steps=200, warmup=20, sets=16):
         plans[i % sets].execute(stream)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sp = stream.cuda_stream
     e0.record(stream)
     for i in range(steps):
-        plans[i % sets].execute(stream)
+        plans[i % sets].execute(sp)
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps

@@ -409,9 +409,12 @@ class Plan:
                  keepalive: Iterable = ()):
         self._keep = list(keepalive)      # tensors whose memory the plan points at
         self.handle = lrbg_plan_create(descs, tune_cache, flags)
+        self._execute = load().lrbg_plan_execute   # bound once: replays are short calls
 
     def execute(self, stream=None):
-        lrbg_plan_execute(self.handle, stream)
+        st = self._execute(self.handle, stream if stream is None or isinstance(stream, int) else stream.cuda_stream)
+        if st != LRBG_OK:
+            _check(st, "lrbg_plan_execute")
 
     def stats(self) -> dict:
         return lrbg_plan_get_stats(self.handle)
