@@ -664,11 +664,14 @@ __global__ void __launch_bounds__(64) lrbg_add_core_kernel(const AddCoreDesc *__
     // RVt[l * (S + 1) + c] = R_V(c, l)
     __shared__ double RVt[S * (S + 1)];
     gcp ru = (gcp)d.ru, rv = (gcp)d.rv;
-    for (int e = lane; e < s * s; e += 64) {
-        const int i = e / s, c = e % s;
-        RU[i * S + c] = ru[e];
-        RVt[c * (S + 1) + i] = rv[e];
-    }
+    // row by row, lane = column (row-major factors: coalesced), several rows'
+    // loads in flight at once
+#pragma unroll 8
+    for (int i = 0; i < s; ++i)
+        if (lane < s) {
+            RU[i * S + lane] = ru[(size_t)i * s + lane];
+            RVt[lane * (S + 1) + i] = rv[(size_t)i * s + lane];
+        }
     __syncthreads();
     // E(:, l) = R_U(:, block of l) * D(block of l, l), lane l
     double e_[S];
