@@ -214,11 +214,24 @@ __global__ void __launch_bounds__(64 * qr_waves(S)) lrbg_qr_blocks_kernel(const 
                 // and every lane forms the reflection itself.  LDS broadcasts
                 // of the tail would move 32 doubles to every lane twice per
                 // reflection, more than the CU's LDS bandwidth keeps up with.
+                // The upper half of the tail goes through LDS instead (the
+                // pivot lane stores it, every lane reads it back), which
+                // splits the broadcast between the VALU and the LDS.
+                constexpr int HR = kQrRows / 2;
+                if (c == j) {
+#pragma unroll
+                    for (int i = HR; i < kQrRows; ++i) xs[i - HR] = x[i];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 double y[kQrRows];
 #pragma unroll
-                for (int i = 0; i < kQrRows; ++i)
+                for (int i = 0; i < HR; ++i)
                     y[i] = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x[i]), j),
                                             __builtin_amdgcn_readlane(__double2loint(x[i]), j));
+#pragma unroll
+                for (int i = HR; i < kQrRows; ++i) y[i] = xs[i - HR];
                 // every lane's dot product with the tail; the pivot lane's is
                 // the tail's squared norm, read out like the tail
                 double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
@@ -249,8 +262,11 @@ __global__ void __launch_bounds__(64 * qr_waves(S)) lrbg_qr_blocks_kernel(const 
                     const double tw = tau * (*rjc + scale * w);
                     *rjc -= tw;
                     const double f = tw * scale;
+                    __asm__ volatile("" ::: "memory");   // read the LDS half again
 #pragma unroll
-                    for (int i = 0; i < kQrRows; ++i) x[i] -= f * y[i];
+                    for (int i = 0; i < HR; ++i) x[i] -= f * y[i];
+#pragma unroll
+                    for (int i = HR; i < kQrRows; ++i) x[i] -= f * xs[i - HR];
                 }
             } else {
             if (c == j) {
