@@ -214,10 +214,11 @@ __global__ void __launch_bounds__(64 * qr_waves(S)) lrbg_qr_blocks_kernel(const 
                 // and every lane forms the reflection itself.  LDS broadcasts
                 // of the tail would move 32 doubles to every lane twice per
                 // reflection, more than the CU's LDS bandwidth keeps up with.
-                // The upper half of the tail goes through LDS instead (the
+                // The last quarter of the tail goes through LDS instead (the
                 // pivot lane stores it, every lane reads it back), which
-                // splits the broadcast between the VALU and the LDS.
-                constexpr int HR = kQrRows / 2;
+                // splits the broadcast between the VALU and the LDS (a half
+                // or three quarters through LDS measured no faster).
+                constexpr int HR = 3 * kQrRows / 4;
                 if (c == j) {
 #pragma unroll
                     for (int i = HR; i < kQrRows; ++i) xs[i - HR] = x[i];
@@ -262,7 +263,7 @@ __global__ void __launch_bounds__(64 * qr_waves(S)) lrbg_qr_blocks_kernel(const 
                     const double tw = tau * (*rjc + scale * w);
                     *rjc -= tw;
                     const double f = tw * scale;
-                    __asm__ volatile("" ::: "memory");   // read the LDS half again
+                    __asm__ volatile("" ::: "memory");   // read the LDS part again
 #pragma unroll
                     for (int i = 0; i < HR; ++i) x[i] -= f * y[i];
 #pragma unroll
