@@ -43,9 +43,11 @@
 
 namespace lrbg {
 
-// Wavefronts sharing one triangle in the QR's block kernel (alternate
-// blocks): two for 64-wide bases, whose triangles in LDS limit how many
-// wavefronts a CU holds; one for narrower bases, which registers limit.
+// Wavefronts per basis in the QR kernels: two for 64-wide bases, whose LDS
+// (the first rows' block, the triangle) limits how many wavefronts a CU
+// holds -- the head kernel splits the rows of every dot product and update
+// between them, the block kernel gives them alternate blocks -- and one for
+// narrower bases, which registers limit.
 constexpr int qr_waves(int cols) { return cols == 64 ? 2 : 1; }
 
 // G = 64 / S stacked bases per wavefront, one per group of S lanes (group g
@@ -65,10 +67,11 @@ constexpr int qr_waves(int cols) { return cols == 64 ? 2 : 1; }
 // so that a CU holds twice as many of its wavefronts (64-wide bases: 17 KB
 // against 33 KB).
 template <int S>
-__global__ void __launch_bounds__(64) lrbg_qr_head_kernel(const QrDesc *__restrict__ descs, int count)
+__global__ void __launch_bounds__(64 * qr_waves(S)) lrbg_qr_head_kernel(const QrDesc *__restrict__ descs, int count)
 {
-    constexpr int G = 64 / S;
-    const int lane = threadIdx.x, g = lane / S, c = lane % S;
+    constexpr int G = 64 / S, NW = qr_waves(S), RW = S / NW;   // rows per wavefront
+    const int wv = NW > 1 ? __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6) : 0;
+    const int lane = (int)threadIdx.x & 63, g = lane / S, c = lane % S;
     const int t = (int)blockIdx.x * G + g;
     QrDesc d{};
     if (t < count) d = descs[t];
@@ -77,58 +80,79 @@ __global__ void __launch_bounds__(64) lrbg_qr_head_kernel(const QrDesc *__restri
     // c reading row i (column c) both stay off each other's banks
     constexpr int SP = S + 1, RSTR = S * SP + (G > 1 ? 16 : 0);
     __shared__ double R_[G * RSTR];      // the first rows, row-major, stride SP
+    __shared__ double part_[NW > 1 ? NW * 64 : 1];   // the wavefronts' partial dot products
     double *R = R_ + g * RSTR;
     const bool mine = c < s;
     gcp cp = (gcp)(!mine ? d.w0 : c < c0 ? d.w0 + (size_t)c * d.ld0 : d.w1 + (size_t)(c - c0) * d.ld1);
     gp ws = (gp)d.ws;
     gp tau0 = ws + (size_t)s * s;
     gp T = tau0 + s;
+    const int rlo = RW * wv, rhi = rlo + RW;   // this wavefront's rows
 
     // Householder QR in LDS, pivots on the diagonal.  The group forms each
     // reflection together: lane i holds row i of the pivot column, the
     // squared norm is a sum over the group's lanes, and every lane derives
-    // beta, tau and the scale itself; lane i scales its own entry.
-    for (int i = 0; i < S; ++i) R[i * SP + c] = (mine && i < s0) ? cp[i] : 0.0;
+    // beta, tau and the scale itself.  The tails stay unscaled until the end
+    // (a column's tail is not read again after its own reflection), so the
+    // dot products take the scale once.  For 64-wide bases two wavefronts
+    // split the rows of every dot product and update, and join the partial
+    // dot products through LDS.
+    for (int i = rlo; i < rhi; ++i) R[i * SP + c] = (mine && i < s0) ? cp[i] : 0.0;
     __syncthreads();
-    double my_tau = 0.0;
+    double my_tau = 0.0, my_sc = 0.0;
     for (int j = 0; j < S; ++j) {
-        const bool act = j < s0;
         const double xi = (c > j && c < s0) ? R[c * SP + j] : 0.0;
         double nrm2 = xi * xi;
 #pragma unroll
         for (int m = 1; m < S; m <<= 1) nrm2 += __shfl_xor(nrm2, m);
         const double alpha = R[j * SP + j];
-        double tau = 0.0;
-        if (act && nrm2 > 0.0) {
-            const double beta = -copysign(sqrt(alpha * alpha + nrm2), alpha);
+        double tau = 0.0, scale = 0.0, beta = alpha;
+        if (j < s0 && nrm2 > 0.0) {
+            beta = -copysign(sqrt(alpha * alpha + nrm2), alpha);
             tau = (beta - alpha) / beta;
-            const double scale = 1.0 / (alpha - beta);
-            if (c > j && c < s0) R[c * SP + j] = xi * scale;
-            if (c == j) R[j * SP + j] = beta;
+            scale = 1.0 / (alpha - beta);
         }
-        if (c == j) my_tau = tau;
-        __syncthreads();
-        if (tau != 0.0 && c > j && mine) {
-            double w0 = R[j * SP + c], w1 = 0.0;
-            int i = j + 1;
+        if (c == j) {
+            my_tau = tau;
+            my_sc = scale;
+        }
+        const bool upd = tau != 0.0 && c > j && mine;
+        const int lo = j + 1 > rlo ? j + 1 : rlo, hi = s0 < rhi ? s0 : rhi;
+        const double rjc = upd ? R[j * SP + c] : 0.0;   // read before row j is updated
+        double p0 = 0.0, p1 = 0.0;
+        if (upd) {
+            int i = lo;
 #pragma unroll 4
-            for (; i + 1 < s0; i += 2) {
-                w0 += R[i * SP + j] * R[i * SP + c];
-                w1 += R[(i + 1) * SP + j] * R[(i + 1) * SP + c];
+            for (; i + 1 < hi; i += 2) {
+                p0 += R[i * SP + j] * R[i * SP + c];
+                p1 += R[(i + 1) * SP + j] * R[(i + 1) * SP + c];
             }
-            if (i < s0) w0 += R[i * SP + j] * R[i * SP + c];
-            const double tw = tau * (w0 + w1);
-            R[j * SP + c] -= tw;
+            if (i < hi) p0 += R[i * SP + j] * R[i * SP + c];
+        }
+        double p = p0 + p1;
+        if constexpr (NW > 1) {
+            part_[wv * 64 + lane] = p;
+            __syncthreads();
+            p = part_[lane] + part_[64 + lane];
+        }
+        if (c == j && j >= rlo && j < rhi && tau != 0.0) R[j * SP + j] = beta;
+        if (upd) {
+            const double tw = tau * (rjc + scale * p), f = tw * scale;
+            if (j >= rlo && j < rhi) R[j * SP + c] = rjc - tw;
 #pragma unroll 4
-            for (int i = j + 1; i < s0; ++i) R[i * SP + c] -= tw * R[i * SP + j];
+            for (int i = lo; i < hi; ++i) R[i * SP + c] -= f * R[i * SP + j];
         }
         __syncthreads();
     }
     if (mine) {
-        for (int i = 0; i < s0; ++i) T[(size_t)i * s + c] = R[i * SP + c];
-        tau0[c] = my_tau;
+        // the tails below the diagonal scaled to the reflectors' y
+        for (int i = rlo; i < rhi && i < s0; ++i) {
+            const double v = R[i * SP + c];
+            T[(size_t)i * s + c] = i > c ? v * my_sc : v;
+        }
+        if (wv == 0) tau0[c] = my_tau;
         // R so far: the triangle, zeros below it (rows s0 .. s - 1 too)
-        for (int i = 0; i < s; ++i) ws[(size_t)i * s + c] = (i <= c && i < s0) ? R[i * SP + c] : 0.0;
+        for (int i = rlo; i < rhi && i < s; ++i) ws[(size_t)i * s + c] = (i <= c && i < s0) ? R[i * SP + c] : 0.0;
     }
 }
 
@@ -754,7 +778,7 @@ static int launch_by_class(int cols, const D *descs, int count, void *stream, K1
 int launch_qr_factor(int cols, const QrDesc *descs, int count, void *stream)
 {
     const int rc = launch_by_class(cols, descs, count, stream, lrbg_qr_head_kernel<16>, lrbg_qr_head_kernel<32>,
-                                   lrbg_qr_head_kernel<64>, {4, 2, 1});
+                                   lrbg_qr_head_kernel<64>, {4, 2, 1}, 64 * qr_waves(cols));
     if (rc != 0) return rc;
     return launch_by_class(cols, descs, count, stream, lrbg_qr_blocks_kernel<16>, lrbg_qr_blocks_kernel<32>,
                            lrbg_qr_blocks_kernel<64>, {4, 2, 1}, 64 * qr_waves(cols));
