@@ -713,7 +713,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the batched products are "
-              f"independent per instance and shard across GPUs without communication, but this build "
+              f"independent per instance and shard across GPUs without communication; the benchmark "
               f"measures one GPU's share.", file=sys.stderr)
         sys.exit(2)
     import torch
