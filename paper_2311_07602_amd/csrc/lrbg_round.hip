@@ -140,7 +140,7 @@ lrbg_core_svd_kernel(const SvdDesc *__restrict__ descs, int count)
                 if (ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
                     const double zeta = (be - al) / (2.0 * ga);
                     const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
+                    const double c = rsqrt(1.0 + tt * tt), s = c * tt;   // 1 / sqrt, one call
 #pragma unroll
                     for (int j = 0; j < RPL; ++j) {
                         const double x0 = x[j], y0 = y[j], v0 = vx[j], w0 = vy[j];
