@@ -386,10 +386,17 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
     const int s = d.c0 + d.c1, b = d.b, s0 = s < b ? s : b, km = d.kmax;
     // per-group arrays, padded as in the factorisation
     constexpr int ZSTR = S * KZ + (G > 1 ? 16 : 0);
-    // a block's reflection tails (column j at j * kQrRows), later the first
-    // s0 rows' packed tails (s0 (s0 - 1) / 2 <= S (S - 1) / 2 <= kQrRows S)
-    constexpr int YL = kQrRows * S, YSTR = YL + (G > 1 ? 2 : 0), TSTR = S + (G > 1 ? 2 : 0);
+    // CH reflections' tails of a block at a time (column j at (j - jlo)
+    // kQrRows), later the first s0 rows' packed tails (s0 (s0 - 1) / 2 <=
+    // S (S - 1) / 2 <= kQrRows CH).  For 32-wide bases a block takes two
+    // pieces, the next one loaded into registers while the current one is
+    // applied (half the LDS of a whole block: more wavefronts per CU).
+    constexpr int CH = 16, NQ = S / CH;
+    constexpr bool PREF = NQ > 1;
+    constexpr int PF = PREF ? CH * kQrRows / NL : 1;
+    constexpr int YL = kQrRows * CH, YSTR = YL + (G > 1 ? 2 : 0), TSTR = S + (G > 1 ? 2 : 0);
     static_assert(S * (S - 1) / 2 <= YL, "packed tails fit");
+    static_assert(NL == S, "one tau per loader");
     __shared__ double Z_[G * ZSTR];            // s x kmax top part, Z[j * KZ + c]
     __shared__ double Yl_[G * YSTR];
     __shared__ double tl_[G * TSTR];
@@ -410,67 +417,98 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
     int nbmax = 0;
 #pragma unroll
     for (int q = 0; q < G; ++q) nbmax = nb_[q] > nbmax ? nb_[q] : nbmax;
+    // this group's piece q of block kb's tails, and the block's taus
+    double pf[PF], pt = 0.0;
+    auto fetch = [&](int kb, int q) {
+        const bool lv = kb < nblk;
+        gcp bp = blk + (size_t)kb * (s + (size_t)kQrRows * s);
+        const int base = q * YL;
+#pragma unroll
+        for (int p = 0; p < PF; ++p) {
+            const int e = li + NL * p;
+            pf[p] = (lv && base + e < s * kQrRows) ? bp[s + base + e] : 0.0;
+        }
+        pt = (lv && li < s) ? bp[li] : 0.0;
+    };
+    if constexpr (PREF) {
+        if (nbmax > 0) fetch(nbmax - 1, NQ - 1);
+    }
     for (int kb = nbmax - 1; kb >= 0; --kb) {
         const bool live = kb < nblk;
         gcp bp = blk + (size_t)kb * (s + (size_t)kQrRows * s);
         const int r0 = s0 + kb * kQrRows, hb = live ? (b - r0 < kQrRows ? b - r0 : kQrRows) : 0;
-        __syncthreads();                       // the previous block's reads of Yl are done
-        for (int e = li; e < S * kQrRows; e += NL) Yl[e] = (live && e < s * kQrRows) ? bp[s + e] : 0.0;
-        for (int e = li; e < S; e += NL) tl[e] = (live && e < s) ? bp[e] : 0.0;
-        __syncthreads();
         double u[RH];
 #pragma unroll
         for (int i = 0; i < RH; ++i) u[i] = 0.0;
-        // Reflections past the basis's width are the identity (tau = 0), and
-        // so is any other with tau = 0: it is applied as such rather than
-        // skipped, so that no branch waits on the LDS read of tau.  The tail
-        // stays in registers for the update and the next reflection's tail is
-        // read a step ahead (LDS, not registers, limits the wavefronts here).
-        const int jtop = S - 1;
-        // reflection j with its tail in yc, loading the next one into yn;
-        // two at a time with the buffers' roles swapped, so no copies
-        auto reflect = [&](int j, const double (&yc)[RH], double (&yn)[RH]) {
-            const double tau = tl[j];
-            const double zj = (mine && top) ? Z[j * KZ + c] : 0.0;
+        for (int q = NQ - 1; q >= 0; --q) {
+            __syncthreads();                       // the previous piece's reads of Yl are done
+            if constexpr (PREF) {
+#pragma unroll
+                for (int p = 0; p < PF; ++p) Yl[li + NL * p] = pf[p];
+                if (q == NQ - 1) tl[li] = pt;
+            } else {
+                for (int e = li; e < YL; e += NL) Yl[e] = (live && e < s * kQrRows) ? bp[s + e] : 0.0;
+                tl[li] = (live && li < s) ? bp[li] : 0.0;
+            }
+            __syncthreads();
+            if constexpr (PREF) {
+                if (q > 0)
+                    fetch(kb, q - 1);
+                else if (kb > 0)
+                    fetch(kb - 1, NQ - 1);
+            }
+            const int jlo = q * CH;
+            // Reflections past the basis's width are the identity (tau = 0), and
+            // so is any other with tau = 0: it is applied as such rather than
+            // skipped, so that no branch waits on the LDS read of tau.  The tail
+            // stays in registers for the update and the next reflection's tail is
+            // read a step ahead (LDS, not registers, limits the wavefronts here).
+            const int jtop = jlo + CH - 1;
+            // reflection j with its tail in yc, loading the next one into yn;
+            // two at a time with the buffers' roles swapped, so no copies
+            auto reflect = [&](int j, const double (&yc)[RH], double (&yn)[RH]) {
+                const double tau = tl[j];
+                const double zj = (mine && top) ? Z[j * KZ + c] : 0.0;
+                {
+                    const double *y = Yl + (j > jlo ? j - 1 - jlo : 0) * kQrRows + RH * h;
+#pragma unroll
+                    for (int i = 0; i < RH; ++i) yn[i] = y[i];
+                }
+                double w0 = zj, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+#pragma unroll
+                for (int i = 0; i < RH; i += 4) {
+                    w0 += yc[i] * u[i];
+                    w1 += yc[i + 1] * u[i + 1];
+                    w2 += yc[i + 2] * u[i + 2];
+                    w3 += yc[i + 3] * u[i + 3];
+                }
+                double w = (w0 + w1) + (w2 + w3);
+                if constexpr (SPLIT) {
+                    // after the swap one result holds this lane's partial and the
+                    // other its partner's (lane ^ 16), in either order
+                    const unsigned lo = __double2loint(w), hi = __double2hiint(w);
+                    const auto sl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+                    const auto sh = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+                    w = __hiloint2double((int)sh[0], (int)sl[0]) + __hiloint2double((int)sh[1], (int)sl[1]);
+                }
+                const double tw = tau * w;
+                if (mine && top) Z[j * KZ + c] = zj - tw;
+#pragma unroll
+                for (int i = 0; i < RH; ++i) u[i] -= tw * yc[i];
+            };
+            double ya[RH], yb[RH];
             {
-                const double *y = Yl + (j > 0 ? j - 1 : 0) * kQrRows + RH * h;
+                const double *y = Yl + (jtop - jlo) * kQrRows + RH * h;
 #pragma unroll
-                for (int i = 0; i < RH; ++i) yn[i] = y[i];
+                for (int i = 0; i < RH; ++i) ya[i] = y[i];
             }
-            double w0 = zj, w1 = 0.0, w2 = 0.0, w3 = 0.0;
-#pragma unroll
-            for (int i = 0; i < RH; i += 4) {
-                w0 += yc[i] * u[i];
-                w1 += yc[i + 1] * u[i + 1];
-                w2 += yc[i + 2] * u[i + 2];
-                w3 += yc[i + 3] * u[i + 3];
+            int j = jtop;
+            for (; j > jlo; j -= 2) {
+                reflect(j, ya, yb);
+                reflect(j - 1, yb, ya);
             }
-            double w = (w0 + w1) + (w2 + w3);
-            if constexpr (SPLIT) {
-                // after the swap one result holds this lane's partial and the
-                // other its partner's (lane ^ 16), in either order
-                const unsigned lo = __double2loint(w), hi = __double2hiint(w);
-                const auto sl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-                const auto sh = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-                w = __hiloint2double((int)sh[0], (int)sl[0]) + __hiloint2double((int)sh[1], (int)sl[1]);
-            }
-            const double tw = tau * w;
-            if (mine && top) Z[j * KZ + c] = zj - tw;
-#pragma unroll
-            for (int i = 0; i < RH; ++i) u[i] -= tw * yc[i];
-        };
-        double ya[RH], yb[RH];
-        {
-            const double *y = Yl + jtop * kQrRows + RH * h;
-#pragma unroll
-            for (int i = 0; i < RH; ++i) ya[i] = y[i];
+            if (j == jlo) reflect(jlo, ya, yb);
         }
-        int j = jtop;
-        for (; j > 0; j -= 2) {
-            reflect(j, ya, yb);
-            reflect(j - 1, yb, ya);
-        }
-        if (j == 0) reflect(0, ya, yb);
         if (mine && live) {
             gp o = (gp)d.out + (size_t)c * d.ldo + r0 + RH * h;
             const int hv = hb - RH * h;        // valid rows of this lane's part
