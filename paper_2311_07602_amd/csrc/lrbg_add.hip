@@ -400,7 +400,7 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
     __shared__ double Z_[G * ZSTR];            // s x kmax top part, Z[j * KZ + c]
     __shared__ double Yl_[G * YSTR];
     __shared__ double tl_[G * TSTR];
-    __shared__ int nb_[G];
+    __shared__ int nb_[G], sw_[G];
     double *Z = Z_ + g * ZSTR, *Yl = Yl_ + g * YSTR, *tl = tl_ + g * TSTR;
     const bool mine = c < km && c < KZ;       // km <= S implies km <= KZ
     const bool top = h == 0;                  // the lane that owns Z(., c)
@@ -412,11 +412,20 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
     gcp T = tau0 + s;
     gcp blk = T + (size_t)s0 * s;
     const int nblk = b > s0 ? (b - s0 + kQrRows - 1) / kQrRows : 0;
-    if (li == 0) nb_[g] = nblk;
+    if (li == 0) {
+        nb_[g] = nblk;
+        sw_[g] = s;
+    }
     __syncthreads();
-    int nbmax = 0;
+    int nbmax = 0, smax = 1;
 #pragma unroll
-    for (int q = 0; q < G; ++q) nbmax = nb_[q] > nbmax ? nb_[q] : nbmax;
+    for (int q = 0; q < G; ++q) {
+        nbmax = nb_[q] > nbmax ? nb_[q] : nbmax;
+        smax = sw_[q] > smax ? sw_[q] : smax;
+    }
+    // reflections past the widest basis of the wavefront are the identity
+    // for every group: the pieces of a block stop there
+    const int jmax = smax - 1, qtop = jmax / CH;
     // this group's piece q of block kb's tails, and the block's taus
     double pf[PF], pt = 0.0;
     auto fetch = [&](int kb, int q) {
@@ -431,7 +440,7 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
         pt = (lv && li < s) ? bp[li] : 0.0;
     };
     if constexpr (PREF) {
-        if (nbmax > 0) fetch(nbmax - 1, NQ - 1);
+        if (nbmax > 0) fetch(nbmax - 1, qtop);
     }
     for (int kb = nbmax - 1; kb >= 0; --kb) {
         const bool live = kb < nblk;
@@ -440,12 +449,12 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
         double u[RH];
 #pragma unroll
         for (int i = 0; i < RH; ++i) u[i] = 0.0;
-        for (int q = NQ - 1; q >= 0; --q) {
+        for (int q = qtop; q >= 0; --q) {
             __syncthreads();                       // the previous piece's reads of Yl are done
             if constexpr (PREF) {
 #pragma unroll
                 for (int p = 0; p < PF; ++p) Yl[li + NL * p] = pf[p];
-                if (q == NQ - 1) tl[li] = pt;
+                if (q == qtop) tl[li] = pt;
             } else {
                 for (int e = li; e < YL; e += NL) Yl[e] = (live && e < s * kQrRows) ? bp[s + e] : 0.0;
                 tl[li] = (live && li < s) ? bp[li] : 0.0;
@@ -455,7 +464,7 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
                 if (q > 0)
                     fetch(kb, q - 1);
                 else if (kb > 0)
-                    fetch(kb - 1, NQ - 1);
+                    fetch(kb - 1, qtop);
             }
             const int jlo = q * CH;
             // Reflections past the basis's width are the identity (tau = 0), and
@@ -463,7 +472,7 @@ __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restr
             // skipped, so that no branch waits on the LDS read of tau.  The tail
             // stays in registers for the update and the next reflection's tail is
             // read a step ahead (LDS, not registers, limits the wavefronts here).
-            const int jtop = jlo + CH - 1;
+            const int jtop = jlo + CH - 1 < jmax ? jlo + CH - 1 : jmax;
             // reflection j with its tail in yc, loading the next one into yn;
             // two at a time with the buffers' roles swapped, so no copies
             auto reflect = [&](int j, const double (&yc)[RH], double (&yn)[RH]) {
@@ -827,7 +836,9 @@ int launch_qr_apply(int cols, int kmax, const QrDesc *descs, int count, void *st
     if (count <= 0) return 0;
     hipStream_t st = (hipStream_t)stream;
     const int kz = kmax <= 16 ? 16 : kmax <= 32 ? 32 : 64;
-    if (cols == 16)
+    if (cols == 16 && kz == 16)   // two lanes per column: as a 32-wide class with the later reflections skipped
+        hipLaunchKernelGGL((lrbg_qr_apply_kernel<32, 16>), dim3((count + 1) / 2), dim3(64), 0, st, descs, count);
+    else if (cols == 16)
         hipLaunchKernelGGL((lrbg_qr_apply_kernel<16, 16>), dim3((count + 3) / 4), dim3(64), 0, st, descs, count);
     else if (cols == 32 && kz == 16)
         hipLaunchKernelGGL((lrbg_qr_apply_kernel<32, 16>), dim3((count + 1) / 2), dim3(64), 0, st, descs, count);

@@ -154,6 +154,25 @@ def test_lradd_wide_stack_rounded_to_at_most_half(b, ra, rb, kmax):
         _check(g, ref, ref[1][0])
 
 
+def test_lradd_kmax_beyond_the_stack_width():
+    """kmax above the stacked width of 16-, 32- and 64-wide classes (the
+    general application kernels at their full top-part width, the output
+    columns past the width zero-filled): everything is kept, so the result is
+    the whole sum."""
+    rng = np.random.default_rng(25)
+    shapes = [(300, 5, 9), (257, 12, 13), (200, 20, 25), (96, 3, 2)]
+    insts = [_instance(rng, b, ra, rb) for b, ra, rb in shapes]
+    kmax = 40
+    got = _run(insts, kmax, 0.0)
+    for (b, ra, rb), ins, g in zip(shapes, insts, got):
+        ref = oracle.lr_add_round(*ins, kmax, 0.0)
+        _check(g, ref, ref[1][0], gap=False)
+        U, s, V, k = g
+        assert k == min(ra + rb, kmax)
+        if ra + rb <= kmax:
+            assert np.max(np.abs(U @ np.diag(s) @ V.T - _full_sum(ins))) <= 1e-11 * ref[1][0]
+
+
 def test_lradd_shared_bases_rank_deficient_stack():
     """B on the same orthonormal bases as A: each stacked basis is exactly
     rank deficient (two copies of one basis); the sum is A_U (A_X + B_X)
