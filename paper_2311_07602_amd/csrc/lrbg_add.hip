@@ -33,9 +33,9 @@
 // in registers, then M = E R_V^T.
 //
 // New bases (lane c of a basis's lane group owns output column c < kmax, or
-// lanes c and c + S / 2 when an S-wide basis (S = 32, 64) keeps at most
-// S / 2 columns): U = Q [X_k; 0], applying the stored reflections in reverse
-// order:
+// lanes c and c + S / 2 of an S-lane group (S = 32, 64) when the basis keeps
+// at most S / 2 columns): U = Q [X_k; 0], applying the stored reflections in
+// reverse order:
 // blocks from the last to the first, each producing its kQrRows output rows
 // in registers while updating the s x kmax top part Z in LDS, then the
 // reflections of the first s0 rows on Z, which gives the top s0 rows.
@@ -367,9 +367,11 @@ __global__ void __launch_bounds__(64 * qr_waves(S)) lrbg_qr_blocks_kernel(const 
 // rounded up to 16): LDS, not registers, decides how many wavefronts a CU
 // holds here.  The first s0 rows' reflection tails are staged packed
 // (column j's s0 - 1 - j entries at j (2 s0 - j - 1) / 2), so they fit the
-// room of one block's tails.  A 32-wide basis keeping at most 16 columns
-// splits each block's rows between lanes c and c + 16 of its group, whose
-// partial dot products meet through one swap of 16-lane rows.
+// room of one block's tails.  A basis of the 32-wide kernel keeping at most
+// 16 columns splits each block's rows between lanes c and c + 16 of its
+// group, whose partial dot products meet through one swap of 16-lane rows;
+// 16-wide bases keeping at most 16 columns run on that kernel too, which
+// stops each block's reflections at the widest basis of the wavefront.
 template <int S, int KZ>
 __global__ void __launch_bounds__(64) lrbg_qr_apply_kernel(const QrDesc *__restrict__ descs, int count)
 {
