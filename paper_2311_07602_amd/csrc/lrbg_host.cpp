@@ -1053,9 +1053,16 @@ struct Staging {
     hipEvent_t ev = nullptr;
     bool in_use = false;
     bool recorded = false;   // ev marks the end of the current use (set under g_mu)
+    uint64_t seq = 0;        // order in which the uses' events were recorded
 };
 static std::mutex g_mu;
 static std::vector<Staging *> g_staging;
+static uint64_t g_seq = 0;
+// Scratch this large is not allocated for a third call in flight: the call
+// waits for the oldest of two busy buffers instead (allocating tens of GB
+// per call is slow, and device memory is finite).  The call it waits for was
+// enqueued two calls earlier, so the device stays busy with the one between.
+constexpr size_t kBigScratch = size_t(1) << 30;
 
 // with_host: also a pinned host buffer of the same size (for uploads);
 // without: device scratch only.
@@ -1070,6 +1077,16 @@ static Staging *acquire_staging(size_t bytes, bool with_host = true)
         if (st->in_use && st->recorded && hipEventQuery(st->ev) == hipSuccess) st->in_use = false;
         if (!st->in_use && st->cap >= bytes && (st->host != nullptr) == with_host && (!best || st->cap < best->cap))
             best = st;
+    }
+    if (!best && bytes >= kBigScratch) {
+        Staging *oldest = nullptr;
+        int busy = 0;
+        for (Staging *st : g_staging)
+            if (st->in_use && st->recorded && st->cap >= bytes && (st->host != nullptr) == with_host) {
+                ++busy;
+                if (!oldest || st->seq < oldest->seq) oldest = st;
+            }
+        if (busy >= 2 && hipEventSynchronize(oldest->ev) == hipSuccess) best = oldest;
     }
     if (best) {
         best->in_use = true;
@@ -1131,6 +1148,7 @@ static hipError_t record_release(Staging *sg, hipStream_t stream)
     if (e == hipSuccess) {
         std::lock_guard<std::mutex> lk(g_mu);
         sg->recorded = true;
+        sg->seq = ++g_seq;
     }
     return e;
 }
