@@ -233,15 +233,15 @@ __global__ void __launch_bounds__(64 * qr_waves(S)) lrbg_qr_blocks_kernel(const 
                 }
             }
             if constexpr (G == 1) {
-                // One basis per wavefront: the pivot column's tail comes from
-                // lane j's registers (j is uniform) into scalar registers,
-                // and every lane forms the reflection itself.  LDS broadcasts
-                // of the tail would move 32 doubles to every lane twice per
-                // reflection, more than the CU's LDS bandwidth keeps up with.
-                // The last quarter of the tail goes through LDS instead (the
-                // pivot lane stores it, every lane reads it back), which
-                // splits the broadcast between the VALU and the LDS (a half
-                // or three quarters through LDS measured no faster).
+                // One basis per wavefront, and every lane forms the
+                // reflection itself: three quarters of the pivot column's
+                // tail come from lane j's registers (j is uniform) into
+                // scalar registers, the last quarter through LDS (the pivot
+                // lane stores it, every lane reads it back).  All of it
+                // through LDS (32 doubles to every lane, twice per
+                // reflection) is more than the CU's LDS keeps up with; all
+                // of it by lane reads costs more VALU issue than the split
+                // (half or three quarters through LDS measured no faster).
                 constexpr int HR = 3 * kQrRows / 4;
                 if (c == j) {
 #pragma unroll
